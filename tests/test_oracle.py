@@ -1,0 +1,268 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test states which passage of the paper (or which piece of mathematics)
+fixes the expected value.  Together they are meant to catch a dropped term,
+a flipped sign, a transposed operand, a wrong window bound or a wrong
+normaliser anywhere in the oracle.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage
+import scipy.signal
+
+import oracle
+from paper_2504_19417_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_form_encodings.json")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    A = np.array([[math.pi / 2, 0.0, 0.0], [0.0, math.pi / 3, math.pi]])
+    ev = np.array(g["events_xytp"], dtype=np.int32)
+    return g, A, ev
+
+
+@pytest.mark.parametrize("search", ["scan", "bucket"])
+def test_golden_closed_form_encodings(search):
+    """Hand-derived encodings (Eqn. 10 over Eqn. 1's window, Eqn. 17 count)."""
+    g, A, ev = _golden()
+    case = g["cases"][0]
+    emb, cnt = oracle.encode(ev, A, *case["radii"], search=search)
+    np.testing.assert_array_equal(cnt, case["cnt"])
+    np.testing.assert_allclose(emb, np.array(case["emb_planar"]), atol=1e-15, rtol=0)
+    case = g["cases"][1]
+    emb, cnt = oracle.encode(ev, A, *case["radii"], queries=[case["query"]], search=search)
+    assert cnt[0] == case["cnt"]
+    np.testing.assert_allclose(emb[0], case["emb_planar"], atol=1e-15, rtol=0)
+
+
+def test_golden_mlp():
+    """Hand-evaluated perceptron (Eqns. 5-6) on the golden encodings."""
+    g, A, ev = _golden()
+    m = g["mlp"]
+    emb, _ = oracle.encode(ev, A, *g["cases"][0]["radii"])
+    x = emb[m["inputs_from_queries"]]
+    out = oracle.mlp(x, m["W1"], m["b1"], m["W2"], m["b2"])
+    np.testing.assert_allclose(out, np.array(m["flow"]), atol=1e-14, rtol=0)
+
+
+def test_count_pin_all_ones_feature():
+    """A = 0 makes every phase 1: emb == 1 + 0i exactly, and the count equals
+    the box-filtered event histogram (scipy.ndimage, an independent route)."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    ev = synth.random_events(rng, 3000, 40, 30, 12, t_base=5000)
+    A = np.zeros((8, 3))
+    rx, ry, rt = 3, 2, 1
+    emb, cnt = oracle.encode(ev, A, rx, ry, rt, search="scan")
+    assert np.all(emb[:, :8] == 1.0) and np.all(emb[:, 8:] == 0.0)
+    hist = np.zeros((40, 30, 12))
+    np.add.at(hist, (ev[:, 0], ev[:, 1], ev[:, 2] - 5000), 1)
+    box = scipy.ndimage.convolve(hist, np.ones((2 * rx + 1, 2 * ry + 1, 2 * rt + 1)),
+                                 mode="constant", cval=0.0)
+    expect = box[ev[:, 0], ev[:, 1], ev[:, 2] - 5000]
+    np.testing.assert_array_equal(cnt, expect.astype(np.int64))
+
+
+def test_isolated_event_is_one():
+    """An event alone in its window encodes to exactly 1 + 0i for any A."""
+    ev = np.array([[5, 5, 10, 1], [20, 5, 10, 1], [5, 5, 30, -1]], dtype=np.int32)
+    A = synth.draw_frequencies(16, 3, 3, 2)
+    emb, cnt = oracle.encode(ev, A, 3, 3, 2)
+    np.testing.assert_array_equal(cnt, [1, 1, 1])
+    assert np.all(emb[:, :16] == 1.0) and np.all(emb[:, 16:] == 0.0)
+
+
+def test_two_events_closed_form():
+    """Two events: emb = (1 + e^{i A.d}) / 2 for the first, its conjugate for
+    the second (Eqn. 10 with n = 2)."""
+    ev = np.array([[7, 9, 100, 1], [9, 8, 101, 1]], dtype=np.int32)
+    A = synth.draw_frequencies(32, 3, 3, 2)
+    emb, cnt = oracle.encode(ev, A, 3, 3, 2)
+    d = np.array([2.0, -1.0, 1.0])
+    ph = A @ d
+    np.testing.assert_array_equal(cnt, [2, 2])
+    np.testing.assert_allclose(emb[0, :32], (1 + np.cos(ph)) / 2, atol=1e-15)
+    np.testing.assert_allclose(emb[0, 32:], np.sin(ph) / 2, atol=1e-15)
+    np.testing.assert_allclose(emb[1, :32], (1 + np.cos(ph)) / 2, atol=1e-15)
+    np.testing.assert_allclose(emb[1, 32:], -np.sin(ph) / 2, atol=1e-15)
+
+
+def test_translation_invariance_bitwise():
+    """Shifting every event by an integer vector (including 2^30 in t) leaves
+    every encoding bit-identical: only relative offsets enter."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    ev = synth.random_events(rng, 2000, 50, 40, 10)
+    A = synth.draw_frequencies(24, 3, 3, 2)
+    e1, c1 = oracle.encode(ev, A, 3, 3, 2)
+    ev2 = ev.astype(np.int64) + np.array([123, 77, 2 ** 30, 0])
+    e2, c2 = oracle.encode(ev2.astype(np.int32), A, 3, 3, 2)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(e1, e2)
+
+
+def test_hermitian_sum():
+    """With every event queried, pairs (i, k) and (k, i) carry conjugate
+    phases, so sum_i cnt_i * Im emb_i[j] = 0 for every j."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    ev = synth.random_events(rng, 4000, 30, 30, 8)
+    A = synth.draw_frequencies(16, 2, 2, 1)
+    emb, cnt = oracle.encode(ev, A, 2, 2, 1)
+    s = (cnt[:, None] * emb[:, 16:]).sum(0)
+    assert np.max(np.abs(s)) < 1e-9
+    # and the real part is the symmetric pair sum, so it is even in A
+    emb2, _ = oracle.encode(ev, -A, 2, 2, 1)
+    np.testing.assert_allclose((cnt[:, None] * emb[:, :16]).sum(0),
+                               (cnt[:, None] * emb2[:, :16]).sum(0), rtol=1e-12)
+
+
+def test_modulus_bound():
+    """|emb[j]| <= 1: an average of unit phases."""
+    W = synth.workloads()["tiny"]
+    ev, _, _ = synth.make_slice(W.slices[0])
+    q = synth.sample_queries(len(ev), 2000, 5)
+    A = synth.draw_frequencies(W.d, W.rx, W.ry, W.rt)
+    emb, _ = oracle.encode(ev, A, W.rx, W.ry, W.rt, queries=q)
+    mod = np.hypot(emb[:, :W.d], emb[:, W.d:])
+    assert mod.max() <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mirror_symmetry(axis):
+    """Reflecting one axis of every event and negating that column of A
+    gives bit-identical encodings."""
+    rng = np.random.Generator(np.random.PCG64(14))
+    ev = synth.random_events(rng, 1500, 40, 30, 10, t_base=100)
+    A = synth.draw_frequencies(16, 3, 2, 2)
+    e1, c1 = oracle.encode(ev, A, 3, 2, 2)
+    ev2 = ev.copy()
+    ev2[:, axis] = 1000 - ev2[:, axis]
+    A2 = A.copy()
+    A2[:, axis] *= -1
+    e2, c2 = oracle.encode(ev2, A2, 3, 2, 2)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(e1, e2)
+
+
+def test_paper_form_matches_algorithm1():
+    """No temporal bound: the quadratic adjacency row equals Algorithm 1's
+    PixelEmbed/PixelCount pooling (Eqns. 14-17) to FP64 rounding."""
+    rng = np.random.Generator(np.random.PCG64(15))
+    ev = synth.random_events(rng, 600, 24, 20, 32, t_base=700)
+    A = synth.draw_frequencies(12, 3, 3, -1, nbins=32)
+    e1, c1 = oracle.encode(ev, A, 3, 3, -1, search="scan")
+    e2, c2 = oracle.alg1_paper_form(ev, A, 3, 3)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_allclose(e1, e2, atol=1e-12, rtol=0)
+
+
+def test_pooling_form_3d_matches():
+    """Temporal radius: the quadratic row equals the 3-D voxel pooling form."""
+    rng = np.random.Generator(np.random.PCG64(16))
+    ev = synth.random_events(rng, 800, 20, 18, 10, t_base=1 << 20)
+    A = synth.draw_frequencies(10, 2, 3, 2)
+    e1, c1 = oracle.encode(ev, A, 2, 3, 2, search="scan")
+    e2, c2 = oracle.pooling_form_3d(ev, A, 2, 3, 2)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_allclose(e1, e2, atol=1e-12, rtol=0)
+
+
+def test_fft_convolution_route():
+    """An independent library route: per frequency, the window sum is the 3-D
+    correlation of the event histogram with the offset-phase kernel
+    (scipy.signal.fftconvolve), read back at each event's voxel."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    W_, H_, T_ = 28, 22, 9
+    ev = synth.random_events(rng, 1200, W_, H_, T_)
+    rx, ry, rt = 3, 2, 2
+    A = synth.draw_frequencies(6, rx, ry, rt)
+    emb, cnt = oracle.encode(ev, A, rx, ry, rt)
+    hist = np.zeros((W_, H_, T_))
+    np.add.at(hist, (ev[:, 0], ev[:, 1], ev[:, 2]), 1)
+    ox, oy, ot = np.meshgrid(np.arange(-rx, rx + 1), np.arange(-ry, ry + 1),
+                             np.arange(-rt, rt + 1), indexing="ij")
+    for j in range(6):
+        # sum_o hist[v + o] e^{i A.o} = (hist * flipped kernel)[v]
+        ker = np.exp(1j * (A[j, 0] * ox + A[j, 1] * oy + A[j, 2] * ot))[::-1, ::-1, ::-1]
+        s = scipy.signal.fftconvolve(hist, ker, mode="same")
+        got = s[ev[:, 0], ev[:, 1], ev[:, 2]] / cnt
+        np.testing.assert_allclose(emb[:, j], got.real, atol=1e-10)
+        np.testing.assert_allclose(emb[:, 6 + j], got.imag, atol=1e-10)
+
+
+def test_scan_and_bucket_bitwise_tiny_workload():
+    """The two neighbour searches accumulate in the same order: bit-identical
+    on a sample of the 346x260, 20k-event workload."""
+    W = synth.workloads()["tiny"]
+    ev, _, _ = synth.make_slice(W.slices[0])
+    A = synth.draw_frequencies(W.d, W.rx, W.ry, W.rt)
+    q = synth.sample_queries(len(ev), 400, 3)
+    e1, c1 = oracle.encode(ev, A, W.rx, W.ry, W.rt, queries=q, search="scan")
+    e2, c2 = oracle.encode(ev, A, W.rx, W.ry, W.rt, queries=q, search="bucket")
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(e1, e2)
+
+
+def test_kde_limit():
+    """Eqn. 11: (1/D) <emb, e^{i A.u}> tends, as D grows, to the Gaussian
+    kernel density of the centred neighbours.  With A = sigma z / r and
+    z ~ N(0, I) the limit is (1/cnt) sum_k exp(-sigma^2 |(d_k - u)/r|^2 / 2)
+    (the characteristic function of the frequency draw).  Error O(D^-1/2)."""
+    D = 4096
+    rx, ry, rt = 3, 3, 2
+    ev = np.array([[10, 10, 50, 1], [11, 10, 50, 1], [10, 12, 51, -1],
+                   [9, 9, 49, 1], [12, 11, 52, 1]], dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(21))
+    sigma = 0.8
+    z = rng.normal(size=(D, 3))
+    A = sigma * z / np.array([rx, ry, rt])
+    emb, cnt = oracle.encode(ev, A, rx, ry, rt, queries=[0])
+    e = emb[0, :D] + 1j * emb[0, D:]
+    d = (ev[:, :3] - ev[0, :3]).astype(np.float64)
+    r = np.array([rx, ry, rt], dtype=np.float64)
+    for u in [np.zeros(3), np.array([1.0, 0.0, 0.0]), np.array([0.0, 2.0, 1.0])]:
+        est = (e * np.exp(-1j * (A @ u))).mean()
+        kde = np.mean(np.exp(-sigma ** 2 * (((d - u) / r) ** 2).sum(1) / 2))
+        assert abs(est.real - kde) < 5 / math.sqrt(D)
+        assert abs(est.imag) < 5 / math.sqrt(D)
+
+
+def test_mlp_identity_special_case():
+    """W1 = I (hidden = 2D), b1 = 0 and W2 selecting one coordinate gives
+    relu of that encoding component back: the perceptron is wired as
+    W2 relu(W1 x + b1) + b2 with W1 laid out [hidden][in]."""
+    rng = np.random.Generator(np.random.PCG64(22))
+    x = rng.normal(size=(50, 8))
+    W1 = np.eye(8)
+    b1 = np.zeros(8)
+    for c in range(8):
+        W2 = np.zeros((2, 8))
+        W2[0, c] = 1.0
+        W2[1, (c + 3) % 8] = -2.0
+        out = oracle.mlp(x, W1, b1, W2, np.array([0.5, 0.0]))
+        np.testing.assert_array_equal(out[:, 0], np.maximum(x[:, c], 0) + 0.5)
+        np.testing.assert_array_equal(out[:, 1], -2.0 * np.maximum(x[:, (c + 3) % 8], 0))
+    # a non-square W1 checks the [hidden][in] orientation
+    W1 = rng.normal(size=(5, 8))
+    b1 = rng.normal(size=5)
+    W2 = rng.normal(size=(2, 5))
+    b2 = rng.normal(size=2)
+    out = oracle.mlp(x, W1, b1, W2, b2)
+    ref = np.maximum(x @ W1.T + b1, 0) @ W2.T + b2
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_query_subset_matches_full():
+    """Querying a subset K returns the same rows as querying everything."""
+    rng = np.random.Generator(np.random.PCG64(23))
+    ev = synth.random_events(rng, 1000, 30, 30, 10)
+    A = synth.draw_frequencies(8, 2, 2, 1)
+    full, cf = oracle.encode(ev, A, 2, 2, 1)
+    q = np.array([999, 0, 500, 500, 17])
+    sub, cs = oracle.encode(ev, A, 2, 2, 1, queries=q)
+    assert np.array_equal(sub, full[q]) and np.array_equal(cs, cf[q])
