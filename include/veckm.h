@@ -1,0 +1,191 @@
+/*
+ * veckm: per-event normal-flow estimation from event-camera slices on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Yuan & Fermueller, "A Real-Time Event-Based Normal Flow
+ * Estimator"): every event k of a slice is encoded by random Fourier
+ * features of its centred spatio-temporal neighbourhood (Sec. 2.1, Eqn. 1;
+ * Sec. 2.2.1, Eqn. 10), normalised by the neighbour count (Eqn. 17,
+ * Algorithm 1 final step), and a two-layer perceptron maps the encoding to
+ * a normal-flow vector (Sec. 2.1, Eqns. 5-6).  Because pixel coordinates
+ * and time bins are integers, the window sum is a pooling over an integer
+ * (x, y, t) grid (Sec. 2.2.2, Eqns. 14-17); this library evaluates it on
+ * the GPU as a contraction of per-voxel event counts against a fixed table
+ * of offset phases.
+ *
+ * Conventions shared by every entry point
+ *   - Events are int32 tuples (x, y, t, p), 16 bytes each (veckm_event).
+ *     x in [0, width), y in [0, height), t in [t0, t0 + nbins) counted in
+ *     integer time bins, p in {-1, +1}.  Polarity is validated and not used
+ *     by the encoder (the problem statement of Sec. 2.1 has none).
+ *   - A is the frequency matrix: D rows, columns (x, y, t), FP64, applied to
+ *     integer offsets.  Algorithm 1 draws X, Y, T ~ N(0, 25) and applies them
+ *     to dx/delta-x, dy/delta-y, dt/delta-t: pass A[j] = (X_j/delta-x,
+ *     Y_j/delta-y, T_j/delta-t).  The library does not draw it.
+ *   - Encodings are float32 rows of 2D values, planar: Re emb[0..D-1], then
+ *     Im emb[0..D-1].  Flows are float32 pairs (n_x, n_y).
+ *   - Device pointers are hipMalloc'd (or torch CUDA tensor) memory on the
+ *     context's device; host pointers are ordinary memory.  The caller owns
+ *     every buffer it passes; the library owns what it allocates.
+ *   - Compute calls only enqueue work on `stream` (a hipStream_t, NULL for
+ *     the null stream) and return.  Results are valid once the stream has
+ *     completed.  Input errors found on the device (an event out of range, a
+ *     bad query index, a voxel overflow) are reported by veckm_status(); the
+ *     outputs of that call are then undefined.
+ *   - Return values: VECKM_OK (0) or a negative VECKM_E_* code.  Nothing
+ *     throws across this boundary.  A context is not thread-safe.
+ */
+#ifndef VECKM_H
+#define VECKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VECKM_OK 0
+#define VECKM_E_INVAL (-1)    /* NULL pointer, bad size, radius, D or precision */
+#define VECKM_E_RANGE (-2)    /* event outside sensor/time window, |p| != 1, query
+                                 index outside [0, n), n > max_events, nbins > max_bins */
+#define VECKM_E_NOMEM (-3)    /* device or host allocation failed */
+#define VECKM_E_BUDGET (-4)   /* request does not fit the memory budget */
+#define VECKM_E_AGAIN (-5)    /* result not ready yet / queue full */
+#define VECKM_E_HIP (-6)      /* a HIP runtime call failed */
+#define VECKM_E_NODEVICE (-7) /* no usable gfx950 device */
+#define VECKM_E_OVERFLOW (-8) /* more than VECKM_MAX_VOXEL_EVENTS events in one voxel */
+#define VECKM_E_STATE (-9)    /* call needs state that is not set (e.g. no perceptron) */
+
+/* Largest number of events one (x, y, t) voxel may hold in one call.  Counts
+   enter the matrix cores as fp16 pair sums, exact up to 2048. */
+#define VECKM_MAX_VOXEL_EVENTS 1024
+
+/* Arithmetic of the encoder and perceptron. */
+#define VECKM_FP32 0 /* offset phases carried as an fp16 hi/lo pair (22 significant
+                        bits; counts are exact integers, products exact, all sums
+                        in fp32); perceptron in fp32 on the matrix cores */
+#define VECKM_FP16 1 /* offset phases rounded once to fp16, fp32 sums; encodings
+                        handed to a bf16 x bf16 -> fp32 perceptron */
+
+typedef struct veckm_event {
+  int32_t x, y, t, p;
+} veckm_event;
+
+typedef struct veckm_params {
+  int32_t width, height; /* sensor size W, H (Algorithm 1 inputs)                 */
+  int32_t rx, ry;        /* spatial window radii delta-x, delta-y in pixels (Eqn. 1),
+                            each in [0, 12]                                       */
+  int32_t rt;            /* temporal window radius in bins, in [0, 6]: neighbours
+                            also satisfy |t_k - t_q| <= rt.  The paper's Eqn. 1
+                            bounds only x and y (the whole slice in time); a slice
+                            of nbins <= rt + 1 bins reproduces that exactly       */
+  int32_t d;             /* complex RFF dimension D: 16, 32, 48, 64, 128 or 256   */
+  int32_t max_bins;      /* largest nbins accepted by a compute call               */
+  int32_t precision;     /* VECKM_FP32 or VECKM_FP16                               */
+  int64_t max_events;    /* largest n (and m) accepted by a compute call           */
+  const double* A;       /* host, d x 3 row-major, columns (x, y, t); copied       */
+} veckm_params;
+
+typedef struct veckm_ctx veckm_ctx;
+
+/* ---- host-only helpers (no device needed) ------------------------------ */
+
+/* Validates a parameter block without touching the GPU.  Returns VECKM_OK or
+   VECKM_E_INVAL. */
+int veckm_params_check(const veckm_params* params);
+
+/* Device bytes a context created from `params` allocates (workspaces sized
+   for max_events and width x height x max_bins voxels, the phase table and a
+   perceptron of `hidden` units).  Negative VECKM_E_* on bad parameters. */
+int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden);
+
+/* The precomputed offset-phase table of Algorithm 1 (the "precomputed"
+   spatial factor, here extended to (dx, dy, dt)), as the library builds it
+   on the host in FP64 and rounds it for the matrix cores.  The window
+   {|dx|<=rx, |dy|<=ry, |dt|<=rt} is reduced by conjugate symmetry
+   (e^{-i theta} = conj e^{i theta}) to its centre plus the half with
+   (dt, dy, dx) lexicographically positive: *k_count = ((2rx+1)(2ry+1)(2rt+1)
+   + 1) / 2 offsets.  If `offsets` is non-NULL it receives k_count x 3 int32
+   (dx, dy, dt), entry 0 being the centre.  If `phase_bits` is non-NULL it
+   receives k_count x d x 4 uint16 fp16 bit patterns (cos hi, cos lo, sin hi,
+   sin lo) of theta = A[j] . (dx, dy, dt), with hi = fp16(cos) rounded to
+   nearest even and lo = fp16(cos - hi); the centre entry stores cos = 1/2
+   (it is met twice, as +o and -o).  Returns VECKM_OK or VECKM_E_INVAL. */
+int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* offsets,
+                       uint16_t* phase_bits);
+
+const char* veckm_strerror(int code);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on the current HIP device: copies A, builds the phase
+   table (FP64 on the host) and allocates every workspace up front, so that
+   compute calls allocate nothing.  Returns VECKM_E_NODEVICE when no gfx950
+   device is present, VECKM_E_NOMEM when the workspaces do not fit. */
+int veckm_create(const veckm_params* params, veckm_ctx** out);
+
+void veckm_destroy(veckm_ctx* ctx);
+
+/* Sets the two-layer perceptron (Sec. 2.1, Eqns. 5-6):
+     flow = W2 * relu(W1 * emb + b1) + b2
+   W1: hidden x 2D row-major (the [Re | Im] input order above), b1: hidden,
+   W2: 2 x hidden row-major, b2: 2.  Host float32, copied (and, for
+   VECKM_FP16, also rounded to bf16).  hidden must be a multiple of 64, at
+   most 512.  Synchronous.  Returns VECKM_E_INVAL on bad shapes. */
+int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* b1,
+                  const float* W2, const float* b2);
+
+/* Encodes the queried events of one slice (Algorithm 1 with the bounded
+   window; Eqn. 10 normalised by the Eqn. 17 count).
+     events  device, n events; every event must satisfy the conventions above
+             with the given t0 and nbins (1 <= nbins <= max_bins).
+     queries device, m event indices in [0, n), or NULL for all events (m must
+             then equal n).  Duplicates are allowed.
+     emb     device, m x 2D float32, row i is the encoding of event queries[i].
+   Returns VECKM_E_RANGE if n, m or nbins exceed the context's limits. */
+int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                 int32_t nbins, const int32_t* queries, int64_t m, float* emb,
+                 void* stream);
+
+/* As veckm_encode, followed by the perceptron: flow is device m x 2 float32.
+   Returns VECKM_E_STATE if no perceptron was set. */
+int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+               int32_t nbins, const int32_t* queries, int64_t m, float* flow,
+               void* stream);
+
+/* Waits for `stream`, then reports (and clears) the device-side input error
+   of the calls enqueued so far: VECKM_OK, VECKM_E_RANGE or
+   VECKM_E_OVERFLOW. */
+int veckm_status(veckm_ctx* ctx, void* stream);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Stages of one compute call, in launch order. */
+#define VECKM_STAGE_PREPARE 0 /* clear grid, validate + histogram events, rank query voxels */
+#define VECKM_STAGE_ENCODE 1  /* the count x offset-phase contraction (one kernel)          */
+#define VECKM_STAGE_MLP 2     /* the two-layer perceptron (one kernel)                      */
+#define VECKM_STAGE_EXPAND 3  /* per-voxel rows copied out per query (one kernel)           */
+#define VECKM_NUM_STAGES 4
+
+/* Turns per-stage timing on (1) or off (0).  While on, every compute call
+   records a HIP event before and after each stage on the call's stream (no
+   host synchronisation).  Events are created here, not in the compute calls.
+   Returns VECKM_OK, VECKM_E_INVAL or VECKM_E_HIP. */
+int veckm_profile_enable(veckm_ctx* ctx, int32_t enable);
+
+/* Waits for the recorded events and returns, per stage, the summed device
+   milliseconds (ms[s]) and the number of timed launches (count[s]) since the
+   last read; then clears them.  Arrays hold `nstages` entries (at most
+   VECKM_NUM_STAGES are written).  Returns VECKM_OK, VECKM_E_INVAL or
+   VECKM_E_HIP. */
+int veckm_profile_read(veckm_ctx* ctx, double* ms, int64_t* count, int32_t nstages);
+
+/* Waits for `stream` and returns the number of encoder rows (distinct query
+   voxels) of the last compute call enqueued on this context. */
+int veckm_last_rows(veckm_ctx* ctx, void* stream, int64_t* rows);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VECKM_H */

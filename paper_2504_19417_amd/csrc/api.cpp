@@ -1,0 +1,396 @@
+// C-ABI of the veckm library: context set-up, argument validation and the
+// launch sequence of one slice.  Every step of the computation runs in the
+// HIP kernels of this library; there is no host fallback.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "veckm_internal.h"
+
+using namespace veckm;
+
+struct veckm_ctx {
+  veckm_params p{};
+  std::vector<double> A;
+  int device = 0;
+  int num_cus = 0;
+  OffsetTable ot;
+  EncodeTables et;
+  Workspace w;
+  MlpWeights mw;
+  std::vector<void*> allocs;
+  std::vector<void*> mlp_allocs;
+  // per-stage timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  size_t ev_next = 0;
+};
+
+namespace {
+
+int device_ok(int* dev, int* cus) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return VECKM_E_NODEVICE;
+  if (hipGetDevice(dev) != hipSuccess) return VECKM_E_NODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return VECKM_E_NODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return VECKM_E_NODEVICE;
+  *cus = prop.multiProcessorCount;
+  return VECKM_OK;
+}
+
+template <typename T>
+int dalloc(std::vector<void*>& list, T** out, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return VECKM_E_NOMEM;
+  }
+  list.push_back(p);
+  *out = static_cast<T*>(p);
+  return VECKM_OK;
+}
+
+struct Sizes {
+  int64_t V, nb, bv, U, n;
+};
+
+Sizes sizes_for(const veckm_params* p, const Brick& b) {
+  Sizes s;
+  s.V = (int64_t)p->width * p->height * p->max_bins;
+  s.nb = (int64_t)((p->width + b.bx - 1) / b.bx) * ((p->height + b.by - 1) / b.by) *
+         ((p->max_bins + b.bt - 1) / b.bt);
+  s.bv = b.volume();
+  s.n = p->max_events;
+  s.U = s.n < s.V ? s.n : s.V;
+  return s;
+}
+
+int64_t bytes_for(const veckm_params* p, const Brick& b, const OffsetTable& ot, int hidden) {
+  const Sizes s = sizes_for(p, b);
+  const int na = p->precision == VECKM_FP32 ? 4 : 2;
+  int64_t bytes = 0;
+  bytes += s.V * (4 + 4 + 1);                 // count, rank, qmark
+  bytes += s.nb * s.bv * 4;                   // ulist
+  bytes += (2 * s.nb + 1) * 4;                // brick_nq, brick_off
+  bytes += s.n * (4 + 4);                     // vox, qmap
+  bytes += s.U * 2 * p->d * 4 + s.U * 8;      // rows (fp32 size), rowflow
+  bytes += (int64_t)ot.KP * p->d * na * 2 + ot.KP * 4;  // table, deltas
+  bytes += 64 * 4 + 4;                        // plan, err
+  bytes += (int64_t)hidden * (2 * p->d) * 6 + hidden * 12 + 8;  // perceptron
+  return bytes;
+}
+
+int check_call(veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t nbins,
+               const int32_t* queries, int64_t m, const void* out) {
+  if (!c) return VECKM_E_INVAL;
+  if (n < 0 || m < 0) return VECKM_E_INVAL;
+  if ((n > 0 && !ev) || (m > 0 && !out)) return VECKM_E_INVAL;
+  if (!queries && m != n) return VECKM_E_INVAL;
+  if (n > c->p.max_events || m > c->p.max_events) return VECKM_E_RANGE;
+  if (nbins < 1 || nbins > c->p.max_bins) return VECKM_E_RANGE;
+  return VECKM_OK;
+}
+
+SliceGeom geom_for(const veckm_ctx* c, int64_t n, int32_t t0, int32_t nbins, int64_t m) {
+  SliceGeom g;
+  const Brick& b = c->et.brick;
+  g.W = c->p.width;
+  g.H = c->p.height;
+  g.T = nbins;
+  g.t0 = t0;
+  g.nbx = (g.W + b.bx - 1) / b.bx;
+  g.nby = (g.H + b.by - 1) / b.by;
+  g.nbt = (g.T + b.bt - 1) / b.bt;
+  g.nbricks = g.nbx * g.nby * g.nbt;
+  g.n = (int)n;
+  g.m = (int)m;
+  return g;
+}
+
+// Stage timing: events come from a pool made by veckm_profile_enable.
+struct StageTimer {
+  veckm_ctx* c;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(veckm_ctx* c_, int stage_, void* stream) : c(c_), stage(stage_), s((hipStream_t)stream) {
+    if (!c->prof || c->ev_next + 2 > c->ev_pool.size()) return;
+    a = c->ev_pool[c->ev_next++];
+    b = c->ev_pool[c->ev_next++];
+    (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    c->marks.push_back({stage, a, b});
+  }
+};
+
+int encode_rows(veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t0, int32_t nbins,
+                const int32_t* queries, int64_t m, bool bf16_rows, void* stream, SliceGeom* out) {
+  const SliceGeom g = geom_for(c, n, t0, nbins, m);
+  *out = g;
+  {
+    StageTimer t(c, VECKM_STAGE_PREPARE, stream);
+    const int rc = launch_prepare(g, c->w, ev, queries, c->et, stream);
+    if (rc) return rc;
+  }
+  StageTimer t(c, VECKM_STAGE_ENCODE, stream);
+  return launch_encode(g, c->w, c->et, bf16_rows, c->num_cus, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int veckm_params_check(const veckm_params* params) { return check_params(params); }
+
+int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
+  const int rc = check_params(params);
+  if (rc) return rc;
+  if (hidden < 0) return VECKM_E_INVAL;
+  const Brick b = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision);
+  return bytes_for(params, b, make_offsets(params->rx, params->ry, params->rt), hidden);
+}
+
+int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* offsets,
+                       uint16_t* phase_bits) {
+  const int rc = check_params(params);
+  if (rc) return rc;
+  if (!k_count) return VECKM_E_INVAL;
+  const OffsetTable t = make_offsets(params->rx, params->ry, params->rt);
+  *k_count = t.K;
+  if (offsets) std::memcpy(offsets, t.off.data(), t.off.size() * sizeof(int32_t));
+  if (phase_bits) make_phase_bits(t, params->A, params->d, phase_bits);
+  return VECKM_OK;
+}
+
+const char* veckm_strerror(int code) {
+  switch (code) {
+    case VECKM_OK: return "ok";
+    case VECKM_E_INVAL: return "invalid argument";
+    case VECKM_E_RANGE: return "input out of range";
+    case VECKM_E_NOMEM: return "out of memory";
+    case VECKM_E_BUDGET: return "memory budget exceeded";
+    case VECKM_E_AGAIN: return "not ready";
+    case VECKM_E_HIP: return "HIP runtime error";
+    case VECKM_E_NODEVICE: return "no gfx950 device";
+    case VECKM_E_OVERFLOW: return "too many events in one voxel";
+    case VECKM_E_STATE: return "missing state (perceptron not set)";
+    default: return "unknown error";
+  }
+}
+
+int veckm_create(const veckm_params* params, veckm_ctx** out) {
+  if (!out) return VECKM_E_INVAL;
+  *out = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  veckm_ctx* c = new (std::nothrow) veckm_ctx();
+  if (!c) return VECKM_E_NOMEM;
+  rc = device_ok(&c->device, &c->num_cus);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  c->p = *params;
+  c->A.assign(params->A, params->A + 3 * params->d);
+  c->p.A = c->A.data();
+  c->ot = make_offsets(params->rx, params->ry, params->rt);
+  EncodeTables& et = c->et;
+  et.K = c->ot.K;
+  et.KP = c->ot.KP;
+  et.na = params->precision == VECKM_FP32 ? 4 : 2;
+  et.rx = params->rx;
+  et.ry = params->ry;
+  et.rt = params->rt;
+  et.d = params->d;
+  et.brick = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision);
+
+  const std::vector<uint16_t> frag = make_phase_fragments(c->ot, c->A.data(), params->d, et.na);
+  const std::vector<int32_t> delta = make_lds_deltas(c->ot, et.brick, params->rx, params->ry);
+  const Sizes s = sizes_for(params, et.brick);
+  Workspace& w = c->w;
+  uint16_t* dfrag = nullptr;
+  int32_t* ddelta = nullptr;
+  float* rows = nullptr;
+  rc = VECKM_OK;
+  rc = rc ? rc : dalloc(c->allocs, &dfrag, frag.size());
+  rc = rc ? rc : dalloc(c->allocs, &ddelta, delta.size());
+  rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
+  rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
+  rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
+  rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
+  rc = rc ? rc : dalloc(c->allocs, &w.brick_nq, (size_t)s.nb);
+  rc = rc ? rc : dalloc(c->allocs, &w.brick_off, (size_t)s.nb + 1);
+  rc = rc ? rc : dalloc(c->allocs, &w.vox, (size_t)s.n);
+  rc = rc ? rc : dalloc(c->allocs, &w.qmap, (size_t)s.n);
+  rc = rc ? rc : dalloc(c->allocs, &rows, (size_t)(s.U * 2 * params->d));
+  rc = rc ? rc : dalloc(c->allocs, &w.rowflow, (size_t)(s.U * 2));
+  rc = rc ? rc : dalloc(c->allocs, &w.plan, 64);
+  rc = rc ? rc : dalloc(c->allocs, &w.err, 1);
+  if (!rc && hipMemcpy(dfrag, frag.data(), frag.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
+    rc = VECKM_E_HIP;
+  if (!rc && hipMemcpy(ddelta, delta.data(), delta.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    rc = VECKM_E_HIP;
+  if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
+  if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = VECKM_E_HIP;
+  if (rc) {
+    veckm_destroy(c);
+    return rc;
+  }
+  w.rows = rows;
+  w.vmax = s.V;
+  w.nmax = s.n;
+  w.bmax = s.nb;
+  et.frag = dfrag;
+  et.delta = ddelta;
+  *out = c;
+  return VECKM_OK;
+}
+
+void veckm_destroy(veckm_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (void* p : ctx->mlp_allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* b1,
+                  const float* W2, const float* b2) {
+  if (!ctx || !W1 || !b1 || !W2 || !b2) return VECKM_E_INVAL;
+  if (hidden < 64 || hidden > 512 || hidden % 64) return VECKM_E_INVAL;
+  const int K2 = 2 * ctx->p.d;
+  (void)hipDeviceSynchronize();
+  for (void* p : ctx->mlp_allocs) (void)hipFree(p);
+  ctx->mlp_allocs.clear();
+  ctx->mw = MlpWeights{};
+  float *dW1 = nullptr, *db1 = nullptr, *dW2 = nullptr, *db2 = nullptr;
+  uint16_t* dW1b = nullptr;
+  int rc = VECKM_OK;
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1, (size_t)hidden * K2);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1b, (size_t)hidden * K2);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &db1, (size_t)hidden);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW2, (size_t)2 * hidden);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &db2, 2);
+  if (rc) return rc;
+  std::vector<uint16_t> w1b((size_t)hidden * K2);
+  for (size_t i = 0; i < w1b.size(); ++i) w1b[i] = bf16_bits_rne(W1[i]);
+  if (hipMemcpy(dW1, W1, (size_t)hidden * K2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dW1b, w1b.data(), w1b.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(db1, b1, (size_t)hidden * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dW2, W2, (size_t)2 * hidden * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(db2, b2, 8, hipMemcpyHostToDevice) != hipSuccess)
+    return VECKM_E_HIP;
+  ctx->mw.hidden = hidden;
+  ctx->mw.W1 = dW1;
+  ctx->mw.W1b = dW1b;
+  ctx->mw.b1 = db1;
+  ctx->mw.W2 = dW2;
+  ctx->mw.b2 = db2;
+  return VECKM_OK;
+}
+
+int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                 int32_t nbins, const int32_t* queries, int64_t m, float* emb, void* stream) {
+  int rc = check_call(ctx, events, n, nbins, queries, m, emb);
+  if (rc) return rc;
+  if (m == 0) return VECKM_OK;
+  SliceGeom g;
+  rc = encode_rows(ctx, events, n, t0, nbins, queries, m, false, stream, &g);
+  if (rc) return rc;
+  StageTimer t(ctx, VECKM_STAGE_EXPAND, stream);
+  return launch_expand_emb(g, ctx->w, ctx->p.d, emb, stream);
+}
+
+int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+               int32_t nbins, const int32_t* queries, int64_t m, float* flow, void* stream) {
+  int rc = check_call(ctx, events, n, nbins, queries, m, flow);
+  if (rc) return rc;
+  if (ctx->mw.hidden == 0) return VECKM_E_STATE;
+  if (m == 0) return VECKM_OK;
+  const bool bf16 = ctx->p.precision == VECKM_FP16;
+  SliceGeom g;
+  rc = encode_rows(ctx, events, n, t0, nbins, queries, m, bf16, stream, &g);
+  if (rc) return rc;
+  {
+    StageTimer t(ctx, VECKM_STAGE_MLP, stream);
+    rc = launch_mlp(g, ctx->w, ctx->mw, ctx->p.d, bf16, ctx->num_cus, stream);
+    if (rc) return rc;
+  }
+  StageTimer t(ctx, VECKM_STAGE_EXPAND, stream);
+  return launch_expand_flow(g, ctx->w, flow, stream);
+}
+
+int veckm_profile_enable(veckm_ctx* ctx, int32_t enable) {
+  if (!ctx) return VECKM_E_INVAL;
+  ctx->prof = enable != 0;
+  if (ctx->prof && ctx->ev_pool.empty()) {
+    ctx->ev_pool.resize(8192);
+    for (auto& e : ctx->ev_pool)
+      if (hipEventCreate(&e) != hipSuccess) {
+        ctx->prof = false;
+        return VECKM_E_HIP;
+      }
+  }
+  return VECKM_OK;
+}
+
+int veckm_profile_read(veckm_ctx* ctx, double* ms, int64_t* count, int32_t nstages) {
+  if (!ctx || !ms || !count || nstages < 0) return VECKM_E_INVAL;
+  for (int s = 0; s < nstages; ++s) {
+    ms[s] = 0.0;
+    count[s] = 0;
+  }
+  int rc = VECKM_OK;
+  for (const auto& mk : ctx->marks) {
+    float t = 0.f;
+    if (hipEventSynchronize(mk.b) != hipSuccess || hipEventElapsedTime(&t, mk.a, mk.b) != hipSuccess) {
+      rc = VECKM_E_HIP;
+      continue;
+    }
+    if (mk.stage < nstages) {
+      ms[mk.stage] += t;
+      count[mk.stage] += 1;
+    }
+  }
+  ctx->marks.clear();
+  ctx->ev_next = 0;
+  return rc;
+}
+
+int veckm_last_rows(veckm_ctx* ctx, void* stream, int64_t* rows) {
+  if (!ctx || !rows) return VECKM_E_INVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return VECKM_E_HIP;
+  int32_t u = 0;
+  if (hipMemcpy(&u, ctx->w.plan, 4, hipMemcpyDeviceToHost) != hipSuccess) return VECKM_E_HIP;
+  *rows = u;
+  return VECKM_OK;
+}
+
+int veckm_status(veckm_ctx* ctx, void* stream) {
+  if (!ctx) return VECKM_E_INVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return VECKM_E_HIP;
+  int32_t bits = 0;
+  if (hipMemcpy(&bits, ctx->w.err, 4, hipMemcpyDeviceToHost) != hipSuccess) return VECKM_E_HIP;
+  if (bits && hipMemset(ctx->w.err, 0, 4) != hipSuccess) return VECKM_E_HIP;
+  if (bits & kErrOverflow) return VECKM_E_OVERFLOW;
+  if (bits & (kErrRange | kErrQuery)) return VECKM_E_RANGE;
+  return VECKM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Host-side set-up of the encoder: parameter checks, the half-window offset
+// list, the FP64-built offset-phase table and its matrix-core layout.
+//
+// The phase of a neighbour at integer offset o = (dx, dy, dt) from the query
+// is theta_j(o) = A[j] . o (Eqn. 10 with A holding the per-axis frequencies
+// already divided by the radii, Algorithm 1 frequency draw).  Algorithm 1
+// precomputes the spatial factor because offsets are integers with a finite
+// range; the same holds for dt once time is binned, so the whole factor
+// e^{i theta_j(o)} is tabulated once per context.  Since e^{-i theta} is the
+// conjugate of e^{i theta}, the window sum over o and -o only needs
+// cos(theta) on the pair sum of counts and sin(theta) on their difference,
+// which halves the table (and the contraction) to the centre plus the
+// lexicographically positive half of the window.
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "veckm_internal.h"
+
+namespace veckm {
+
+static bool valid_d(int d) {
+  return d == 16 || d == 32 || d == 48 || d == 64 || d == 128 || d == 256;
+}
+
+int check_params(const veckm_params* p) {
+  if (!p || !p->A) return VECKM_E_INVAL;
+  if (p->width < 1 || p->height < 1 || p->max_bins < 1) return VECKM_E_INVAL;
+  if (p->rx < 0 || p->rx > kMaxRxy || p->ry < 0 || p->ry > kMaxRxy) return VECKM_E_INVAL;
+  if (p->rt < 0 || p->rt > kMaxRt) return VECKM_E_INVAL;
+  if (!valid_d(p->d)) return VECKM_E_INVAL;
+  if (p->precision != VECKM_FP32 && p->precision != VECKM_FP16) return VECKM_E_INVAL;
+  if (p->max_events < 1 || p->max_events > (int64_t)std::numeric_limits<int32_t>::max())
+    return VECKM_E_INVAL;
+  const int64_t V = (int64_t)p->width * p->height * p->max_bins;
+  if (V > (int64_t)std::numeric_limits<int32_t>::max() / 2) return VECKM_E_INVAL;
+  for (int i = 0; i < 3 * p->d; ++i)
+    if (!std::isfinite(p->A[i])) return VECKM_E_INVAL;
+  return VECKM_OK;
+}
+
+OffsetTable make_offsets(int rx, int ry, int rt) {
+  OffsetTable t;
+  t.off = {0, 0, 0};  // centre
+  for (int dt = 0; dt <= rt; ++dt)
+    for (int dy = (dt == 0 ? 0 : -ry); dy <= ry; ++dy)
+      for (int dx = (dt == 0 && dy == 0 ? 1 : -rx); dx <= rx; ++dx) {
+        t.off.push_back(dx);
+        t.off.push_back(dy);
+        t.off.push_back(dt);
+      }
+  t.K = (int)t.off.size() / 3;
+  t.KP = (t.K + kKStep - 1) / kKStep * kKStep;
+  return t;
+}
+
+uint16_t fp16_bits_rne(double v) {
+  if (std::isnan(v)) return 0x7e00;
+  const uint16_t sign = std::signbit(v) ? 0x8000 : 0;
+  const double a = std::fabs(v);
+  if (a == 0.0) return sign;
+  if (a >= 65520.0) return sign | 0x7c00;  // rounds to infinity
+  int e;
+  std::frexp(a, &e);  // a = f * 2^e, f in [0.5, 1)
+  if (e - 1 >= -14) {  // normal: 1.m * 2^(e-1)
+    double r = std::nearbyint(std::ldexp(a, 10 - (e - 1)));  // in [1024, 2048]
+    int E = e - 1 + 15;
+    if (r >= 2048.0) { r *= 0.5; E += 1; }
+    if (E >= 31) return sign | 0x7c00;
+    return (uint16_t)(sign | (E << 10) | ((int)r - 1024));
+  }
+  // subnormal: multiples of 2^-24 (rounding up to 1024 gives the smallest normal)
+  return (uint16_t)(sign | (int)std::nearbyint(std::ldexp(a, 24)));
+}
+
+static double fp16_bits_to_double(uint16_t h) {
+  const int s = h >> 15, E = (h >> 10) & 31, M = h & 1023;
+  double v;
+  if (E == 0) v = std::ldexp((double)M, -24);
+  else if (E == 31) v = M ? std::numeric_limits<double>::quiet_NaN()
+                          : std::numeric_limits<double>::infinity();
+  else v = std::ldexp((double)(M + 1024), E - 25);
+  return s ? -v : v;
+}
+
+uint16_t bf16_bits_rne(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// cos/sin of the offset phase for table entry k and frequency j, in FP64.
+static void phase(const OffsetTable& t, const double* A, int k, int j, double* c, double* s) {
+  if (k == 0) {  // centre: met as +o and -o, so half of cos(0); sin(0) = 0
+    *c = 0.5;
+    *s = 0.0;
+    return;
+  }
+  const double th = A[3 * j + 0] * (double)t.off[3 * k + 0] +
+                    A[3 * j + 1] * (double)t.off[3 * k + 1] +
+                    A[3 * j + 2] * (double)t.off[3 * k + 2];
+  *c = std::cos(th);
+  *s = std::sin(th);
+}
+
+void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out) {
+  for (int k = 0; k < t.K; ++k)
+    for (int j = 0; j < d; ++j) {
+      double c, s;
+      phase(t, A, k, j, &c, &s);
+      const uint16_t ch = fp16_bits_rne(c), sh = fp16_bits_rne(s);
+      uint16_t* o = out + ((size_t)k * d + j) * 4;
+      o[0] = ch;
+      o[1] = fp16_bits_rne(c - fp16_bits_to_double(ch));
+      o[2] = sh;
+      o[3] = fp16_bits_rne(s - fp16_bits_to_double(sh));
+    }
+}
+
+std::vector<uint16_t> make_phase_fragments(const OffsetTable& t, const double* A, int d,
+                                           int na) {
+  const int nt_total = d / 16, ksteps = t.KP / kKStep;
+  std::vector<uint16_t> bits((size_t)t.K * d * 4);
+  make_phase_bits(t, A, d, bits.data());
+  // which of (cos hi, cos lo, sin hi, sin lo) each fragment array holds
+  const int pick4[4] = {0, 1, 2, 3}, pick2[2] = {0, 2};
+  const int* pick = na == 4 ? pick4 : pick2;
+  std::vector<uint16_t> frag((size_t)ksteps * na * nt_total * 64 * 8, 0);
+  size_t idx = 0;
+  for (int ks = 0; ks < ksteps; ++ks)
+    for (int a = 0; a < na; ++a)
+      for (int nt = 0; nt < nt_total; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < 8; ++e, ++idx) {
+            const int k = ks * kKStep + 8 * (lane >> 4) + e;
+            const int j = 16 * nt + (lane & 15);
+            frag[idx] = k < t.K ? bits[((size_t)k * d + j) * 4 + pick[a]] : 0;
+          }
+  return frag;
+}
+
+std::vector<int32_t> make_lds_deltas(const OffsetTable& t, const Brick& b, int rx, int ry) {
+  const int SX = b.bx + 2 * rx, SY = b.by + 2 * ry;
+  std::vector<int32_t> delta(t.KP, 0);
+  for (int k = 0; k < t.K; ++k)
+    delta[k] = (t.off[3 * k + 2] * SY + t.off[3 * k + 1]) * SX + t.off[3 * k + 0];
+  return delta;
+}
+
+int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {
+  return (b.bx + 2 * rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
+}
+
+// Largest brick whose fp16 count volume (with halo) fits in LDS beside two
+// buffered k-slabs of the phase table.
+Brick choose_brick(int rx, int ry, int rt, int d, int precision) {
+  const int na = precision == VECKM_FP32 ? 4 : 2;
+  const int slab = na * (d / 16) * 1024;
+  const int budget = 160 * 1024 - 2 * slab - 8 * 1024;
+  const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
+                        {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}};
+  for (const Brick& b : cand)
+    if (2 * lds_volume_halves(b, rx, ry, rt) <= budget) return b;
+  return Brick{4, 4, 1};
+}
+
+}  // namespace veckm

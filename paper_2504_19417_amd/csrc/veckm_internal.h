@@ -1,0 +1,107 @@
+// Internal declarations of the veckm library (not part of the C-ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/veckm.h"
+
+namespace veckm {
+
+// Window radius limits (the LDS count volume and the offset table must fit).
+constexpr int kMaxRxy = 12;
+constexpr int kMaxRt = 6;
+constexpr int kKStep = 32;  // K elements per MFMA k-step (16x16x32 f16)
+
+// Device-side input error bits (OR-ed into a device int).
+constexpr int kErrRange = 1;     // event outside sensor / time window, or |p| != 1
+constexpr int kErrQuery = 2;     // query index outside [0, n)
+constexpr int kErrOverflow = 4;  // more than VECKM_MAX_VOXEL_EVENTS in a voxel
+
+// Brick (x, y, t) that one encoder work item covers.
+struct Brick {
+  int bx, by, bt;
+  int volume() const { return bx * by * bt; }
+};
+
+// Offsets of the half window (entry 0 is the centre), their phase table in
+// the matrix-core fragment layout, and LDS deltas for a given brick.
+struct OffsetTable {
+  int K = 0;        // real offsets (centre + half window)
+  int KP = 0;       // padded to a multiple of kKStep
+  std::vector<int32_t> off;  // K x 3 (dx, dy, dt)
+};
+
+int check_params(const veckm_params* p);
+OffsetTable make_offsets(int rx, int ry, int rt);
+// FP64 phases -> fp16 bit patterns [k][j][4] = (cos hi, cos lo, sin hi, sin lo).
+void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out);
+// Fragment-native table for the encoder: [ks][a][nt][lane][8] halves, with
+// a in {cos hi, cos lo, sin hi, sin lo} (na = 4) or {cos, sin} (na = 2).
+std::vector<uint16_t> make_phase_fragments(const OffsetTable& t, const double* A, int d,
+                                           int na);
+// LDS index delta of each padded offset for a brick (volume x fastest):
+// ((dt * SY) + dy) * SX + dx with SX = bx + 2rx, SY = by + 2ry; 0 for padding.
+std::vector<int32_t> make_lds_deltas(const OffsetTable& t, const Brick& b, int rx, int ry);
+Brick choose_brick(int rx, int ry, int rt, int d, int precision);
+int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
+uint16_t fp16_bits_rne(double v);
+uint16_t bf16_bits_rne(float v);
+
+// ---------------------------------------------------------------- launches
+// Every slice-level argument the kernels need, passed by value.
+struct SliceGeom {
+  int W, H, T;         // grid extent (T = nbins)
+  int t0;              // time of bin 0
+  int nbx, nby, nbt;   // bricks per axis
+  int nbricks;
+  int n;               // events
+  int m;               // queries
+};
+
+struct Workspace {
+  int32_t* count = nullptr;     // V int32 event counts per voxel [T][H][W]
+  int32_t* rank = nullptr;      // V int32 brick-local rank of query voxels
+  uint8_t* qmark = nullptr;     // V bytes, query-voxel marks (query subsets)
+  int32_t* ulist = nullptr;     // nbricks * brick volume: brick-local voxel of each rank
+  int32_t* brick_nq = nullptr;  // nbricks
+  int32_t* brick_off = nullptr; // nbricks + 1 (exclusive scan)
+  int32_t* vox = nullptr;       // n: voxel of each event, -1 if invalid
+  int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
+  void* rows = nullptr;         // U x 2D encodings (fp32 or bf16)
+  float* rowflow = nullptr;     // U x 2
+  int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2..] spare
+  int32_t* err = nullptr;       // error bits
+  int64_t vmax = 0, nmax = 0, bmax = 0;
+};
+
+struct EncodeTables {
+  const uint16_t* frag = nullptr;  // fragment-native phase table
+  const int32_t* delta = nullptr;  // KP LDS deltas
+  int K = 0, KP = 0, na = 4;
+  int rx = 0, ry = 0, rt = 0;
+  Brick brick{32, 16, 8};
+  int d = 0;
+};
+
+struct MlpWeights {
+  int hidden = 0;
+  const float* W1 = nullptr;       // hidden x 2D fp32
+  const uint16_t* W1b = nullptr;   // hidden x 2D bf16
+  const float* b1 = nullptr;
+  const float* W2 = nullptr;       // 2 x hidden
+  const float* b2 = nullptr;
+};
+
+int launch_prepare(const SliceGeom& g, const Workspace& w, const veckm_event* ev,
+                   const int32_t* queries, const EncodeTables& et, void* stream);
+int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et,
+                  bool bf16_rows, int num_cus, void* stream);
+int launch_expand_emb(const SliceGeom& g, const Workspace& w, int d, float* emb,
+                      void* stream);
+int launch_mlp(const SliceGeom& g, const Workspace& w, const MlpWeights& mw, int d,
+               bool bf16, int num_cus, void* stream);
+int launch_expand_flow(const SliceGeom& g, const Workspace& w, float* flow, void* stream);
+
+}  // namespace veckm

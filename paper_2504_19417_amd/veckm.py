@@ -1,0 +1,225 @@
+"""Python binding of the veckm C-ABI (``include/veckm.h``).
+
+Argument marshalling only: every function below forwards to the function of
+the same name in ``_lib/libveckm.so``, and every step of the computation runs
+in that library's HIP kernels.  Importing this module fails loudly when the
+library has not been built (``python -m paper_2504_19417_amd.build``).
+
+``Context`` is a convenience holder for a ``veckm_ctx*`` that takes torch
+CUDA tensors, passes their device pointers and the current HIP stream, and
+allocates outputs with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libveckm.so")
+
+VECKM_OK = 0
+VECKM_E_INVAL = -1
+VECKM_E_RANGE = -2
+VECKM_E_NOMEM = -3
+VECKM_E_BUDGET = -4
+VECKM_E_AGAIN = -5
+VECKM_E_HIP = -6
+VECKM_E_NODEVICE = -7
+VECKM_E_OVERFLOW = -8
+VECKM_E_STATE = -9
+VECKM_MAX_VOXEL_EVENTS = 1024
+VECKM_FP32 = 0
+VECKM_FP16 = 1
+
+PRECISIONS = {"fp32": VECKM_FP32, "fp16": VECKM_FP16}
+
+
+class veckm_params(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rt", ctypes.c_int32),
+        ("d", ctypes.c_int32), ("max_bins", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("max_events", ctypes.c_int64),
+        ("A", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class VeckmError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, veckm_strerror(code), code))
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libveckm.so is not built (%s); run "
+                      "`python -m paper_2504_19417_amd.build`" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_sig = {
+    "veckm_params_check": (ctypes.c_int, [ctypes.POINTER(veckm_params)]),
+    "veckm_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(veckm_params), ctypes.c_int32]),
+    "veckm_offset_table": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.POINTER(ctypes.c_int32),
+                                          _P, _P]),
+    "veckm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "veckm_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.POINTER(_P)]),
+    "veckm_destroy": (None, [_P]),
+    "veckm_set_mlp": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "veckm_encode": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
+                                    ctypes.c_int64, _P, _P]),
+    "veckm_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
+                                  ctypes.c_int64, _P, _P]),
+    "veckm_status": (ctypes.c_int, [_P, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32"):
+    """Build a veckm_params; the returned object keeps A alive."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    p = veckm_params()
+    p.width, p.height, p.rx, p.ry, p.rt = int(width), int(height), int(rx), int(ry), int(rt)
+    p.d = int(A.shape[0])
+    p.max_bins = int(max_bins)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.max_events = int(max_events)
+    p.A = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p._A_keepalive = A
+    return p
+
+
+def veckm_params_check(params):
+    return _lib.veckm_params_check(ctypes.byref(params))
+
+
+def veckm_workspace_bytes(params, hidden=0):
+    return _lib.veckm_workspace_bytes(ctypes.byref(params), int(hidden))
+
+
+def veckm_offset_table(params, with_phases=True):
+    """(offsets int32[K,3], phase_bits uint16[K,D,4] or None)."""
+    k = ctypes.c_int32(0)
+    rc = _lib.veckm_offset_table(ctypes.byref(params), ctypes.byref(k), None, None)
+    if rc:
+        raise VeckmError(rc, "veckm_offset_table")
+    off = np.zeros((k.value, 3), dtype=np.int32)
+    bits = np.zeros((k.value, params.d, 4), dtype=np.uint16) if with_phases else None
+    rc = _lib.veckm_offset_table(ctypes.byref(params), ctypes.byref(k), off.ctypes.data,
+                                 None if bits is None else bits.ctypes.data)
+    if rc:
+        raise VeckmError(rc, "veckm_offset_table")
+    return off, bits
+
+
+def veckm_strerror(code):
+    return _lib.veckm_strerror(int(code)).decode()
+
+
+def veckm_create(params):
+    h = _P()
+    rc = _lib.veckm_create(ctypes.byref(params), ctypes.byref(h))
+    if rc:
+        raise VeckmError(rc, "veckm_create")
+    return h
+
+
+def veckm_destroy(ctx):
+    _lib.veckm_destroy(ctx)
+
+
+def veckm_set_mlp(ctx, hidden, W1, b1, W2, b2):
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in (W1, b1, W2, b2)]
+    rc = _lib.veckm_set_mlp(ctx, int(hidden), *[a.ctypes.data for a in arrs])
+    if rc:
+        raise VeckmError(rc, "veckm_set_mlp")
+
+
+def veckm_encode(ctx, events_ptr, n, t0, nbins, queries_ptr, m, emb_ptr, stream):
+    return _lib.veckm_encode(ctx, events_ptr, int(n), int(t0), int(nbins), queries_ptr, int(m),
+                             emb_ptr, stream)
+
+
+def veckm_flow(ctx, events_ptr, n, t0, nbins, queries_ptr, m, flow_ptr, stream):
+    return _lib.veckm_flow(ctx, events_ptr, int(n), int(t0), int(nbins), queries_ptr, int(m),
+                           flow_ptr, stream)
+
+
+def veckm_status(ctx, stream):
+    return _lib.veckm_status(ctx, stream)
+
+
+class Context:
+    """A veckm context driven with torch CUDA tensors."""
+
+    def __init__(self, width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32"):
+        self.params = make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision)
+        self.d = self.params.d
+        self.handle = veckm_create(self.params)
+        self.hidden = 0
+
+    def close(self):
+        if self.handle:
+            veckm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mlp(self, W1, b1, W2, b2):
+        hidden = np.asarray(W1).shape[0]
+        veckm_set_mlp(self.handle, hidden, W1, b1, W2, b2)
+        self.hidden = hidden
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _check_inputs(self, events, queries):
+        import torch
+        if not (events.is_cuda and events.dtype == torch.int32 and events.dim() == 2
+                and events.shape[1] == 4 and events.is_contiguous()):
+            raise ValueError("events must be a contiguous int32 CUDA tensor [n, 4]")
+        if queries is not None and not (queries.is_cuda and queries.dtype == torch.int32
+                                        and queries.dim() == 1 and queries.is_contiguous()):
+            raise ValueError("queries must be a contiguous int32 CUDA tensor [m]")
+
+    def encode(self, events, t0, nbins, queries=None, out=None, stream=None):
+        import torch
+        self._check_inputs(events, queries)
+        n = events.shape[0]
+        m = n if queries is None else queries.shape[0]
+        if out is None:
+            out = torch.empty((m, 2 * self.d), dtype=torch.float32, device=events.device)
+        rc = veckm_encode(self.handle, events.data_ptr(), n, t0, nbins,
+                          None if queries is None else queries.data_ptr(), m,
+                          out.data_ptr(), self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_encode")
+        return out
+
+    def flow(self, events, t0, nbins, queries=None, out=None, stream=None):
+        import torch
+        self._check_inputs(events, queries)
+        n = events.shape[0]
+        m = n if queries is None else queries.shape[0]
+        if out is None:
+            out = torch.empty((m, 2), dtype=torch.float32, device=events.device)
+        rc = veckm_flow(self.handle, events.data_ptr(), n, t0, nbins,
+                        None if queries is None else queries.data_ptr(), m,
+                        out.data_ptr(), self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_flow")
+        return out
+
+    def status(self, stream=None):
+        return veckm_status(self.handle, self._stream(stream))
