@@ -1,0 +1,232 @@
+"""Benchmark: normal flows per second on a 1M-event slice, FP32 and FP16/BF16.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step is one veckm_flow call over the whole slice: validate and bin the
+events, rank the query voxels, the encoder contraction, the perceptron and
+the per-event output, with the events already resident in HBM.  Every event
+is queried (one flow per event).  Workload: 346x260 sensor, 1,000,000
+events of 32 moving edges plus 10 % noise over 50 one-bin time steps,
+D = 128, window +-5 px, +-3 bins, perceptron 256 -> 256 -> 2.
+
+Prints one JSON line.  `value` is the FP32 form's flows/s; the FP16/BF16
+form, per-step latency percentiles, per-stage device times, the roofline of
+the dominant kernel and the CPU oracle timed on a bounded sample are extra
+keys.  Only one GPU is used.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "fp16_TFLOPs": 2500.0,
+    "bf16_TFLOPs": 2500.0,
+    "fp32_TFLOPs": 157.3,
+}
+
+
+def encoder_flops_per_row(K, d):
+    """Algorithmic flops of one encoder row: the window sum written over the
+    centre plus half window (conjugate symmetry), real count pair sums times
+    cos for Re (K terms) and pair differences times sin for Im (K-1 terms),
+    one multiply-add = 2 flops, for each of the d frequencies."""
+    return 2 * (2 * K - 1) * d
+
+
+def mlp_flops_per_row(d, hidden):
+    """Layer 1 (2d -> hidden) and layer 2 (hidden -> 2) multiply-adds."""
+    return 2 * (2 * d) * hidden + 2 * hidden * 2
+
+
+def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup):
+    ctx = vk.Context(w.slices[0].width, w.slices[0].height, w.rx, w.ry, w.rt, A, T, len(ev),
+                     precision)
+    ctx.set_mlp(*mlp)
+    evt = torch.from_numpy(ev).cuda()
+    out = torch.empty((len(ev), 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.flow(evt, t0, T, out=out)
+    torch.cuda.synchronize()
+    if ctx.status() != vk.VECKM_OK:
+        raise RuntimeError("input error reported by the device")
+    ctx.profile(True)
+    ctx.profile_read()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        ctx.flow(evt, t0, T, out=out)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    stages = ctx.profile_read()
+    ctx.profile(False)
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    rows = ctx.last_rows()
+    flows = out.cpu().numpy()
+    st = ctx.status()
+    ctx.close()
+    if st != vk.VECKM_OK:
+        raise RuntimeError("input error reported by the device")
+    return dict(elapsed=elapsed, lat=lat, stages=stages, rows=rows, flows=flows)
+
+
+def cpu_baseline(oracle, w, ev, A, mlp, target_s):
+    """The FP64 oracle (bucketed neighbour search, OpenMP over queries) on a
+    seeded sample of the same slice's queries, sized to ~target_s seconds."""
+    from paper_2504_19417_amd import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    q0 = synth.sample_queries(len(ev), 512, 901)
+    t = time.perf_counter()
+    e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q0, threads=threads)
+    oracle.mlp(e, *mlp, threads=threads)
+    t0 = time.perf_counter() - t
+    m = int(min(len(ev), max(512, 512 * target_s / max(t0, 1e-3))))
+    q = synth.sample_queries(len(ev), m, 902)
+    t = time.perf_counter()
+    e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q, threads=threads)
+    oracle.mlp(e, *mlp, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "flows/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of the slice's %d queries (seeded), FP64 quadratic adjacency-row "
+                      "encoding with bucketed neighbour search + FP64 perceptron, %.1f s"
+                      % (m, len(ev), dt)}
+
+
+def sampled_error(oracle, w, ev, A, mlp, flows, seed=903, count=2048):
+    from paper_2504_19417_amd import synth
+    q = synth.sample_queries(len(ev), count, seed)
+    e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q)
+    ref = oracle.mlp(e, *mlp)
+    got = flows[q].astype(np.float64)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def load_traffic(kernel):
+    """HBM traffic of `kernel` measured with rocprofv3 counters, if the
+    summary in profiles/ was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+        src = os.path.join(ROOT, rec["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if sha != rec["source_sha"]:
+            return None
+        return rec["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent slices shard across GPUs with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2504_19417_amd import synth, veckm as vk
+
+    w = synth.workloads()["slice1m"]
+    ev, t0, T = synth.make_slice(w.slices[0])
+    A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
+    mlp = synth.init_mlp(w.d, w.hidden)
+    K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
+    n = len(ev)
+
+    res = {}
+    for form in ("fp32", "fp16"):
+        res[form] = run_form(vk, torch, w, ev, t0, T, A, mlp, form, args.steps, args.warmup)
+
+    def summary(r):
+        ms = r["elapsed"] / args.steps * 1e3
+        st = {k: (v[0] / v[1] if v[1] else None) for k, v in r["stages"].items()}
+        return ms, st
+
+    ms32, st32 = summary(res["fp32"])
+    ms16, st16 = summary(res["fp16"])
+    rows = res["fp32"]["rows"]
+
+    # dominant kernel of the FP32 form, from the live per-stage event times
+    cand = {
+        "encode": dict(ms=st32["encode"], flops=encoder_flops_per_row(K, w.d) * rows,
+                       peak=PEAK["fp16_TFLOPs"], kernel="k_encode"),
+        "mlp": dict(ms=st32["mlp"], flops=mlp_flops_per_row(w.d, w.hidden) * rows,
+                    peak=PEAK["fp32_TFLOPs"], kernel="k_mlp_f32"),
+    }
+    dom = max(cand, key=lambda k: cand[k]["ms"])
+    c = cand[dom]
+    achieved = c["flops"] / (c["ms"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": c["peak"],
+                "unit": "TFLOP/s", "frac": round(achieved / c["peak"], 4),
+                "traffic": load_traffic(c["kernel"]), "kernel": c["kernel"],
+                "avg_launch_ms": round(c["ms"], 4), "rows_per_launch": rows,
+                "flops_per_row": c["flops"] // rows}
+
+    err32 = sampled_error(oracle, w, ev, A, mlp, res["fp32"]["flows"])
+    err16 = sampled_error(oracle, w, ev, A, mlp, res["fp16"]["flows"])
+    cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, w, ev, A, mlp, args.cpu_seconds)
+
+    def lat(r):
+        return {"p50": round(float(np.percentile(r["lat"], 50)), 4),
+                "p99": round(float(np.percentile(r["lat"], 99)), 4)}
+
+    line = {
+        "metric": "normal flows/sec at 1M-event slices (FP32 vs BF16); p99 slice latency",
+        "value": n * args.steps / res["fp32"]["elapsed"],
+        "unit": "flows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded moving edges + 10% uniform noise)",
+        "config": {"workload": "slice1m", "sensor": "346x260", "events": n, "bins": T,
+                   "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
+                   "queries": "all events"},
+        "latency_ms": lat(res["fp32"]),
+        "err_vs_oracle": {"flow_relL2_sampled": err32},
+        "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st32.items()},
+        "fp16_bf16": {
+            "value": n * args.steps / res["fp16"]["elapsed"],
+            "ms_per_step": round(ms16, 4),
+            "latency_ms": lat(res["fp16"]),
+            "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st16.items()},
+            "err_vs_oracle": {"flow_relL2_sampled": err16},
+            "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
+        },
+        "rows": rows,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paper_context_flows_per_s": {"rtx3070": 4e6, "rtx_a5000": 6e6},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

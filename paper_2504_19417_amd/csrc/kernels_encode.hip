@@ -62,6 +62,19 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Copies one k-step slab of the phase table from global memory straight into
+// LDS (gfx950 global_load_lds_dwordx4: no registers, completion tracked by
+// vmcnt).  Each wave moves 1 KB runs; the LDS base of a run is wave-uniform.
+template <int SLAB_U4>
+__device__ inline void issue_slab(const uint4* src, int, uint4* dst, int wid, int lane) {
+#pragma unroll
+  for (int u = 0; u < (SLAB_U4 + 255) / 256; ++u) {
+    const int base = u * 256 + wid * 64;
+    if (SLAB_U4 % 256 == 0 || base < SLAB_U4)
+      __builtin_amdgcn_global_load_lds(src + base + lane, dst + base, 16, 0, 0);
+  }
+}
+
 template <int NA, int NT>
 struct EncShape {
   static constexpr int NTW = NT < 4 ? NT : 4;  // frequency tiles per wave
@@ -70,14 +83,12 @@ struct EncShape {
   static constexpr int CH = WM * 64;            // rows per chunk
   static constexpr int MT = 4;                  // 16-row tiles per wave
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-offset slab
-  static constexpr int PF = (SLAB_U4 + 255) / 256;
 };
 
 template <int NA, int NT, bool BF16OUT>
 __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   using S = EncShape<NA, NT>;
-  constexpr int NTW = S::NTW, WN = S::WN, CH = S::CH, MT = S::MT, SLAB_U4 = S::SLAB_U4,
-                PF = S::PF;
+  constexpr int NTW = S::NTW, WN = S::WN, CH = S::CH, MT = S::MT, SLAB_U4 = S::SLAB_U4;
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* slab = reinterpret_cast<uint4*>(smem);
   int32_t* delta_l = reinterpret_cast<int32_t*>(slab + 2 * SLAB_U4);
@@ -140,17 +151,8 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
         const int lx = li % a.b.bx, ly = (li / a.b.bx) % a.b.by, lt = li / (a.b.bx * a.b.by);
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx);
       }
-      uint4 pf[PF];
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const int idx = tid + u * 256;
-        if (idx < SLAB_U4) pf[u] = a.frag[idx];
-      }
-#pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const int idx = tid + u * 256;
-        if (idx < SLAB_U4) slab[idx] = pf[u];
-      }
+      issue_slab<SLAB_U4>(a.frag, 0, slab, wid, lane);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
 
       int rb[MT];
@@ -171,14 +173,6 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
       for (int ks = 0; ks < a.nsteps; ++ks) {
         const int buf = ks & 1;
         const bool more = ks + 1 < a.nsteps;
-        if (more) {
-          const uint4* src = a.frag + (size_t)(ks + 1) * SLAB_U4;
-#pragma unroll
-          for (int u = 0; u < PF; ++u) {
-            const int idx = tid + u * 256;
-            if (idx < SLAB_U4) pf[u] = src[idx];
-          }
-        }
         // A operands: pair sums and differences of counts at +o / -o
         const int kg = ks * 32 + 8 * (lane >> 4);
         const int4 d0 = *reinterpret_cast<const int4*>(delta_l + kg);
@@ -201,43 +195,42 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
           const int k = kg + e;
           bw[e] = k < a.K ? (k == 0 ? (_Float16)0.5f : (_Float16)1.0f) : (_Float16)0.0f;
         }
+        // B operands of this step, then start fetching the next slab into
+        // the other buffer while the matrix cores work
         const uint4* sb = slab + buf * SLAB_U4;
+        half8 bf[NA][NTW];
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+          for (int q = 0; q < NA; ++q) bf[q][nt] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
+        if (more) issue_slab<SLAB_U4>(a.frag + (size_t)(ks + 1) * SLAB_U4, 0,
+                                      slab + (buf ^ 1) * SLAB_U4, wid, lane);
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
-          const int ntg = wn * NTW + nt;
-          if constexpr (NA == 4) {
-            const half8 bch = as_half8(sb[(0 * NT + ntg) * 64 + lane]);
-            const half8 bcl = as_half8(sb[(1 * NT + ntg) * 64 + lane]);
-            const half8 bsh = as_half8(sb[(2 * NT + ntg) * 64 + lane]);
-            const half8 bsl = as_half8(sb[(3 * NT + ntg) * 64 + lane]);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bch, accR[mt][nt], 0, 0, 0);
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bcl, accR[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bsh, accI[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bsl, accI[mt][nt], 0, 0, 0);
-            }
-          } else {
-            const half8 bc = as_half8(sb[(0 * NT + ntg) * 64 + lane]);
-            const half8 bs = as_half8(sb[(1 * NT + ntg) * 64 + lane]);
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bc, accR[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bs, accI[mt][nt], 0, 0, 0);
+          for (int mt = 0; mt < MT; ++mt) {
+            if constexpr (NA == 4) {
+              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0][nt], accR[mt][nt], 0, 0, 0);
+              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2][nt], accI[mt][nt], 0, 0, 0);
+            } else {
+              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0][nt], accR[mt][nt], 0, 0, 0);
+              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1][nt], accI[mt][nt], 0, 0, 0);
             }
           }
+        }
+        if constexpr (NA == 4) {
+#pragma unroll
+          for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1][nt], accR[mt][nt], 0, 0, 0);
+              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3][nt], accI[mt][nt], 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
-        if (more) {
-          uint4* dst = slab + (buf ^ 1) * SLAB_U4;
-#pragma unroll
-          for (int u = 0; u < PF; ++u) {
-            const int idx = tid + u * 256;
-            if (idx < SLAB_U4) dst[idx] = pf[u];
-          }
-        }
+        if (more) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
       }
 
@@ -249,12 +242,18 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
           const int r = wm * 64 + mt * 16 + 4 * (lane >> 4) + i;
           if (c0 + r >= nq) continue;
           const float cnt = accN[mt][i];
+          const float rc = __builtin_amdgcn_rcpf(cnt);
+          // x / cnt: reciprocal estimate plus one residual correction (exact
+          // for x = cnt, so an all-ones feature still gives exactly 1)
+          auto div = [cnt, rc](float x) {
+            const float q = x * rc;
+            return fmaf(fmaf(-q, cnt, x), rc, q);
+          };
           const int64_t u = (int64_t)(row0 + c0 + r) * (2 * D);
 #pragma unroll
           for (int nt = 0; nt < NTW; ++nt) {
             const int j = (wn * NTW + nt) * 16 + (lane & 15);
-            // correctly rounded division: an all-ones feature gives exactly 1
-            const float re = accR[mt][nt][i] / cnt, im = accI[mt][nt][i] / cnt;
+            const float re = div(accR[mt][nt][i]), im = div(accI[mt][nt][i]);
             if constexpr (BF16OUT) {
               uint16_t* out = static_cast<uint16_t*>(a.rows);
               out[u + j] = f32_to_bf16_rne(re);

@@ -32,6 +32,12 @@ VECKM_E_STATE = -9
 VECKM_MAX_VOXEL_EVENTS = 1024
 VECKM_FP32 = 0
 VECKM_FP16 = 1
+VECKM_STAGE_PREPARE = 0
+VECKM_STAGE_ENCODE = 1
+VECKM_STAGE_MLP = 2
+VECKM_STAGE_EXPAND = 3
+VECKM_NUM_STAGES = 4
+STAGE_NAMES = ("prepare", "encode", "mlp", "expand")
 
 PRECISIONS = {"fp32": VECKM_FP32, "fp16": VECKM_FP16}
 
@@ -72,6 +78,9 @@ _sig = {
     "veckm_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
+    "veckm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "veckm_profile_read": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "veckm_last_rows": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -153,6 +162,30 @@ def veckm_status(ctx, stream):
     return _lib.veckm_status(ctx, stream)
 
 
+def veckm_profile_enable(ctx, enable):
+    rc = _lib.veckm_profile_enable(ctx, int(enable))
+    if rc:
+        raise VeckmError(rc, "veckm_profile_enable")
+
+
+def veckm_profile_read(ctx):
+    """{stage name: (milliseconds, launches)} since the last read."""
+    ms = np.zeros(VECKM_NUM_STAGES, dtype=np.float64)
+    cnt = np.zeros(VECKM_NUM_STAGES, dtype=np.int64)
+    rc = _lib.veckm_profile_read(ctx, ms.ctypes.data, cnt.ctypes.data, VECKM_NUM_STAGES)
+    if rc:
+        raise VeckmError(rc, "veckm_profile_read")
+    return {STAGE_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(VECKM_NUM_STAGES)}
+
+
+def veckm_last_rows(ctx, stream):
+    r = ctypes.c_int64(0)
+    rc = _lib.veckm_last_rows(ctx, stream, ctypes.byref(r))
+    if rc:
+        raise VeckmError(rc, "veckm_last_rows")
+    return r.value
+
+
 class Context:
     """A veckm context driven with torch CUDA tensors."""
 
@@ -223,3 +256,12 @@ class Context:
 
     def status(self, stream=None):
         return veckm_status(self.handle, self._stream(stream))
+
+    def profile(self, enable=True):
+        veckm_profile_enable(self.handle, enable)
+
+    def profile_read(self):
+        return veckm_profile_read(self.handle)
+
+    def last_rows(self, stream=None):
+        return veckm_last_rows(self.handle, self._stream(stream))
