@@ -82,10 +82,11 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, const OffsetTable& ot, 
   int64_t bytes = 0;
   bytes += s.V * (4 + 4 + 1);                 // count, rank, qmark
   bytes += s.nb * s.bv * 4;                   // ulist
-  bytes += (2 * s.nb + 1) * 4;                // brick_nq, brick_off
+  bytes += (3 * s.nb + 1) * 4;                // brick_nq, brick_off, order
   bytes += s.n * (4 + 4);                     // vox, qmap
   bytes += s.U * 2 * p->d * 4 + s.U * 8;      // rows (fp32 size), rowflow
-  bytes += (int64_t)ot.KP * p->d * na * 2 + ot.KP * 4;  // table, deltas
+  const SlotTable st = make_slots(p->rx, p->ry, p->rt);
+  bytes += (int64_t)st.KP * p->d * na * 2 + st.KP * 3;  // table, run offsets, weights
   bytes += 64 * 4 + 4;                        // plan, err
   bytes += (int64_t)hidden * (2 * p->d) * 6 + hidden * 12 + 8;  // perceptron
   return bytes;
@@ -160,7 +161,8 @@ int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
   const int rc = check_params(params);
   if (rc) return rc;
   if (hidden < 0) return VECKM_E_INVAL;
-  const Brick b = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision);
+  const Brick b = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision,
+                               choose_nbuf(params->d, params->precision));
   return bytes_for(params, b, make_offsets(params->rx, params->ry, params->rt), hidden);
 }
 
@@ -216,24 +218,35 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   et.ry = params->ry;
   et.rt = params->rt;
   et.d = params->d;
-  et.brick = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision);
+  et.nbuf = choose_nbuf(params->d, params->precision);
+  if (const char* e = std::getenv("VECKM_ENCODE_NBUF")) {  // tuning experiments
+    const int v = std::atoi(e);
+    if (v == 2 || v == 3) et.nbuf = v;
+  }
+  et.brick = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision, et.nbuf);
 
-  const std::vector<uint16_t> frag = make_phase_fragments(c->ot, c->A.data(), params->d, et.na);
-  const std::vector<int32_t> delta = make_lds_deltas(c->ot, et.brick, params->rx, params->ry);
+  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
+  et.KP = st.KP;
+  const std::vector<uint16_t> frag = make_slot_fragments(st, c->A.data(), params->d, et.na);
+  const std::vector<int32_t> runs = make_run_offsets(st, et.brick, params->rx, params->ry);
+  const std::vector<uint16_t> wts = make_slot_weights(st);
   const Sizes s = sizes_for(params, et.brick);
   Workspace& w = c->w;
   uint16_t* dfrag = nullptr;
-  int32_t* ddelta = nullptr;
+  int32_t* druns = nullptr;
+  uint16_t* dwts = nullptr;
   float* rows = nullptr;
   rc = VECKM_OK;
   rc = rc ? rc : dalloc(c->allocs, &dfrag, frag.size());
-  rc = rc ? rc : dalloc(c->allocs, &ddelta, delta.size());
+  rc = rc ? rc : dalloc(c->allocs, &druns, runs.size());
+  rc = rc ? rc : dalloc(c->allocs, &dwts, wts.size());
   rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
   rc = rc ? rc : dalloc(c->allocs, &w.brick_nq, (size_t)s.nb);
   rc = rc ? rc : dalloc(c->allocs, &w.brick_off, (size_t)s.nb + 1);
+  rc = rc ? rc : dalloc(c->allocs, &w.order, (size_t)s.nb);
   rc = rc ? rc : dalloc(c->allocs, &w.vox, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &w.qmap, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &rows, (size_t)(s.U * 2 * params->d));
@@ -242,7 +255,9 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.err, 1);
   if (!rc && hipMemcpy(dfrag, frag.data(), frag.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
-  if (!rc && hipMemcpy(ddelta, delta.data(), delta.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+  if (!rc && hipMemcpy(druns, runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    rc = VECKM_E_HIP;
+  if (!rc && hipMemcpy(dwts, wts.data(), wts.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
@@ -256,7 +271,8 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   w.nmax = s.n;
   w.bmax = s.nb;
   et.frag = dfrag;
-  et.delta = ddelta;
+  et.runs = druns;
+  et.wts = dwts;
   *out = c;
   return VECKM_OK;
 }

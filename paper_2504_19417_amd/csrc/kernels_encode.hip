@@ -43,8 +43,10 @@ struct EncArgs {
   const int32_t* ulist;
   const int32_t* brick_nq;
   const int32_t* brick_off;
+  const int32_t* order;
   const uint4* frag;
-  const int32_t* delta;
+  const int32_t* runs;
+  const uint16_t* wts;
   void* rows;
   int32_t* plan;
 };
@@ -53,6 +55,21 @@ __device__ inline half8 as_half8(uint4 u) {
   half8 h;
   __builtin_memcpy(&h, &u, 16);
   return h;
+}
+
+// (p.lo + q.hi, p.hi + q.lo) and (p.lo - q.hi, p.hi - q.lo) on packed fp16:
+// the -o run comes out of the pair layout half-swapped, and the swap is free
+// as an operand select.  Exact for the integer counts used here (<= 2048).
+__device__ inline uint32_t pk_sum_swapped(uint32_t p, uint32_t q) {
+  uint32_t r;
+  asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0]" : "=v"(r) : "v"(p), "v"(q));
+  return r;
+}
+__device__ inline uint32_t pk_diff_swapped(uint32_t p, uint32_t q) {
+  uint32_t r;
+  asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[0,1]"
+      : "=v"(r) : "v"(p), "v"(q));
+  return r;
 }
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -75,6 +92,12 @@ __device__ inline void issue_slab(const uint4* src, int, uint4* dst, int wid, in
   }
 }
 
+// s_waitcnt immediate (gfx9 encoding) waiting until at most n vector memory
+// operations are outstanding; expcnt and lgkmcnt are left unconstrained.
+constexpr int kGuard = 16;  // zeroed halves on each side of the LDS count volume
+
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
 template <int NA, int NT>
 struct EncShape {
   static constexpr int NTW = NT < 4 ? NT : 4;  // frequency tiles per wave
@@ -85,16 +108,23 @@ struct EncShape {
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-offset slab
 };
 
-template <int NA, int NT, bool BF16OUT>
+template <int NA, int NT, int NBUF, bool BF16OUT>
 __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   using S = EncShape<NA, NT>;
+  static_assert(NBUF == 2 || (NBUF == 3 && S::SLAB_U4 % 256 == 0), "slab buffering");
+  constexpr int PFW = S::SLAB_U4 / 256;  // loads per wave per slab (NBUF == 3)
   constexpr int NTW = S::NTW, WN = S::WN, CH = S::CH, MT = S::MT, SLAB_U4 = S::SLAB_U4;
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* slab = reinterpret_cast<uint4*>(smem);
-  int32_t* delta_l = reinterpret_cast<int32_t*>(slab + 2 * SLAB_U4);
-  int32_t* rowbase = delta_l + a.nsteps * 32;
+  int32_t* runs_l = reinterpret_cast<int32_t*>(slab + NBUF * SLAB_U4);
+  uint16_t* wts_l = reinterpret_cast<uint16_t*>(runs_l + a.nsteps * 8);
+  int32_t* rowbase = reinterpret_cast<int32_t*>(wts_l + a.nsteps * 32);
   int32_t* item = rowbase + CH;
-  _Float16* vol = reinterpret_cast<_Float16*>(item + 4);
+  // Count volume as overlapping fp16 pairs: dword i holds the counts of
+  // voxels i and i + 1 (low, high), so any run of 4 consecutive voxels is
+  // two aligned dword reads.  Zeroed guards on both sides: padding slots may
+  // read up to three voxels past the halo, which must hold finite values.
+  uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4) + kGuard;
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -102,18 +132,22 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   const int KP = a.nsteps * 32;
   const int BV = a.b.bx * a.b.by * a.b.bt;
   const int D = a.D;
-  for (int k = tid; k < KP; k += 256) delta_l[k] = a.delta[k];
+  for (int k = tid; k < KP / 4; k += 256) runs_l[k] = a.runs[k];
+  for (int k = tid; k < KP; k += 256) wts_l[k] = a.wts[k];
+  _Float16* vol16 = reinterpret_cast<_Float16*>(vol2);
+  // every half that staging never writes (guards, the high half of the last
+  // dword) must stay finite: clear the whole region once
+  for (int i = tid; i < a.vol + 2 * kGuard; i += 256) vol2[i - kGuard] = 0u;
 
   for (;;) {
-    if (tid == 0) item[0] = atomicAdd(&a.plan[1], 1);
+    if (tid == 0) {
+      const int it = atomicAdd(&a.plan[1], 1);
+      item[0] = it < a.plan[2] ? a.order[it] : -1;
+    }
     __syncthreads();
     const int bid = item[0];
-    if (bid >= a.g.nbricks) break;
+    if (bid < 0) break;
     const int nq = a.brick_nq[bid];
-    if (nq == 0) {
-      __syncthreads();
-      continue;
-    }
     const int row0 = a.brick_off[bid];
 
     // ---- stage the brick's counts (with halo) into LDS as fp16
@@ -124,10 +158,10 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
       const int nrows = a.SY * a.ST;
       const int x = x0 + lane;
       const bool xin = lane < a.SX && (unsigned)x < (unsigned)a.g.W;
-      for (int r0 = wid * 8; r0 < nrows; r0 += 32) {
-        int cv[8];
+      for (int r0 = wid * 16; r0 < nrows; r0 += 64) {
+        int cv[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int rr = r0 + u;
           const int sy = rr % a.SY, st = rr / a.SY;
           const int y = y0 + sy, t = tb + st;
@@ -136,9 +170,17 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
             cv[u] = a.count[(t * a.g.H + y) * a.g.W + x];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
           const int rr = r0 + u;
-          if (rr < nrows && lane < a.SX) vol[rr * a.SX + lane] = (_Float16)(float)cv[u];
+          // voxel i is the low half of dword i and the high half of dword
+          // i - 1 (which may belong to the previous x row: a -o run can end
+          // there with real slots)
+          if (rr < nrows && lane < a.SX) {
+            const int i = rr * a.SX + lane;
+            const _Float16 c = (_Float16)(float)cv[u];
+            vol16[2 * i] = c;
+            vol16[2 * i - 1] = c;
+          }
         }
       }
     }
@@ -152,10 +194,19 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx);
       }
       issue_slab<SLAB_U4>(a.frag, 0, slab, wid, lane);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if constexpr (NBUF == 3) {
+        if (a.nsteps > 1) {
+          issue_slab<SLAB_U4>(a.frag + SLAB_U4, 0, slab + SLAB_U4, wid, lane);
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
+        } else {
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        }
+      } else {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      }
       __syncthreads();
 
-      int rb[MT];
+      int rb[MT];  // voxel index of each row in the volume
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) rb[mt] = rowbase[wm * 64 + mt * 16 + (lane & 15)];
 
@@ -171,30 +222,37 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
       }
 
       for (int ks = 0; ks < a.nsteps; ++ks) {
-        const int buf = ks & 1;
-        const bool more = ks + 1 < a.nsteps;
-        // A operands: pair sums and differences of counts at +o / -o
-        const int kg = ks * 32 + 8 * (lane >> 4);
-        const int4 d0 = *reinterpret_cast<const int4*>(delta_l + kg);
-        const int4 d1 = *reinterpret_cast<const int4*>(delta_l + kg + 4);
-        const int dk[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
+        const int ahead = NBUF - 1;  // slab issued this step: ks + ahead
+        const bool more = ks + ahead < a.nsteps;
+        // A operands: pair sums and differences of counts at +o / -o.  The
+        // lane's 8 slots are two runs of 4 consecutive dx; a +o run starts at
+        // voxel base + off (ascending), its -o partner ends at base - off
+        // (descending), read as dwords and half-swapped.
+        const int g = lane >> 4;
+        const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
         half8 aS[MT], aD[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const _Float16 p = vol[rb[mt] + dk[e]];
-            const _Float16 q = vol[rb[mt] - dk[e]];
-            aS[mt][e] = p + q;
-            aD[mt][e] = p - q;
-          }
+          const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
+          const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
+          const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
+          const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
+          const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
+          const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
+          uint4 s4, d4;
+          s4.x = pk_sum_swapped(P[0], Qr[0]);
+          s4.y = pk_sum_swapped(P[1], Qr[1]);
+          s4.z = pk_sum_swapped(P[2], Qr[2]);
+          s4.w = pk_sum_swapped(P[3], Qr[3]);
+          d4.x = pk_diff_swapped(P[0], Qr[0]);
+          d4.y = pk_diff_swapped(P[1], Qr[1]);
+          d4.z = pk_diff_swapped(P[2], Qr[2]);
+          d4.w = pk_diff_swapped(P[3], Qr[3]);
+          aS[mt] = as_half8(s4);
+          aD[mt] = as_half8(d4);
         }
-        half8 bw;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = kg + e;
-          bw[e] = k < a.K ? (k == 0 ? (_Float16)0.5f : (_Float16)1.0f) : (_Float16)0.0f;
-        }
+        const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
         // B operands of this step, then start fetching the next slab into
         // the other buffer while the matrix cores work
         const uint4* sb = slab + buf * SLAB_U4;
@@ -203,8 +261,11 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
         for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
           for (int q = 0; q < NA; ++q) bf[q][nt] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
-        if (more) issue_slab<SLAB_U4>(a.frag + (size_t)(ks + 1) * SLAB_U4, 0,
-                                      slab + (buf ^ 1) * SLAB_U4, wid, lane);
+        if (more) {
+          const int nbuf = NBUF == 3 ? (ks + 2) % 3 : (buf ^ 1);
+          issue_slab<SLAB_U4>(a.frag + (size_t)(ks + ahead) * SLAB_U4, 0, slab + nbuf * SLAB_U4,
+                              wid, lane);
+        }
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
 #pragma unroll
@@ -230,7 +291,12 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
-        if (more) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // the slab of step ks + 1 must have landed; with three buffers the
+        // one just issued (step ks + 2) may stay in flight
+        if (NBUF == 3 && more)
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
+        else
+          __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
         __syncthreads();
       }
 
@@ -254,14 +320,15 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
           for (int nt = 0; nt < NTW; ++nt) {
             const int j = (wn * NTW + nt) * 16 + (lane & 15);
             const float re = div(accR[mt][nt][i]), im = div(accI[mt][nt][i]);
+            // streaming stores: the rows are read once, later; keep L2 for the table
             if constexpr (BF16OUT) {
               uint16_t* out = static_cast<uint16_t*>(a.rows);
-              out[u + j] = f32_to_bf16_rne(re);
-              out[u + D + j] = f32_to_bf16_rne(im);
+              __builtin_nontemporal_store(f32_to_bf16_rne(re), out + u + j);
+              __builtin_nontemporal_store(f32_to_bf16_rne(im), out + u + D + j);
             } else {
               float* out = static_cast<float*>(a.rows);
-              out[u + j] = re;
-              out[u + D + j] = im;
+              __builtin_nontemporal_store(re, out + u + j);
+              __builtin_nontemporal_store(im, out + u + D + j);
             }
           }
         }
@@ -271,20 +338,20 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   }
 }
 
-template <int NA, int NT>
+template <int NA, int NT, int NBUF>
 static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
   using S = EncShape<NA, NT>;
-  return (size_t)2 * S::SLAB_U4 * 16 + (size_t)et.KP * 4 + (size_t)S::CH * 4 + 16 +
-         ((size_t)vol * 2 + 15) / 16 * 16;
+  return (size_t)NBUF * S::SLAB_U4 * 16 + (size_t)et.KP + (size_t)et.KP * 2 +
+         (size_t)S::CH * 4 + 16 + (size_t)(vol + 2 * kGuard) * 4;
 }
 
-template <int NA, int NT>
+template <int NA, int NT, int NBUF>
 static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
                     hipStream_t s) {
-  const size_t lds = encode_lds_bytes<NA, NT>(et, a.vol);
+  const size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
-  const void* fn = bf16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, true>)
-                        : reinterpret_cast<const void*>(&k_encode<NA, NT, false>);
+  const void* fn = bf16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, true>)
+                        : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, false>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
   int per_cu = (int)((160 * 1024) / lds);
@@ -292,24 +359,39 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num
   int grid = num_cus * per_cu;
   if (grid > a.g.nbricks) grid = a.g.nbricks;
   if (bf16)
-    hipLaunchKernelGGL((k_encode<NA, NT, true>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, true>), dim3(grid), dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL((k_encode<NA, NT, false>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, false>), dim3(grid), dim3(256), lds, s, a);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+template <int NA, int NT>
+static int launch_nb(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
+                     hipStream_t s) {
+  if constexpr (EncShape<NA, NT>::SLAB_U4 % 256 == 0) {
+    if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, bf16, num_cus, s);
+  }
+  return launch_t<NA, NT, 2>(a, et, bf16, num_cus, s);
 }
 
 template <int NA>
 static int dispatch_nt(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
                        hipStream_t s) {
   switch (a.D / 16) {
-    case 1: return launch_t<NA, 1>(a, et, bf16, num_cus, s);
-    case 2: return launch_t<NA, 2>(a, et, bf16, num_cus, s);
-    case 3: return launch_t<NA, 3>(a, et, bf16, num_cus, s);
-    case 4: return launch_t<NA, 4>(a, et, bf16, num_cus, s);
-    case 8: return launch_t<NA, 8>(a, et, bf16, num_cus, s);
-    case 16: return launch_t<NA, 16>(a, et, bf16, num_cus, s);
+    case 1: return launch_nb<NA, 1>(a, et, bf16, num_cus, s);
+    case 2: return launch_nb<NA, 2>(a, et, bf16, num_cus, s);
+    case 3: return launch_nb<NA, 3>(a, et, bf16, num_cus, s);
+    case 4: return launch_nb<NA, 4>(a, et, bf16, num_cus, s);
+    case 8: return launch_nb<NA, 8>(a, et, bf16, num_cus, s);
+    case 16: return launch_nb<NA, 16>(a, et, bf16, num_cus, s);
     default: return VECKM_E_INVAL;
   }
+}
+
+int encode_rows_per_chunk(int d) {
+  const int nt = d / 16;
+  const int ntw = nt < 4 ? nt : 4;
+  return (4 / (nt / ntw)) * 64;
 }
 
 int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et,
@@ -331,8 +413,10 @@ int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et
   a.ulist = w.ulist;
   a.brick_nq = w.brick_nq;
   a.brick_off = w.brick_off;
+  a.order = w.order;
   a.frag = reinterpret_cast<const uint4*>(et.frag);
-  a.delta = et.delta;
+  a.runs = et.runs;
+  a.wts = et.wts;
   a.rows = w.rows;
   a.plan = w.plan;
   if (a.SX > 64) return VECKM_E_INVAL;  // one wavefront stages one x row

@@ -108,12 +108,19 @@ __global__ __launch_bounds__(256) void k_rank(SliceGeom g, Brick b,
 }
 
 // One block: exclusive scan of the per-brick row counts; plan[0] = total
-// rows U, plan[1] = 0 (the encoder's work counter).
+// rows U, plan[1] = 0 (the encoder's work counter), plan[2] = number of
+// non-empty bricks, listed in order[] with the most encoder chunks first
+// (longest job first keeps the persistent encoder's tail short).
+constexpr int kMaxChunkBins = 64;
+
 __global__ __launch_bounds__(1024) void k_brick_scan(const int32_t* __restrict__ nq, int nb,
-                                                     int32_t* __restrict__ off,
+                                                     int ch, int32_t* __restrict__ off,
+                                                     int32_t* __restrict__ order,
                                                      int32_t* __restrict__ plan) {
   __shared__ int sums[1024];
+  __shared__ int hist[kMaxChunkBins + 1];
   const int tid = threadIdx.x;
+  if (tid <= kMaxChunkBins) hist[tid] = 0;
   const int per = (nb + 1023) / 1024;
   const int s0 = min(tid * per, nb), s1 = min(s0 + per, nb);
   int local = 0;
@@ -130,11 +137,26 @@ __global__ __launch_bounds__(1024) void k_brick_scan(const int32_t* __restrict__
   for (int i = s0; i < s1; ++i) {
     off[i] = run;
     run += nq[i];
+    const int c = min((nq[i] + ch - 1) / ch, kMaxChunkBins);
+    if (c > 0) atomicAdd(&hist[kMaxChunkBins - c], 1);
   }
-  if (tid == 1023) {
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b <= kMaxChunkBins; ++b) {
+      const int h = hist[b];
+      hist[b] = acc;
+      acc += h;
+    }
     off[nb] = sums[1023];
     plan[0] = sums[1023];
     plan[1] = 0;
+    plan[2] = acc;
+  }
+  __syncthreads();
+  for (int i = s0; i < s1; ++i) {
+    const int c = min((nq[i] + ch - 1) / ch, kMaxChunkBins);
+    if (c > 0) order[atomicAdd(&hist[kMaxChunkBins - c], 1)] = i;
   }
 }
 
@@ -207,7 +229,7 @@ int launch_prepare(const SliceGeom& g, const Workspace& w, const veckm_event* ev
     hipLaunchKernelGGL(k_rank<true>, dim3(g.nbricks), dim3(256), 0, s, g, et.brick, w.count,
                        w.qmark, w.rank, w.ulist, w.brick_nq);
   hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, g.nbricks,
-                     w.brick_off, w.plan);
+                     encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
   if (g.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(g.m, 256)), dim3(256), 0, s, queries, g,
                        et.brick, w.vox, w.rank, w.brick_off, w.qmap);

@@ -119,14 +119,32 @@ void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out
     }
 }
 
-std::vector<uint16_t> make_phase_fragments(const OffsetTable& t, const double* A, int d,
-                                           int na) {
+int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {
+  return (b.bx + 2 * rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
+}
+
+SlotTable make_slots(int rx, int ry, int rt) {
+  SlotTable t;
+  auto row = [&](int dx0, int dx1, int dy, int dt, bool centre) {
+    const int n = dx1 - dx0 + 1, padded = (n + 3) / 4 * 4;
+    for (int i = 0; i < padded; ++i) {
+      const int dx = dx0 + i;
+      const int kind = i >= n ? 0 : (centre && dx == 0 ? 2 : 1);
+      t.slot.insert(t.slot.end(), {dx, dy, dt, kind});
+      if (kind) ++t.K;
+    }
+  };
+  row(0, rx, 0, 0, true);  // centre row: the centre and dx > 0
+  for (int dt = 0; dt <= rt; ++dt)
+    for (int dy = (dt == 0 ? 1 : -ry); dy <= ry; ++dy) row(-rx, rx, dy, dt, false);
+  int n = (int)t.slot.size() / 4;
+  t.KP = (n + kKStep - 1) / kKStep * kKStep;
+  for (; n < t.KP; ++n) t.slot.insert(t.slot.end(), {0, 0, 0, 0});
+  return t;
+}
+
+std::vector<uint16_t> make_slot_fragments(const SlotTable& t, const double* A, int d, int na) {
   const int nt_total = d / 16, ksteps = t.KP / kKStep;
-  std::vector<uint16_t> bits((size_t)t.K * d * 4);
-  make_phase_bits(t, A, d, bits.data());
-  // which of (cos hi, cos lo, sin hi, sin lo) each fragment array holds
-  const int pick4[4] = {0, 1, 2, 3}, pick2[2] = {0, 2};
-  const int* pick = na == 4 ? pick4 : pick2;
   std::vector<uint16_t> frag((size_t)ksteps * na * nt_total * 64 * 8, 0);
   size_t idx = 0;
   for (int ks = 0; ks < ksteps; ++ks)
@@ -136,33 +154,61 @@ std::vector<uint16_t> make_phase_fragments(const OffsetTable& t, const double* A
           for (int e = 0; e < 8; ++e, ++idx) {
             const int k = ks * kKStep + 8 * (lane >> 4) + e;
             const int j = 16 * nt + (lane & 15);
-            frag[idx] = k < t.K ? bits[((size_t)k * d + j) * 4 + pick[a]] : 0;
+            const int* s = &t.slot[4 * k];
+            if (s[3] == 0) continue;
+            double c = 0.5, sn = 0.0;  // centre: met as +o and -o
+            if (s[3] == 1) {
+              const double th = A[3 * j + 0] * (double)s[0] + A[3 * j + 1] * (double)s[1] +
+                                A[3 * j + 2] * (double)s[2];
+              c = std::cos(th);
+              sn = std::sin(th);
+            }
+            const double v = (na == 4 ? (a < 2) : (a == 0)) ? c : sn;
+            const uint16_t hi = fp16_bits_rne(v);
+            const bool lo = na == 4 && (a & 1);
+            frag[idx] = lo ? fp16_bits_rne(v - fp16_bits_to_double(hi)) : hi;
           }
   return frag;
 }
 
-std::vector<int32_t> make_lds_deltas(const OffsetTable& t, const Brick& b, int rx, int ry) {
+std::vector<int32_t> make_run_offsets(const SlotTable& t, const Brick& b, int rx, int ry) {
   const int SX = b.bx + 2 * rx, SY = b.by + 2 * ry;
-  std::vector<int32_t> delta(t.KP, 0);
-  for (int k = 0; k < t.K; ++k)
-    delta[k] = (t.off[3 * k + 2] * SY + t.off[3 * k + 1]) * SX + t.off[3 * k + 0];
-  return delta;
+  std::vector<int32_t> runs(t.KP / 4, 0);
+  for (int r = 0; r < t.KP / 4; ++r) {
+    const int* s = &t.slot[4 * 4 * r];
+    runs[r] = (s[2] * SY + s[1]) * SX + s[0];
+  }
+  return runs;
 }
 
-int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {
-  return (b.bx + 2 * rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
+std::vector<uint16_t> make_slot_weights(const SlotTable& t) {
+  std::vector<uint16_t> w(t.KP, 0);
+  for (int k = 0; k < t.KP; ++k) {
+    const int kind = t.slot[4 * k + 3];
+    w[k] = kind == 0 ? 0 : (kind == 2 ? fp16_bits_rne(0.5) : fp16_bits_rne(1.0));
+  }
+  return w;
 }
 
-// Largest brick whose fp16 count volume (with halo) fits in LDS beside two
-// buffered k-slabs of the phase table.
-Brick choose_brick(int rx, int ry, int rt, int d, int precision) {
+// Number of phase-table slabs kept in flight in LDS: three when they fit
+// beside a useful brick, two otherwise.
+int choose_nbuf(int d, int precision) {
   const int na = precision == VECKM_FP32 ? 4 : 2;
   const int slab = na * (d / 16) * 1024;
-  const int budget = 160 * 1024 - 2 * slab - 8 * 1024;
+  if ((na * (d / 16)) % 4 != 0) return 2;
+  return 3 * slab + 72 * 1024 <= 160 * 1024 ? 3 : 2;
+}
+
+// Largest brick whose count volume (with halo and guards, one fp16 pair per
+// voxel) fits in LDS beside the buffered k-slabs of the phase table.
+Brick choose_brick(int rx, int ry, int rt, int d, int precision, int nbuf) {
+  const int na = precision == VECKM_FP32 ? 4 : 2;
+  const int slab = na * (d / 16) * 1024;
+  const int budget = 160 * 1024 - nbuf * slab - 8 * 1024;
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
                         {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}};
   for (const Brick& b : cand)
-    if (2 * lds_volume_halves(b, rx, ry, rt) <= budget) return b;
+    if (4 * (lds_volume_halves(b, rx, ry, rt) + 32) <= budget) return b;
   return Brick{4, 4, 1};
 }
 

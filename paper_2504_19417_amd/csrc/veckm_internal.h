@@ -33,18 +33,32 @@ struct OffsetTable {
   std::vector<int32_t> off;  // K x 3 (dx, dy, dt)
 };
 
+// The encoder's k-slot layout: the half window cut into runs of 4
+// consecutive dx offsets (each window row padded to a multiple of 4 with
+// zero-weight slots), so that every 8-slot group of an MFMA lane is two
+// runs that the kernel reads with one address each.
+struct SlotTable {
+  int K = 0;   // real offsets
+  int KP = 0;  // slots, a multiple of kKStep
+  std::vector<int32_t> slot;  // KP x 4: dx, dy, dt, kind (0 pad, 1 offset, 2 centre)
+};
+
 int check_params(const veckm_params* p);
+SlotTable make_slots(int rx, int ry, int rt);
+// Fragment-native table over the slot layout: [ks][a][nt][lane][8] halves.
+std::vector<uint16_t> make_slot_fragments(const SlotTable& t, const double* A, int d, int na);
+// LDS voxel-index delta of the first slot of every run, laid out
+// [ks][lane group][2].
+std::vector<int32_t> make_run_offsets(const SlotTable& t, const Brick& b, int rx, int ry);
+// fp16 bit patterns of the neighbour-count weight of every slot (1 for an
+// offset, 1/2 for the centre, 0 for padding).
+std::vector<uint16_t> make_slot_weights(const SlotTable& t);
 OffsetTable make_offsets(int rx, int ry, int rt);
 // FP64 phases -> fp16 bit patterns [k][j][4] = (cos hi, cos lo, sin hi, sin lo).
 void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out);
-// Fragment-native table for the encoder: [ks][a][nt][lane][8] halves, with
-// a in {cos hi, cos lo, sin hi, sin lo} (na = 4) or {cos, sin} (na = 2).
-std::vector<uint16_t> make_phase_fragments(const OffsetTable& t, const double* A, int d,
-                                           int na);
-// LDS index delta of each padded offset for a brick (volume x fastest):
-// ((dt * SY) + dy) * SX + dx with SX = bx + 2rx, SY = by + 2ry; 0 for padding.
-std::vector<int32_t> make_lds_deltas(const OffsetTable& t, const Brick& b, int rx, int ry);
-Brick choose_brick(int rx, int ry, int rt, int d, int precision);
+Brick choose_brick(int rx, int ry, int rt, int d, int precision, int nbuf);
+int choose_nbuf(int d, int precision);
+int encode_rows_per_chunk(int d);
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
 uint16_t fp16_bits_rne(double v);
 uint16_t bf16_bits_rne(float v);
@@ -67,19 +81,22 @@ struct Workspace {
   int32_t* ulist = nullptr;     // nbricks * brick volume: brick-local voxel of each rank
   int32_t* brick_nq = nullptr;  // nbricks
   int32_t* brick_off = nullptr; // nbricks + 1 (exclusive scan)
+  int32_t* order = nullptr;     // nbricks: non-empty bricks, most encoder chunks first
   int32_t* vox = nullptr;       // n: voxel of each event, -1 if invalid
   int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
   void* rows = nullptr;         // U x 2D encodings (fp32 or bf16)
   float* rowflow = nullptr;     // U x 2
-  int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2..] spare
+  int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2] = non-empty bricks
   int32_t* err = nullptr;       // error bits
   int64_t vmax = 0, nmax = 0, bmax = 0;
 };
 
 struct EncodeTables {
-  const uint16_t* frag = nullptr;  // fragment-native phase table
-  const int32_t* delta = nullptr;  // KP LDS deltas
+  const uint16_t* frag = nullptr;  // fragment-native phase table over the slots
+  const int32_t* runs = nullptr;   // KP / 4 run byte offsets
+  const uint16_t* wts = nullptr;   // KP slot weights (fp16)
   int K = 0, KP = 0, na = 4;
+  int nbuf = 3;  // k-step slabs of the table buffered in LDS (2 or 3)
   int rx = 0, ry = 0, rt = 0;
   Brick brick{32, 16, 8};
   int d = 0;
