@@ -161,8 +161,10 @@ int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
   const int rc = check_params(params);
   if (rc) return rc;
   if (hidden < 0) return VECKM_E_INVAL;
-  const Brick b = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision,
-                               choose_nbuf(params->d, params->precision));
+  Brick b;
+  int nbuf;
+  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
+  choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &b, &nbuf);
   return bytes_for(params, b, make_offsets(params->rx, params->ry, params->rt), hidden);
 }
 
@@ -218,15 +220,10 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   et.ry = params->ry;
   et.rt = params->rt;
   et.d = params->d;
-  et.nbuf = choose_nbuf(params->d, params->precision);
-  if (const char* e = std::getenv("VECKM_ENCODE_NBUF")) {  // tuning experiments
-    const int v = std::atoi(e);
-    if (v == 2 || v == 3) et.nbuf = v;
-  }
-  et.brick = choose_brick(params->rx, params->ry, params->rt, params->d, params->precision, et.nbuf);
-
   const SlotTable st = make_slots(params->rx, params->ry, params->rt);
   et.KP = st.KP;
+  choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &et.brick,
+                &et.nbuf);
   const std::vector<uint16_t> frag = make_slot_fragments(st, c->A.data(), params->d, et.na);
   const std::vector<int32_t> runs = make_run_offsets(st, et.brick, params->rx, params->ry);
   const std::vector<uint16_t> wts = make_slot_weights(st);

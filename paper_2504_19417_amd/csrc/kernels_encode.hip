@@ -100,20 +100,37 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 
 template <int NA, int NT>
 struct EncShape {
-  static constexpr int NTW = NT < 4 ? NT : 4;  // frequency tiles per wave
+  static constexpr int NW = 8;                  // waves per block (2 per SIMD)
+  static constexpr int NTW = NT < 4 ? NT : 4;   // 16-frequency tiles per wave
   static constexpr int WN = NT / NTW;           // waves across frequencies
-  static constexpr int WM = 4 / WN;             // waves across rows
-  static constexpr int CH = WM * 64;            // rows per chunk
-  static constexpr int MT = 4;                  // 16-row tiles per wave
-  static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-offset slab
+  static constexpr int WM = NW / WN;            // waves across rows
+  static constexpr int MT = NT >= 8 ? 4 : 2;    // 16-row tiles per wave
+  static constexpr int CH = WM * MT * 16;       // rows per chunk
+  static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-slot slab
+  static constexpr int PFW = SLAB_U4 / (NW * 64);  // loads per wave per slab
+  static constexpr bool EVEN = SLAB_U4 % (NW * 64) == 0;
 };
 
+// Copies one k-step slab of the phase table from global memory straight into
+// LDS (gfx950 global_load_lds_dwordx4: no registers, completion tracked by
+// vmcnt).  Each wave moves 1 KB runs; the LDS base of a run is wave-uniform.
+template <int SLAB_U4, int NW>
+__device__ inline void issue_slab(const uint4* src, uint4* dst, int wid, int lane) {
+#pragma unroll
+  for (int u = 0; u < (SLAB_U4 + NW * 64 - 1) / (NW * 64); ++u) {
+    const int base = u * NW * 64 + wid * 64;
+    if (SLAB_U4 % (NW * 64) == 0 || base < SLAB_U4)
+      __builtin_amdgcn_global_load_lds(src + base + lane, dst + base, 16, 0, 0);
+  }
+}
+
 template <int NA, int NT, int NBUF, bool BF16OUT>
-__global__ __launch_bounds__(256) void k_encode(EncArgs a) {
+__global__ __launch_bounds__(512) void k_encode(EncArgs a) {
   using S = EncShape<NA, NT>;
-  static_assert(NBUF == 2 || (NBUF == 3 && S::SLAB_U4 % 256 == 0), "slab buffering");
-  constexpr int PFW = S::SLAB_U4 / 256;  // loads per wave per slab (NBUF == 3)
-  constexpr int NTW = S::NTW, WN = S::WN, CH = S::CH, MT = S::MT, SLAB_U4 = S::SLAB_U4;
+  constexpr int NW = S::NW, NTW = S::NTW, WN = S::WN, WM = S::WM, MT = S::MT, CH = S::CH,
+                SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
+  static_assert(NBUF == 2 || (NBUF == 3 && S::EVEN), "three slab buffers need even slab loads");
+  constexpr int AHEAD = NBUF - 1;  // slabs in flight beyond the one in use
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* slab = reinterpret_cast<uint4*>(smem);
   int32_t* runs_l = reinterpret_cast<int32_t*>(slab + NBUF * SLAB_U4);
@@ -125,6 +142,7 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   // two aligned dword reads.  Zeroed guards on both sides: padding slots may
   // read up to three voxels past the halo, which must hold finite values.
   uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4) + kGuard;
+  _Float16* vol16 = reinterpret_cast<_Float16*>(vol2);
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -132,12 +150,11 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
   const int KP = a.nsteps * 32;
   const int BV = a.b.bx * a.b.by * a.b.bt;
   const int D = a.D;
-  for (int k = tid; k < KP / 4; k += 256) runs_l[k] = a.runs[k];
-  for (int k = tid; k < KP; k += 256) wts_l[k] = a.wts[k];
-  _Float16* vol16 = reinterpret_cast<_Float16*>(vol2);
+  for (int k = tid; k < KP / 4; k += NW * 64) runs_l[k] = a.runs[k];
+  for (int k = tid; k < KP; k += NW * 64) wts_l[k] = a.wts[k];
   // every half that staging never writes (guards, the high half of the last
   // dword) must stay finite: clear the whole region once
-  for (int i = tid; i < a.vol + 2 * kGuard; i += 256) vol2[i - kGuard] = 0u;
+  for (int i = tid; i < a.vol + 2 * kGuard; i += NW * 64) vol2[i - kGuard] = 0u;
 
   for (;;) {
     if (tid == 0) {
@@ -150,7 +167,7 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     const int nq = a.brick_nq[bid];
     const int row0 = a.brick_off[bid];
 
-    // ---- stage the brick's counts (with halo) into LDS as fp16
+    // ---- stage the brick's counts (with halo) into LDS
     {
       const int bxi = bid % a.g.nbx, byi = (bid / a.g.nbx) % a.g.nby,
                 bti = bid / (a.g.nbx * a.g.nby);
@@ -158,7 +175,7 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
       const int nrows = a.SY * a.ST;
       const int x = x0 + lane;
       const bool xin = lane < a.SX && (unsigned)x < (unsigned)a.g.W;
-      for (int r0 = wid * 16; r0 < nrows; r0 += 64) {
+      for (int r0 = wid * 16; r0 < nrows; r0 += NW * 16) {
         int cv[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -186,29 +203,36 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     }
 
     for (int c0 = 0; c0 < nq; c0 += CH) {
-      // ---- LDS index of each row's voxel (padding rows reuse row c0)
-      for (int r = tid; r < CH; r += 256) {
-        const int rr = c0 + r < nq ? c0 + r : c0;
+      const int nr = nq - c0 < CH ? nq - c0 : CH;  // rows in this chunk
+      const int ntiles = (nr + 15) / 16;          // 16-row tiles holding rows
+      // ---- voxel of each row (row q*16 + l of the chunk; padding reuses row 0)
+      for (int r = tid; r < CH; r += NW * 64) {
+        const int rr = c0 + (r < nr ? r : 0);
         const int li = a.ulist[(int64_t)bid * BV + rr];
         const int lx = li % a.b.bx, ly = (li / a.b.bx) % a.b.by, lt = li / (a.b.bx * a.b.by);
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx);
       }
-      issue_slab<SLAB_U4>(a.frag, 0, slab, wid, lane);
-      if constexpr (NBUF == 3) {
-        if (a.nsteps > 1) {
-          issue_slab<SLAB_U4>(a.frag + SLAB_U4, 0, slab + SLAB_U4, wid, lane);
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
-        } else {
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        }
-      } else {
+      // first slabs of the table
+#pragma unroll
+      for (int u = 0; u < AHEAD; ++u)
+        if (u < a.nsteps)
+          issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
+      if (NBUF == 3 && a.nsteps > 1)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
+      else
         __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-      }
       __syncthreads();
 
+      // tiles are dealt round-robin over the row waves, so a short chunk
+      // spreads evenly and fully padded tiles are skipped
+      int mtv = 0;
       int rb[MT];  // voxel index of each row in the volume
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) rb[mt] = rowbase[wm * 64 + mt * 16 + (lane & 15)];
+      for (int mt = 0; mt < MT; ++mt) {
+        const int q = mt * WM + wm;
+        if (q < ntiles) mtv = mt + 1;
+        rb[mt] = rowbase[q * 16 + (lane & 15)];
+      }
 
       floatx4 accR[MT][NTW], accI[MT][NTW], accN[MT];
 #pragma unroll
@@ -223,8 +247,6 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
 
       for (int ks = 0; ks < a.nsteps; ++ks) {
         const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
-        const int ahead = NBUF - 1;  // slab issued this step: ks + ahead
-        const bool more = ks + ahead < a.nsteps;
         // A operands: pair sums and differences of counts at +o / -o.  The
         // lane's 8 slots are two runs of 4 consecutive dx; a +o run starts at
         // voxel base + off (ascending), its -o partner ends at base - off
@@ -234,65 +256,60 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
         half8 aS[MT], aD[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
-          const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
-          const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
-          const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
-          const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
-          const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
-          uint4 s4, d4;
-          s4.x = pk_sum_swapped(P[0], Qr[0]);
-          s4.y = pk_sum_swapped(P[1], Qr[1]);
-          s4.z = pk_sum_swapped(P[2], Qr[2]);
-          s4.w = pk_sum_swapped(P[3], Qr[3]);
-          d4.x = pk_diff_swapped(P[0], Qr[0]);
-          d4.y = pk_diff_swapped(P[1], Qr[1]);
-          d4.z = pk_diff_swapped(P[2], Qr[2]);
-          d4.w = pk_diff_swapped(P[3], Qr[3]);
-          aS[mt] = as_half8(s4);
-          aD[mt] = as_half8(d4);
+          if (mt < mtv) {
+            const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
+            const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
+            const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
+            const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
+            const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
+            const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
+            uint4 s4, d4;
+            s4.x = pk_sum_swapped(P[0], Qr[0]);
+            s4.y = pk_sum_swapped(P[1], Qr[1]);
+            s4.z = pk_sum_swapped(P[2], Qr[2]);
+            s4.w = pk_sum_swapped(P[3], Qr[3]);
+            d4.x = pk_diff_swapped(P[0], Qr[0]);
+            d4.y = pk_diff_swapped(P[1], Qr[1]);
+            d4.z = pk_diff_swapped(P[2], Qr[2]);
+            d4.w = pk_diff_swapped(P[3], Qr[3]);
+            aS[mt] = as_half8(s4);
+            aD[mt] = as_half8(d4);
+          }
         }
         const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
-        // B operands of this step, then start fetching the next slab into
-        // the other buffer while the matrix cores work
         const uint4* sb = slab + buf * SLAB_U4;
-        half8 bf[NA][NTW];
-#pragma unroll
-        for (int nt = 0; nt < NTW; ++nt)
-#pragma unroll
-          for (int q = 0; q < NA; ++q) bf[q][nt] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
-        if (more) {
-          const int nbuf = NBUF == 3 ? (ks + 2) % 3 : (buf ^ 1);
-          issue_slab<SLAB_U4>(a.frag + (size_t)(ks + ahead) * SLAB_U4, 0, slab + nbuf * SLAB_U4,
-                              wid, lane);
-        }
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
+          const int ntg = wn * NTW + nt;
+          half8 bf[NA];
+#pragma unroll
+          for (int q = 0; q < NA; ++q) bf[q] = as_half8(sb[(q * NT + ntg) * 64 + lane]);
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            if constexpr (NA == 4) {
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0][nt], accR[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2][nt], accI[mt][nt], 0, 0, 0);
-            } else {
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0][nt], accR[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1][nt], accI[mt][nt], 0, 0, 0);
+            if (mt < mtv) {
+              if constexpr (NA == 4) {
+                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
+                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2], accI[mt][nt], 0, 0, 0);
+                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1], accR[mt][nt], 0, 0, 0);
+                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3], accI[mt][nt], 0, 0, 0);
+              } else {
+                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
+                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1], accI[mt][nt], 0, 0, 0);
+              }
             }
           }
         }
-        if constexpr (NA == 4) {
-#pragma unroll
-          for (int nt = 0; nt < NTW; ++nt)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1][nt], accR[mt][nt], 0, 0, 0);
-              accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3][nt], accI[mt][nt], 0, 0, 0);
-            }
-        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
-        // the slab of step ks + 1 must have landed; with three buffers the
-        // one just issued (step ks + 2) may stay in flight
+          if (mt < mtv)
+            accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
+        // every LDS read of this step is issued: start the slab AHEAD steps
+        // out (its buffer was last read in step ks - 1), then make sure the
+        // slab of step ks + 1 has landed
+        const bool more = ks + AHEAD < a.nsteps;
+        if (more)
+          issue_slab<SLAB_U4, NW>(a.frag + (size_t)(ks + AHEAD) * SLAB_U4,
+                                  slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
         if (NBUF == 3 && more)
           __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
         else
@@ -303,17 +320,19 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
       // ---- normalise by the neighbour count and write the rows
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
+        if (mt >= mtv) continue;
+        const int q = mt * WM + wm;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = wm * 64 + mt * 16 + 4 * (lane >> 4) + i;
-          if (c0 + r >= nq) continue;
+          const int r = q * 16 + 4 * (lane >> 4) + i;
+          if (r >= nr) continue;
           const float cnt = accN[mt][i];
           const float rc = __builtin_amdgcn_rcpf(cnt);
           // x / cnt: reciprocal estimate plus one residual correction (exact
           // for x = cnt, so an all-ones feature still gives exactly 1)
           auto div = [cnt, rc](float x) {
-            const float q = x * rc;
-            return fmaf(fmaf(-q, cnt, x), rc, q);
+            const float qq = x * rc;
+            return fmaf(fmaf(-qq, cnt, x), rc, qq);
           };
           const int64_t u = (int64_t)(row0 + c0 + r) * (2 * D);
 #pragma unroll
@@ -345,6 +364,13 @@ static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
          (size_t)S::CH * 4 + 16 + (size_t)(vol + 2 * kGuard) * 4;
 }
 
+size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol) {
+  const int na = precision == VECKM_FP32 ? 4 : 2, nt = d / 16;
+  const int ntw = nt < 4 ? nt : 4, wn = nt / ntw, wm = 8 / wn, mt = nt >= 8 ? 4 : 2;
+  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)wm * mt * 16 * 4 + 16 +
+         (size_t)(vol + 2 * kGuard) * 4;
+}
+
 template <int NA, int NT, int NBUF>
 static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
                     hipStream_t s) {
@@ -354,21 +380,19 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num
                         : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, false>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
-  int per_cu = (int)((160 * 1024) / lds);
-  per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
-  int grid = num_cus * per_cu;
+  int grid = num_cus * ((160 * 1024) / lds >= 2 ? 2 : 1);
   if (grid > a.g.nbricks) grid = a.g.nbricks;
   if (bf16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, true>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, true>), dim3(grid), dim3(512), lds, s, a);
   else
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, false>), dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, false>), dim3(grid), dim3(512), lds, s, a);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
 template <int NA, int NT>
 static int launch_nb(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
                      hipStream_t s) {
-  if constexpr (EncShape<NA, NT>::SLAB_U4 % 256 == 0) {
+  if constexpr (EncShape<NA, NT>::EVEN) {
     if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, bf16, num_cus, s);
   }
   return launch_t<NA, NT, 2>(a, et, bf16, num_cus, s);
@@ -391,7 +415,7 @@ static int dispatch_nt(const EncArgs& a, const EncodeTables& et, bool bf16, int 
 int encode_rows_per_chunk(int d) {
   const int nt = d / 16;
   const int ntw = nt < 4 ? nt : 4;
-  return (4 / (nt / ntw)) * 64;
+  return (8 / (nt / ntw)) * (nt >= 8 ? 4 : 2) * 16;
 }
 
 int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et,

@@ -190,26 +190,24 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t) {
   return w;
 }
 
-// Number of phase-table slabs kept in flight in LDS: three when they fit
-// beside a useful brick, two otherwise.
-int choose_nbuf(int d, int precision) {
-  const int na = precision == VECKM_FP32 ? 4 : 2;
-  const int slab = na * (d / 16) * 1024;
-  if ((na * (d / 16)) % 4 != 0) return 2;
-  return 3 * slab + 72 * 1024 <= 160 * 1024 ? 3 : 2;
-}
-
-// Largest brick whose count volume (with halo and guards, one fp16 pair per
-// voxel) fits in LDS beside the buffered k-slabs of the phase table.
-Brick choose_brick(int rx, int ry, int rt, int d, int precision, int nbuf) {
-  const int na = precision == VECKM_FP32 ? 4 : 2;
-  const int slab = na * (d / 16) * 1024;
-  const int budget = 160 * 1024 - nbuf * slab - 8 * 1024;
+// Brick and number of phase-table slabs buffered in LDS: the largest brick
+// that fits beside three slabs, else beside two.  Larger bricks amortise the
+// window halo and give longer chunks of rows.
+void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick,
+                   int* nbuf) {
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
-                        {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}};
-  for (const Brick& b : cand)
-    if (4 * (lds_volume_halves(b, rx, ry, rt) + 32) <= budget) return b;
-  return Brick{4, 4, 1};
+                        {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}, {4, 4, 1}};
+  const int na = precision == VECKM_FP32 ? 4 : 2;
+  const bool even = (na * (d / 16) * 64) % 512 == 0;
+  for (int nb = even ? 3 : 2; nb >= 2; --nb)
+    for (const Brick& b : cand)
+      if (encode_lds_need(d, precision, nb, kp, lds_volume_halves(b, rx, ry, rt)) <= 160 * 1024) {
+        *brick = b;
+        *nbuf = nb;
+        return;
+      }
+  *brick = Brick{4, 4, 1};
+  *nbuf = 2;
 }
 
 }  // namespace veckm

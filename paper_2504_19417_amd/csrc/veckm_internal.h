@@ -56,8 +56,8 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t);
 OffsetTable make_offsets(int rx, int ry, int rt);
 // FP64 phases -> fp16 bit patterns [k][j][4] = (cos hi, cos lo, sin hi, sin lo).
 void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out);
-Brick choose_brick(int rx, int ry, int rt, int d, int precision, int nbuf);
-int choose_nbuf(int d, int precision);
+void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick, int* nbuf);
+size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol);
 int encode_rows_per_chunk(int d);
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
 uint16_t fp16_bits_rne(double v);
