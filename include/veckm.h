@@ -82,9 +82,24 @@ typedef struct veckm_params {
   int32_t d;             /* complex RFF dimension D: 16, 32, 48, 64, 128 or 256   */
   int32_t max_bins;      /* largest nbins accepted by a compute call               */
   int32_t precision;     /* VECKM_FP32 or VECKM_FP16                               */
-  int64_t max_events;    /* largest n (and m) accepted by a compute call           */
+  int64_t max_events;    /* largest n (and m) accepted by a compute call (all slices
+                            of a batch together)                                   */
   const double* A;       /* host, d x 3 row-major, columns (x, y, t); copied       */
+  int32_t max_slices;    /* largest number of slices in one batch call; 0 means 1  */
+  int64_t max_voxels;    /* largest total grid volume (sum of W*H*nbins over the
+                            slices) of one call; 0 means
+                            width*height*max_bins*max_slices                       */
 } veckm_params;
+
+/* One slice of a batch call.  Slices are independent (every neighbourhood lies
+   inside its slice, Sec. 2.1) and their events lie back to back in one array:
+   slice k owns events[offset_k, offset_k + n_k) with offset_0 = 0 and
+   offset_{k+1} = offset_k + n_k. */
+typedef struct veckm_slice {
+  int32_t width, height; /* sensor of the slice, at most the context's width, height */
+  int32_t t0, nbins;     /* time window [t0, t0 + nbins), 1 <= nbins <= max_bins       */
+  int64_t offset, n;     /* its events                                                 */
+} veckm_slice;
 
 typedef struct veckm_ctx veckm_ctx;
 
@@ -152,6 +167,19 @@ int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t
 int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                int32_t nbins, const int32_t* queries, int64_t m, float* flow,
                void* stream);
+
+/* Batch forms: one launch sequence for `count` slices (1 <= count <=
+   max_slices).  Every event of every slice is queried; outputs follow the
+   event order (emb: device, total n x 2D float32; flow: device, total n x 2
+   float32).  The result for each slice is bit-identical to encoding that
+   slice alone.  `slices` is host memory and is copied before return.
+   Returns VECKM_E_INVAL for non-contiguous slices or bad sizes, VECKM_E_RANGE
+   when the batch exceeds max_events, max_voxels or the sensor / max_bins
+   limits. */
+int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                       const veckm_event* events, float* emb, void* stream);
+int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                     const veckm_event* events, float* flow, void* stream);
 
 /* Waits for `stream`, then reports (and clears) the device-side input error
    of the calls enqueued so far: VECKM_OK, VECKM_E_RANGE or

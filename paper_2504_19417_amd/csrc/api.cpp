@@ -1,29 +1,42 @@
 // C-ABI of the veckm library: context set-up, argument validation and the
-// launch sequence of one slice.  Every step of the computation runs in the
-// HIP kernels of this library; there is no host fallback.
+// launch sequence of one call (one slice or a batch of slices).  Every step
+// of the computation runs in the HIP kernels of this library; there is no
+// host fallback.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
-#include <string>
 #include <vector>
 
 #include "veckm_internal.h"
 
 using namespace veckm;
 
+namespace {
+constexpr int kRing = 8;  // slice tables of batch calls in flight per context
+constexpr int64_t kMaxTotalVoxels = std::numeric_limits<int32_t>::max();
+}  // namespace
+
 struct veckm_ctx {
   veckm_params p{};
   std::vector<double> A;
   int device = 0;
   int num_cus = 0;
-  OffsetTable ot;
   EncodeTables et;
   Workspace w;
   MlpWeights mw;
+  int max_slices = 1;
   std::vector<void*> allocs;
   std::vector<void*> mlp_allocs;
+  // Slice tables of batch calls: pinned staging and device copies, one slot
+  // per call in flight; a slot is reused once the call that used it is done.
+  SliceDesc* table_host = nullptr;
+  SliceDesc* table_dev = nullptr;
+  hipEvent_t ring_ev[kRing] = {};
+  bool ring_used[kRing] = {};
+  int ring_next = 0;
   // per-stage timing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -61,62 +74,145 @@ int dalloc(std::vector<void*>& list, T** out, size_t count) {
   return VECKM_OK;
 }
 
+int slices_of(const veckm_params* p) { return p->max_slices > 0 ? p->max_slices : 1; }
+
+int64_t bricks_of(int W, int H, int T, const Brick& b) {
+  return (int64_t)((W + b.bx - 1) / b.bx) * ((H + b.by - 1) / b.by) * ((T + b.bt - 1) / b.bt);
+}
+
+int64_t voxels_of(const veckm_params* p) {
+  const int64_t per = (int64_t)p->width * p->height * p->max_bins;
+  return p->max_voxels > 0 ? p->max_voxels : per * slices_of(p);
+}
+
+// Pair-grid entries: (W + 1) H T per slice, at most twice the voxels.
+int64_t pair_entries_of(const veckm_params* p) {
+  const int64_t per = (int64_t)(p->width + 1) * p->height * p->max_bins;
+  return p->max_voxels > 0 ? 2 * p->max_voxels : per * slices_of(p);
+}
+
 struct Sizes {
-  int64_t V, nb, bv, U, n;
+  int64_t V, P, nb, bv, U, n;
 };
 
 Sizes sizes_for(const veckm_params* p, const Brick& b) {
   Sizes s;
-  s.V = (int64_t)p->width * p->height * p->max_bins;
-  s.nb = (int64_t)((p->width + b.bx - 1) / b.bx) * ((p->height + b.by - 1) / b.by) *
-         ((p->max_bins + b.bt - 1) / b.bt);
+  s.V = voxels_of(p);
+  s.P = pair_entries_of(p);
+  s.nb = slices_of(p) * bricks_of(p->width, p->height, p->max_bins, b);
   s.bv = b.volume();
   s.n = p->max_events;
   s.U = s.n < s.V ? s.n : s.V;
   return s;
 }
 
-int64_t bytes_for(const veckm_params* p, const Brick& b, const OffsetTable& ot, int hidden) {
+int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   const Sizes s = sizes_for(p, b);
   const int na = p->precision == VECKM_FP32 ? 4 : 2;
   int64_t bytes = 0;
-  bytes += s.V * (4 + 4 + 1);                 // count, rank, qmark
-  bytes += s.nb * s.bv * 4;                   // ulist
-  bytes += (3 * s.nb + 1) * 4;                // brick_nq, brick_off, order
-  bytes += s.n * (4 + 4);                     // vox, qmap
-  bytes += s.U * 2 * p->d * 4 + s.U * 8;      // rows (fp32 size), rowflow
-  const SlotTable st = make_slots(p->rx, p->ry, p->rt);
-  bytes += (int64_t)st.KP * p->d * na * 2 + st.KP * 3;  // table, run offsets, weights
-  bytes += 64 * 4 + 4;                        // plan, err
-  bytes += (int64_t)hidden * (2 * p->d) * 6 + hidden * 12 + 8;  // perceptron
+  bytes += s.V * (4 + 4 + 1) + s.P * 4;          // count, rank, qmark, pairs
+  bytes += s.nb * s.bv * 4;                       // ulist
+  bytes += (3 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
+  bytes += s.n * (4 + 4);                         // vox, qmap
+  bytes += s.U * 2 * p->d * 4 + s.U * 8;          // rows (fp32 size), rowflow
+  bytes += (int64_t)kp * p->d * na * 2 + kp * 3;  // phase table, run offsets, weights
+  bytes += 64 * 4 + 4 + 64 * 4;                   // plan, err, zero page
+  bytes += (int64_t)kRing * slices_of(p) * (int64_t)sizeof(SliceDesc);  // slice tables
+  bytes += (int64_t)hidden * (2 * p->d) * 6 + hidden * 12 + 8;          // perceptron
   return bytes;
 }
 
-int check_call(veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t nbins,
-               const int32_t* queries, int64_t m, const void* out) {
-  if (!c) return VECKM_E_INVAL;
+SliceDesc describe(const veckm_ctx* c, int W, int H, int T, int t0, int64_t brick_off,
+                   int64_t grid_off, int64_t pair_off, int64_t ev_off, int64_t n) {
+  const Brick& b = c->et.brick;
+  SliceDesc s;
+  s.W = W;
+  s.H = H;
+  s.T = T;
+  s.t0 = t0;
+  s.nbx = (W + b.bx - 1) / b.bx;
+  s.nby = (H + b.by - 1) / b.by;
+  s.nbt = (T + b.bt - 1) / b.bt;
+  s.brick_off = (int)brick_off;
+  s.grid_off = grid_off;
+  s.pair_off = pair_off;
+  s.ev_off = (int)ev_off;
+  s.n = (int)n;
+  return s;
+}
+
+// One slice on the context's sensor.
+int single_batch(const veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t0, int32_t nbins,
+                 const int32_t* queries, int64_t m, const void* out, Batch* bt) {
   if (n < 0 || m < 0) return VECKM_E_INVAL;
   if ((n > 0 && !ev) || (m > 0 && !out)) return VECKM_E_INVAL;
   if (!queries && m != n) return VECKM_E_INVAL;
   if (n > c->p.max_events || m > c->p.max_events) return VECKM_E_RANGE;
   if (nbins < 1 || nbins > c->p.max_bins) return VECKM_E_RANGE;
+  const int64_t V = (int64_t)c->p.width * c->p.height * nbins;
+  const int64_t P = (int64_t)(c->p.width + 1) * c->p.height * nbins;
+  if (V > c->w.vmax || P > c->w.pmax) return VECKM_E_RANGE;
+  bt->s0 = describe(c, c->p.width, c->p.height, nbins, t0, 0, 0, 0, 0, n);
+  bt->table = nullptr;
+  bt->nslices = 1;
+  bt->nbricks = bt->s0.nbx * bt->s0.nby * bt->s0.nbt;
+  bt->n = (int)n;
+  bt->m = (int)m;
+  bt->nvox = V;
+  bt->npairs = P;
   return VECKM_OK;
 }
 
-SliceGeom geom_for(const veckm_ctx* c, int64_t n, int32_t t0, int32_t nbins, int64_t m) {
-  SliceGeom g;
-  const Brick& b = c->et.brick;
-  g.W = c->p.width;
-  g.H = c->p.height;
-  g.T = nbins;
-  g.t0 = t0;
-  g.nbx = (g.W + b.bx - 1) / b.bx;
-  g.nby = (g.H + b.by - 1) / b.by;
-  g.nbt = (g.T + b.bt - 1) / b.bt;
-  g.nbricks = g.nbx * g.nby * g.nbt;
-  g.n = (int)n;
-  g.m = (int)m;
-  return g;
+// A batch of slices: validate, describe, and upload the slice table through
+// the next ring slot (*slot, released by release_slot after the launches).
+int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
+                const void* out, void* stream, Batch* bt, int* slot) {
+  *slot = -1;
+  if (!sl || count < 1 || count > c->max_slices) return VECKM_E_INVAL;
+  std::vector<SliceDesc> tab((size_t)count);
+  int64_t evs = 0, vox = 0, prs = 0, bricks = 0;
+  for (int k = 0; k < count; ++k) {
+    const veckm_slice& s = sl[k];
+    if (s.n < 0 || s.offset != evs) return VECKM_E_INVAL;
+    if (s.n > c->p.max_events - evs) return VECKM_E_RANGE;
+    if (s.width < 1 || s.height < 1 || s.width > c->p.width || s.height > c->p.height)
+      return VECKM_E_RANGE;
+    if (s.nbins < 1 || s.nbins > c->p.max_bins) return VECKM_E_RANGE;
+    tab[k] = describe(c, s.width, s.height, s.nbins, s.t0, bricks, vox, prs, evs, s.n);
+    evs += s.n;
+    vox += (int64_t)s.width * s.height * s.nbins;
+    prs += (int64_t)(s.width + 1) * s.height * s.nbins;
+    bricks += bricks_of(s.width, s.height, s.nbins, c->et.brick);
+  }
+  if (vox > c->w.vmax || prs > c->w.pmax || bricks > c->w.bmax) return VECKM_E_RANGE;
+  if (evs > 0 && (!ev || !out)) return VECKM_E_INVAL;
+  const int k = c->ring_next;
+  if (c->ring_used[k] && hipEventSynchronize(c->ring_ev[k]) != hipSuccess) return VECKM_E_HIP;
+  c->ring_next = (k + 1) % kRing;
+  SliceDesc* host = c->table_host + (size_t)k * c->max_slices;
+  SliceDesc* dev = c->table_dev + (size_t)k * c->max_slices;
+  std::memcpy(host, tab.data(), tab.size() * sizeof(SliceDesc));
+  if (hipMemcpyAsync(dev, host, tab.size() * sizeof(SliceDesc), hipMemcpyHostToDevice,
+                     (hipStream_t)stream) != hipSuccess)
+    return VECKM_E_HIP;
+  *slot = k;
+  bt->s0 = tab[0];
+  bt->table = dev;
+  bt->nslices = count;
+  bt->nbricks = (int)bricks;
+  bt->n = (int)evs;
+  bt->m = (int)evs;
+  bt->nvox = vox;
+  bt->npairs = prs;
+  return VECKM_OK;
+}
+
+// Marks the end of the call that used ring slot `slot` on `stream`.
+int release_slot(veckm_ctx* c, int slot, void* stream) {
+  if (slot < 0) return VECKM_OK;
+  if (hipEventRecord(c->ring_ev[slot], (hipStream_t)stream) != hipSuccess) return VECKM_E_HIP;
+  c->ring_used[slot] = true;
+  return VECKM_OK;
 }
 
 // Stage timing: events come from a pool made by veckm_profile_enable.
@@ -125,7 +221,8 @@ struct StageTimer {
   int stage;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(veckm_ctx* c_, int stage_, void* stream) : c(c_), stage(stage_), s((hipStream_t)stream) {
+  StageTimer(veckm_ctx* c_, int stage_, void* stream)
+      : c(c_), stage(stage_), s((hipStream_t)stream) {
     if (!c->prof || c->ev_next + 2 > c->ev_pool.size()) return;
     a = c->ev_pool[c->ev_next++];
     b = c->ev_pool[c->ev_next++];
@@ -138,34 +235,53 @@ struct StageTimer {
   }
 };
 
-int encode_rows(veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t0, int32_t nbins,
-                const int32_t* queries, int64_t m, bool bf16_rows, void* stream, SliceGeom* out) {
-  const SliceGeom g = geom_for(c, n, t0, nbins, m);
-  *out = g;
+// The launch sequence of one call: `emb` for encode calls, `flow` for flow
+// calls (exactly one is non-NULL).
+int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* queries, float* emb,
+        float* flow, void* stream) {
+  if (bt.m == 0) return VECKM_OK;
+  const bool bf16 = flow && c->p.precision == VECKM_FP16;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
-    const int rc = launch_prepare(g, c->w, ev, queries, c->et, stream);
+    const int rc = launch_prepare(bt, c->w, ev, queries, c->et, stream);
     if (rc) return rc;
   }
-  StageTimer t(c, VECKM_STAGE_ENCODE, stream);
-  return launch_encode(g, c->w, c->et, bf16_rows, c->num_cus, stream);
+  {
+    StageTimer t(c, VECKM_STAGE_ENCODE, stream);
+    const int rc = launch_encode(bt, c->w, c->et, bf16, c->num_cus, stream);
+    if (rc) return rc;
+  }
+  if (flow) {
+    StageTimer t(c, VECKM_STAGE_MLP, stream);
+    const int rc = launch_mlp(c->w, c->mw, c->p.d, bf16, c->num_cus, stream);
+    if (rc) return rc;
+  }
+  StageTimer t(c, VECKM_STAGE_EXPAND, stream);
+  return flow ? launch_expand_flow(bt, c->w, flow, stream)
+              : launch_expand_emb(bt, c->w, c->p.d, emb, stream);
 }
 
 }  // namespace
 
 extern "C" {
 
-int veckm_params_check(const veckm_params* params) { return check_params(params); }
+int veckm_params_check(const veckm_params* params) {
+  const int rc = check_params(params);
+  if (rc) return rc;
+  if (params->max_slices < 0 || params->max_voxels < 0) return VECKM_E_INVAL;
+  if (voxels_of(params) > kMaxTotalVoxels) return VECKM_E_INVAL;
+  return VECKM_OK;
+}
 
 int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
-  const int rc = check_params(params);
+  const int rc = veckm_params_check(params);
   if (rc) return rc;
   if (hidden < 0) return VECKM_E_INVAL;
   Brick b;
   int nbuf;
   const SlotTable st = make_slots(params->rx, params->ry, params->rt);
   choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &b, &nbuf);
-  return bytes_for(params, b, make_offsets(params->rx, params->ry, params->rt), hidden);
+  return bytes_for(params, b, st.KP, hidden);
 }
 
 int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* offsets,
@@ -199,7 +315,7 @@ const char* veckm_strerror(int code) {
 int veckm_create(const veckm_params* params, veckm_ctx** out) {
   if (!out) return VECKM_E_INVAL;
   *out = nullptr;
-  int rc = check_params(params);
+  int rc = veckm_params_check(params);
   if (rc) return rc;
   veckm_ctx* c = new (std::nothrow) veckm_ctx();
   if (!c) return VECKM_E_NOMEM;
@@ -211,17 +327,16 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   c->p = *params;
   c->A.assign(params->A, params->A + 3 * params->d);
   c->p.A = c->A.data();
-  c->ot = make_offsets(params->rx, params->ry, params->rt);
+  c->max_slices = slices_of(params);
   EncodeTables& et = c->et;
-  et.K = c->ot.K;
-  et.KP = c->ot.KP;
+  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
+  et.K = st.K;
+  et.KP = st.KP;
   et.na = params->precision == VECKM_FP32 ? 4 : 2;
   et.rx = params->rx;
   et.ry = params->ry;
   et.rt = params->rt;
   et.d = params->d;
-  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
-  et.KP = st.KP;
   choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &et.brick,
                 &et.nbuf);
   const std::vector<uint16_t> frag = make_slot_fragments(st, c->A.data(), params->d, et.na);
@@ -232,12 +347,15 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   uint16_t* dfrag = nullptr;
   int32_t* druns = nullptr;
   uint16_t* dwts = nullptr;
+  uint32_t* dzeros = nullptr;
   float* rows = nullptr;
   rc = VECKM_OK;
   rc = rc ? rc : dalloc(c->allocs, &dfrag, frag.size());
   rc = rc ? rc : dalloc(c->allocs, &druns, runs.size());
   rc = rc ? rc : dalloc(c->allocs, &dwts, wts.size());
+  rc = rc ? rc : dalloc(c->allocs, &dzeros, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
+  rc = rc ? rc : dalloc(c->allocs, &w.pairs, (size_t)s.P);
   rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
@@ -250,12 +368,24 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.rowflow, (size_t)(s.U * 2));
   rc = rc ? rc : dalloc(c->allocs, &w.plan, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.err, 1);
+  rc = rc ? rc : dalloc(c->allocs, &c->table_dev, (size_t)kRing * c->max_slices);
+  if (!rc && hipHostMalloc(reinterpret_cast<void**>(&c->table_host),
+                           (size_t)kRing * c->max_slices * sizeof(SliceDesc)) != hipSuccess) {
+    c->table_host = nullptr;
+    rc = VECKM_E_NOMEM;
+  }
+  for (int k = 0; !rc && k < kRing; ++k)
+    if (hipEventCreateWithFlags(&c->ring_ev[k], hipEventDisableTiming) != hipSuccess) {
+      c->ring_ev[k] = nullptr;
+      rc = VECKM_E_HIP;
+    }
   if (!rc && hipMemcpy(dfrag, frag.data(), frag.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
   if (!rc && hipMemcpy(druns, runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
   if (!rc && hipMemcpy(dwts, wts.data(), wts.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
+  if (!rc && hipMemset(dzeros, 0, 64 * sizeof(uint32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = VECKM_E_HIP;
@@ -264,7 +394,9 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     return rc;
   }
   w.rows = rows;
+  w.zeros = dzeros;
   w.vmax = s.V;
+  w.pmax = s.P;
   w.nmax = s.n;
   w.bmax = s.nb;
   et.frag = dfrag;
@@ -280,6 +412,9 @@ void veckm_destroy(veckm_ctx* ctx) {
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (void* p : ctx->mlp_allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ring_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->table_host) (void)hipHostFree(ctx->table_host);
   delete ctx;
 }
 
@@ -320,33 +455,46 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
 
 int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                  int32_t nbins, const int32_t* queries, int64_t m, float* emb, void* stream) {
-  int rc = check_call(ctx, events, n, nbins, queries, m, emb);
+  if (!ctx) return VECKM_E_INVAL;
+  Batch bt;
+  const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, emb, &bt);
   if (rc) return rc;
-  if (m == 0) return VECKM_OK;
-  SliceGeom g;
-  rc = encode_rows(ctx, events, n, t0, nbins, queries, m, false, stream, &g);
-  if (rc) return rc;
-  StageTimer t(ctx, VECKM_STAGE_EXPAND, stream);
-  return launch_expand_emb(g, ctx->w, ctx->p.d, emb, stream);
+  return run(ctx, bt, events, queries, emb, nullptr, stream);
 }
 
 int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                int32_t nbins, const int32_t* queries, int64_t m, float* flow, void* stream) {
-  int rc = check_call(ctx, events, n, nbins, queries, m, flow);
+  if (!ctx) return VECKM_E_INVAL;
+  Batch bt;
+  const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, flow, &bt);
   if (rc) return rc;
   if (ctx->mw.hidden == 0) return VECKM_E_STATE;
-  if (m == 0) return VECKM_OK;
-  const bool bf16 = ctx->p.precision == VECKM_FP16;
-  SliceGeom g;
-  rc = encode_rows(ctx, events, n, t0, nbins, queries, m, bf16, stream, &g);
+  return run(ctx, bt, events, queries, nullptr, flow, stream);
+}
+
+int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                       const veckm_event* events, float* emb, void* stream) {
+  if (!ctx) return VECKM_E_INVAL;
+  Batch bt;
+  int slot;
+  int rc = multi_batch(ctx, slices, count, events, emb, stream, &bt, &slot);
   if (rc) return rc;
-  {
-    StageTimer t(ctx, VECKM_STAGE_MLP, stream);
-    rc = launch_mlp(g, ctx->w, ctx->mw, ctx->p.d, bf16, ctx->num_cus, stream);
-    if (rc) return rc;
-  }
-  StageTimer t(ctx, VECKM_STAGE_EXPAND, stream);
-  return launch_expand_flow(g, ctx->w, flow, stream);
+  rc = run(ctx, bt, events, nullptr, emb, nullptr, stream);
+  const int rc2 = release_slot(ctx, slot, stream);
+  return rc ? rc : rc2;
+}
+
+int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                     const veckm_event* events, float* flow, void* stream) {
+  if (!ctx) return VECKM_E_INVAL;
+  if (ctx->mw.hidden == 0) return VECKM_E_STATE;
+  Batch bt;
+  int slot;
+  int rc = multi_batch(ctx, slices, count, events, flow, stream, &bt, &slot);
+  if (rc) return rc;
+  rc = run(ctx, bt, events, nullptr, nullptr, flow, stream);
+  const int rc2 = release_slot(ctx, slot, stream);
+  return rc ? rc : rc2;
 }
 
 int veckm_profile_enable(veckm_ctx* ctx, int32_t enable) {
@@ -372,7 +520,8 @@ int veckm_profile_read(veckm_ctx* ctx, double* ms, int64_t* count, int32_t nstag
   int rc = VECKM_OK;
   for (const auto& mk : ctx->marks) {
     float t = 0.f;
-    if (hipEventSynchronize(mk.b) != hipSuccess || hipEventElapsedTime(&t, mk.a, mk.b) != hipSuccess) {
+    if (hipEventSynchronize(mk.b) != hipSuccess ||
+        hipEventElapsedTime(&t, mk.a, mk.b) != hipSuccess) {
       rc = VECKM_E_HIP;
       continue;
     }

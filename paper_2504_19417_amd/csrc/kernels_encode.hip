@@ -25,6 +25,7 @@
 // wave owns 64 rows (4 MFMA row tiles) and up to 64 frequencies.
 #include <hip/hip_runtime.h>
 
+#include "slices.h"
 #include "veckm_internal.h"
 
 namespace veckm {
@@ -33,7 +34,7 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct EncArgs {
-  SliceGeom g;
+  Batch bt;
   Brick b;
   int rx, ry, rt;
   int K, nsteps;
@@ -47,6 +48,8 @@ struct EncArgs {
   const uint4* frag;
   const int32_t* runs;
   const uint16_t* wts;
+  const uint32_t* pairs;
+  const uint32_t* zeros;
   void* rows;
   int32_t* plan;
 };
@@ -94,8 +97,6 @@ __device__ inline void issue_slab(const uint4* src, int, uint4* dst, int wid, in
 
 // s_waitcnt immediate (gfx9 encoding) waiting until at most n vector memory
 // operations are outstanding; expcnt and lgkmcnt are left unconstrained.
-constexpr int kGuard = 16;  // zeroed halves on each side of the LDS count volume
-
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 template <int NA, int NT>
@@ -137,12 +138,11 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
   uint16_t* wts_l = reinterpret_cast<uint16_t*>(runs_l + a.nsteps * 8);
   int32_t* rowbase = reinterpret_cast<int32_t*>(wts_l + a.nsteps * 32);
   int32_t* item = rowbase + CH;
-  // Count volume as overlapping fp16 pairs: dword i holds the counts of
-  // voxels i and i + 1 (low, high), so any run of 4 consecutive voxels is
-  // two aligned dword reads.  Zeroed guards on both sides: padding slots may
-  // read up to three voxels past the halo, which must hold finite values.
-  uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4) + kGuard;
-  _Float16* vol16 = reinterpret_cast<_Float16*>(vol2);
+  // Count box as overlapping fp16 pairs: dword i holds the counts of box
+  // voxels i and i + 1 of the same x row, so any run of 4 consecutive voxels
+  // is two aligned dword reads.  Box rows are kRunPad voxels wider than the
+  // halo on each side, so runs (padding slots included) stay inside a row.
+  uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4);
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -152,9 +152,6 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
   const int D = a.D;
   for (int k = tid; k < KP / 4; k += NW * 64) runs_l[k] = a.runs[k];
   for (int k = tid; k < KP; k += NW * 64) wts_l[k] = a.wts[k];
-  // every half that staging never writes (guards, the high half of the last
-  // dword) must stay finite: clear the whole region once
-  for (int i = tid; i < a.vol + 2 * kGuard; i += NW * 64) vol2[i - kGuard] = 0u;
 
   for (;;) {
     if (tid == 0) {
@@ -167,37 +164,29 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
     const int nq = a.brick_nq[bid];
     const int row0 = a.brick_off[bid];
 
-    // ---- stage the brick's counts (with halo) into LDS
+    // ---- the brick's count box: one global->LDS copy per box row from the
+    //      pair grid (lanes outside the slice read zeros); it has landed once
+    //      the first chunk's prologue wait returns
     {
-      const int bxi = bid % a.g.nbx, byi = (bid / a.g.nbx) % a.g.nby,
-                bti = bid / (a.g.nbx * a.g.nby);
-      const int x0 = bxi * a.b.bx - a.rx, y0 = byi * a.b.by - a.ry, tb = bti * a.b.bt - a.rt;
+      const SliceDesc sl = slice_by_brick(a.bt, bid);
+      const int lb = bid - sl.brick_off;
+      const int bxi = lb % sl.nbx, byi = (lb / sl.nbx) % sl.nby, bti = lb / (sl.nbx * sl.nby);
+      const int x = bxi * a.b.bx - a.rx - kRunPad + lane;
+      const int y0 = byi * a.b.by - a.ry, tb = bti * a.b.bt - a.rt;
+      const bool xin = x >= -1 && x < sl.W;  // the pair grid has a column for x = -1
       const int nrows = a.SY * a.ST;
-      const int x = x0 + lane;
-      const bool xin = lane < a.SX && (unsigned)x < (unsigned)a.g.W;
-      for (int r0 = wid * 16; r0 < nrows; r0 += NW * 16) {
-        int cv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int rr = r0 + u;
-          const int sy = rr % a.SY, st = rr / a.SY;
-          const int y = y0 + sy, t = tb + st;
-          cv[u] = 0;
-          if (rr < nrows && xin && (unsigned)y < (unsigned)a.g.H && (unsigned)t < (unsigned)a.g.T)
-            cv[u] = a.count[(t * a.g.H + y) * a.g.W + x];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int rr = r0 + u;
-          // voxel i is the low half of dword i and the high half of dword
-          // i - 1 (which may belong to the previous x row: a -o run can end
-          // there with real slots)
-          if (rr < nrows && lane < a.SX) {
-            const int i = rr * a.SX + lane;
-            const _Float16 c = (_Float16)(float)cv[u];
-            vol16[2 * i] = c;
-            vol16[2 * i - 1] = c;
-          }
+      int sy = wid % a.SY, st = wid / a.SY;
+      for (int rr = wid; rr < nrows; rr += NW) {
+        const int y = y0 + sy, t = tb + st;
+        const bool in = xin && (unsigned)y < (unsigned)sl.H && (unsigned)t < (unsigned)sl.T;
+        const uint32_t* src =
+            in ? a.pairs + sl.pair_off + ((int64_t)t * sl.H + y) * (sl.W + 1) + (x + 1)
+               : a.zeros + lane;
+        if (lane < a.SX) __builtin_amdgcn_global_load_lds(src, vol2 + rr * a.SX, 4, 0, 0);
+        sy += NW;
+        while (sy >= a.SY) {
+          sy -= a.SY;
+          ++st;
         }
       }
     }
@@ -210,7 +199,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         const int rr = c0 + (r < nr ? r : 0);
         const int li = a.ulist[(int64_t)bid * BV + rr];
         const int lx = li % a.b.bx, ly = (li / a.b.bx) % a.b.by, lt = li / (a.b.bx * a.b.by);
-        rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx);
+        rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx + kRunPad);
       }
       // first slabs of the table
 #pragma unroll
@@ -361,14 +350,15 @@ template <int NA, int NT, int NBUF>
 static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
   using S = EncShape<NA, NT>;
   return (size_t)NBUF * S::SLAB_U4 * 16 + (size_t)et.KP + (size_t)et.KP * 2 +
-         (size_t)S::CH * 4 + 16 + (size_t)(vol + 2 * kGuard) * 4;
+         (size_t)S::CH * 4 + 16 + (size_t)vol * 4;
 }
+
 
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol) {
   const int na = precision == VECKM_FP32 ? 4 : 2, nt = d / 16;
   const int ntw = nt < 4 ? nt : 4, wn = nt / ntw, wm = 8 / wn, mt = nt >= 8 ? 4 : 2;
   return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)wm * mt * 16 * 4 + 16 +
-         (size_t)(vol + 2 * kGuard) * 4;
+         (size_t)vol * 4;
 }
 
 template <int NA, int NT, int NBUF>
@@ -381,7 +371,7 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
   int grid = num_cus * ((160 * 1024) / lds >= 2 ? 2 : 1);
-  if (grid > a.g.nbricks) grid = a.g.nbricks;
+  if (grid > a.bt.nbricks) grid = a.bt.nbricks;
   if (bf16)
     hipLaunchKernelGGL((k_encode<NA, NT, NBUF, true>), dim3(grid), dim3(512), lds, s, a);
   else
@@ -418,17 +408,17 @@ int encode_rows_per_chunk(int d) {
   return (8 / (nt / ntw)) * (nt >= 8 ? 4 : 2) * 16;
 }
 
-int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et,
-                  bool bf16_rows, int num_cus, void* stream) {
+int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, bool bf16_rows,
+                  int num_cus, void* stream) {
   EncArgs a;
-  a.g = g;
+  a.bt = bt;
   a.b = et.brick;
   a.rx = et.rx;
   a.ry = et.ry;
   a.rt = et.rt;
   a.K = et.K;
   a.nsteps = et.KP / kKStep;
-  a.SX = et.brick.bx + 2 * et.rx;
+  a.SX = box_sx(et.brick, et.rx);
   a.SY = et.brick.by + 2 * et.ry;
   a.ST = et.brick.bt + 2 * et.rt;
   a.vol = a.SX * a.SY * a.ST;
@@ -441,9 +431,11 @@ int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et
   a.frag = reinterpret_cast<const uint4*>(et.frag);
   a.runs = et.runs;
   a.wts = et.wts;
+  a.pairs = w.pairs;
+  a.zeros = w.zeros;
   a.rows = w.rows;
   a.plan = w.plan;
-  if (a.SX > 64) return VECKM_E_INVAL;  // one wavefront stages one x row
+  if (a.SX > 64) return VECKM_E_INVAL;  // one wavefront copies one box row
   hipStream_t s = (hipStream_t)stream;
   return et.na == 4 ? dispatch_nt<4>(a, et, bf16_rows, num_cus, s)
                     : dispatch_nt<2>(a, et, bf16_rows, num_cus, s);

@@ -1,7 +1,7 @@
 // Front end of the encoder: validate and bin events into an integer
-// (x, y, t) count grid, rank the voxels that carry queries, and map queries
-// to their voxel's row; plus the back-end expansion of per-voxel rows to
-// per-query outputs.
+// (x, y, t) count grid per slice, rank the voxels that carry queries, and
+// map queries to their voxel's row; plus the back-end expansion of
+// per-voxel rows to per-query outputs.
 //
 // All events that share a voxel have the same offset to every neighbour, so
 // the scatter of Algorithm 1 (PixelEmbed/PixelCount, Eqns. 14-15) reduces
@@ -10,8 +10,15 @@
 // (Sec. 2.1: the encoding depends on the event's position and time only), so
 // the encoder computes one row per distinct query voxel and the rows are
 // copied out per query.
+//
+// A call covers one slice or a batch of slices.  Slices are independent
+// (neighbourhoods never leave a slice); each has its own sensor size, time
+// window, event range and region of the shared grids, and the bricks of all
+// slices form one work list.
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
+#include "slices.h"
 #include "veckm_internal.h"
 
 namespace veckm {
@@ -26,66 +33,99 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 
-// One thread per event: validate, histogram, remember the voxel.
-__global__ void k_scatter(const int4* __restrict__ ev, SliceGeom g, int32_t* __restrict__ count,
+// One thread per event: validate against its slice, histogram, remember the
+// slice-local voxel.
+__global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n) return;
+  if (i >= bt.n) return;
+  const SliceDesc s = slice_by_event(bt, i);
   const int4 e = ev[i];
-  const int64_t dt = (int64_t)e.z - (int64_t)g.t0;
-  const bool ok = e.x >= 0 && e.x < g.W && e.y >= 0 && e.y < g.H && dt >= 0 && dt < g.T &&
+  const int64_t dt = (int64_t)e.z - (int64_t)s.t0;
+  const bool ok = e.x >= 0 && e.x < s.W && e.y >= 0 && e.y < s.H && dt >= 0 && dt < s.T &&
                   (e.w == 1 || e.w == -1);
   if (!ok) {
     atomicOr(err, kErrRange);
     vox[i] = -1;
     return;
   }
-  const int v = ((int)dt * g.H + e.y) * g.W + e.x;
-  const int old = atomicAdd(&count[v], 1);
+  const int v = ((int)dt * s.H + e.y) * s.W + e.x;
+  const int old = atomicAdd(&count[s.grid_off + v], 1);
   if (old == VECKM_MAX_VOXEL_EVENTS) atomicOr(err, kErrOverflow);
   vox[i] = v;
 }
 
-// Query subsets: mark the voxels that carry at least one query.
-__global__ void k_mark(const int32_t* __restrict__ queries, SliceGeom g,
+// The encoder's view of the counts: per slice, rows of W + 1 dwords; entry
+// x + 1 of a row holds the fp16 counts of voxels x and x + 1 of that x row
+// (0 outside [0, W)), for x in [-1, W).  Any 4 consecutive voxels of a row
+// then sit in two aligned dwords, including a run that starts at x = -1.
+// Exact: counts are at most VECKM_MAX_VOXEL_EVENTS.
+__global__ void k_pairs(Batch bt, const int32_t* __restrict__ count, uint32_t* __restrict__ pairs) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < bt.npairs; g += stride) {
+    int64_t poff = 0, voff = 0;
+    int W = bt.s0.W;
+    if (bt.nslices > 1) {
+      int lo = 0, hi = bt.nslices - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bt.table[mid].pair_off <= g) lo = mid; else hi = mid - 1;
+      }
+      poff = bt.table[lo].pair_off;
+      voff = bt.table[lo].grid_off;
+      W = bt.table[lo].W;
+    }
+    const int64_t p = g - poff;
+    const int64_t row = p / (W + 1);
+    const int x = (int)(p - row * (W + 1)) - 1;
+    const int32_t* c = count + voff + row * W;
+    const uint32_t lo16 = x >= 0 ? __half_as_ushort(__float2half((float)c[x])) : 0u;
+    const uint32_t hi16 = x + 1 < W ? __half_as_ushort(__float2half((float)c[x + 1])) : 0u;
+    pairs[g] = lo16 | (hi16 << 16);
+  }
+}
+
+// Query subsets (one slice): mark the voxels that carry at least one query.
+__global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
                        const int32_t* __restrict__ vox, uint8_t* __restrict__ qmark,
                        int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.m) return;
+  if (i >= bt.m) return;
   const int q = queries[i];
-  if (q < 0 || q >= g.n) {
+  if (q < 0 || q >= bt.n) {
     atomicOr(err, kErrQuery);
     return;
   }
   const int v = vox[q];
-  if (v >= 0) qmark[v] = 1;
+  if (v >= 0) qmark[bt.s0.grid_off + v] = 1;
 }
 
 // One block per brick: number the brick's query voxels in (t, y, x) order.
 // rank[v] gets the brick-local number, ulist[brick][number] the brick-local
 // voxel index, brick_nq[brick] the total.
 template <bool ALL>
-__global__ __launch_bounds__(256) void k_rank(SliceGeom g, Brick b,
-                                              const int32_t* __restrict__ count,
+__global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
                                               const uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
                                               int32_t* __restrict__ brick_nq) {
   __shared__ int wave_tot[4];
-  const int bid = blockIdx.x;
-  const int bxi = bid % g.nbx, byi = (bid / g.nbx) % g.nby, bti = bid / (g.nbx * g.nby);
+  const int gb = blockIdx.x;
+  const SliceDesc s = slice_by_brick(bt, gb);
+  const int lb = gb - s.brick_off;
+  const int bxi = lb % s.nbx, byi = (lb / s.nbx) % s.nby, bti = lb / (s.nbx * s.nby);
   const int BV = b.bx * b.by * b.bt;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int base = 0;
   for (int it = 0; it < BV; it += 256) {
     const int li = it + threadIdx.x;
     bool flag = false;
-    int v = 0;
+    int64_t v = 0;
     if (li < BV) {
       const int lx = li % b.bx, ly = (li / b.bx) % b.by, lt = li / (b.bx * b.by);
       const int x = bxi * b.bx + lx, y = byi * b.by + ly, t = bti * b.bt + lt;
-      if (x < g.W && y < g.H && t < g.T) {
-        v = (t * g.H + y) * g.W + x;
+      if (x < s.W && y < s.H && t < s.T) {
+        v = s.grid_off + (t * s.H + y) * s.W + x;
         flag = ALL ? (count[v] > 0) : (qmark[v] != 0);
       }
     }
@@ -99,12 +139,12 @@ __global__ __launch_bounds__(256) void k_rank(SliceGeom g, Brick b,
     if (flag) {
       const int r = base + woff + pre;
       rank[v] = r;
-      ulist[(int64_t)bid * BV + r] = li;
+      ulist[(int64_t)gb * BV + r] = li;
     }
     base += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) brick_nq[bid] = base;
+  if (threadIdx.x == 0) brick_nq[gb] = base;
 }
 
 // One block: exclusive scan of the per-brick row counts; plan[0] = total
@@ -161,13 +201,13 @@ __global__ __launch_bounds__(1024) void k_brick_scan(const int32_t* __restrict__
 }
 
 // One thread per query: the row of its voxel (or -1 for an invalid event).
-__global__ void k_qmap(const int32_t* __restrict__ queries, SliceGeom g, Brick b,
+__global__ void k_qmap(const int32_t* __restrict__ queries, Batch bt, Brick b,
                        const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
                        const int32_t* __restrict__ brick_off, int32_t* __restrict__ qmap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.m) return;
+  if (i >= bt.m) return;
   const int e = queries ? queries[i] : i;
-  if (e < 0 || e >= g.n) {
+  if (e < 0 || e >= bt.n) {
     qmap[i] = -1;
     return;
   }
@@ -176,9 +216,10 @@ __global__ void k_qmap(const int32_t* __restrict__ queries, SliceGeom g, Brick b
     qmap[i] = -1;
     return;
   }
-  const int x = v % g.W, y = (v / g.W) % g.H, t = v / (g.W * g.H);
-  const int bid = ((t / b.bt) * g.nby + y / b.by) * g.nbx + x / b.bx;
-  qmap[i] = brick_off[bid] + rank[v];
+  const SliceDesc s = slice_by_event(bt, e);
+  const int x = v % s.W, y = (v / s.W) % s.H, t = v / (s.W * s.H);
+  const int lb = ((t / b.bt) * s.nby + y / b.by) * s.nbx + x / b.bx;
+  qmap[i] = brick_off[s.brick_off + lb] + rank[s.grid_off + v];
 }
 
 // One wavefront per query: copy its voxel's encoding row.
@@ -210,44 +251,45 @@ static int fill_grid(int64_t n) {
   return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
-int launch_prepare(const SliceGeom& g, const Workspace& w, const veckm_event* ev,
+int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int64_t V = (int64_t)g.W * g.H * g.T;
-  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(V)), dim3(256), 0, s, w.count, V, 0);
-  if (queries) hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(V)), dim3(256), 0, s, w.qmark, V);
-  if (g.n > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(g.n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const int4*>(ev), g, w.count, w.vox, w.err);
-  if (queries && g.m > 0)
-    hipLaunchKernelGGL(k_mark, dim3(blocks_for(g.m, 256)), dim3(256), 0, s, queries, g, w.vox,
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
+  if (queries)
+    hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.qmark, bt.nvox);
+  if (bt.n > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
+  hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs);
+  if (queries && bt.m > 0)
+    hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
   if (queries)
-    hipLaunchKernelGGL(k_rank<false>, dim3(g.nbricks), dim3(256), 0, s, g, et.brick, w.count,
+    hipLaunchKernelGGL(k_rank<false>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
                        w.qmark, w.rank, w.ulist, w.brick_nq);
   else
-    hipLaunchKernelGGL(k_rank<true>, dim3(g.nbricks), dim3(256), 0, s, g, et.brick, w.count,
+    hipLaunchKernelGGL(k_rank<true>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
                        w.qmark, w.rank, w.ulist, w.brick_nq);
-  hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, g.nbricks,
+  hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, bt.nbricks,
                      encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
-  if (g.m > 0)
-    hipLaunchKernelGGL(k_qmap, dim3(blocks_for(g.m, 256)), dim3(256), 0, s, queries, g,
+  if (bt.m > 0)
+    hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
                        et.brick, w.vox, w.rank, w.brick_off, w.qmap);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-int launch_expand_emb(const SliceGeom& g, const Workspace& w, int d, float* emb, void* stream) {
-  if (g.m <= 0) return VECKM_OK;
-  hipLaunchKernelGGL(k_expand_emb, dim3(blocks_for((int64_t)g.m * 64, 256)), dim3(256), 0,
-                     (hipStream_t)stream, w.qmap, g.m, static_cast<const float*>(w.rows), 2 * d,
+int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream) {
+  if (bt.m <= 0) return VECKM_OK;
+  hipLaunchKernelGGL(k_expand_emb, dim3(blocks_for((int64_t)bt.m * 64, 256)), dim3(256), 0,
+                     (hipStream_t)stream, w.qmap, bt.m, static_cast<const float*>(w.rows), 2 * d,
                      emb);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-int launch_expand_flow(const SliceGeom& g, const Workspace& w, float* flow, void* stream) {
-  if (g.m <= 0) return VECKM_OK;
-  hipLaunchKernelGGL(k_expand_flow, dim3(blocks_for(g.m, 256)), dim3(256), 0,
-                     (hipStream_t)stream, w.qmap, g.m,
+int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream) {
+  if (bt.m <= 0) return VECKM_OK;
+  hipLaunchKernelGGL(k_expand_flow, dim3(blocks_for(bt.m, 256)), dim3(256), 0,
+                     (hipStream_t)stream, w.qmap, bt.m,
                      reinterpret_cast<const float2*>(w.rowflow), reinterpret_cast<float2*>(flow));
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }

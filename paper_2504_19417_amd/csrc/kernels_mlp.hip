@@ -1,19 +1,22 @@
 // The two-layer perceptron of Sec. 2.1 (Eqns. 5-6) on the matrix cores:
-//   flow = W2 relu(W1 x + b1) + b2,  x = [Re emb | Im emb] (2D values).
-// Layer 1 is the dense contraction [rows x 2D] x [2D x hidden]; layer 2 is
+//   flow = W2 relu(W1 x + b1) + b2,  x = [Re emb | Im emb] (K2 = 2D values).
+// Layer 1 is the dense contraction [rows x K2] x [K2 x hidden]; layer 2 is
 // two dot products per row, done in the epilogue while the hidden values
 // are still in registers (ReLU, multiply by W2, reduce across the lanes
 // and waves that hold a row's hidden units).
 //
-// Operands stream straight from global memory into registers: each lane
-// loads 16 contiguous bytes of a row of x and of a row of W1 (W1 is
-// [hidden][2D], so both are contiguous along the contraction).  The
-// contraction index is permuted consistently in A and B so that these
-// 16-byte runs map onto the k-slots of the MFMA.
+// A block of 4 waves owns 64-row tiles of x (persistent loop over tiles);
+// wave w owns hidden units [w*hidden/4, (w+1)*hidden/4).  The x tile of the
+// next iteration streams into LDS with global_load_lds while the current
+// one is multiplied (double buffer), 16-byte chunks XOR-swizzled by row so
+// that fragment reads hit distinct banks.  W1 operands: fp32 fragments are
+// read from L2 one k-slice ahead; bf16 fragments of the wave's hidden units
+// stay in registers for the whole kernel when they fit (else read from L2).
+// The contraction index is permuted consistently in A and B so that each
+// lane's operand is 16 contiguous bytes of a row of x and of a row of W1
+// (W1 is [hidden][K2], contiguous along the contraction).
 //
-// One block of 4 waves handles 64 rows; wave w owns hidden units
-// [w*hidden/4, (w+1)*hidden/4).  Blocks loop over row tiles (persistent);
-// the row count U is read from the device, so no host synchronisation is
+// The row count U is read from the device, so no host synchronisation is
 // needed between the encoder and the perceptron.
 #include <hip/hip_runtime.h>
 
@@ -25,13 +28,13 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct MlpArgs {
-  const void* x;     // U x K2 (fp32 or bf16)
-  const float* W1;   // hidden x K2 fp32
+  const void* x;        // U x K2 (fp32 or bf16)
+  const float* W1;      // hidden x K2 fp32
   const uint16_t* W1b;  // hidden x K2 bf16
   const float* b1;
-  const float* W2;   // 2 x hidden
+  const float* W2;  // 2 x hidden
   const float* b2;
-  float* out;        // U x 2
+  float* out;  // U x 2
   const int32_t* plan;
   int K2;
   int hidden;
@@ -43,14 +46,30 @@ __device__ inline bf16x8 as_bf16x8(uint4 u) {
   return h;
 }
 
-// Layer-2 epilogue shared by both precisions.  acc[mt][nt][i] is the
-// pre-activation of row 16*mt + 4*(lane>>4) + i, hidden unit
-// col0 + 16*nt + (lane&15).
+constexpr int mlp_vmcnt0() { return (7 << 4) | (15 << 8); }
+
+// Per-wave layer constants: b1, W2[0], W2[1] of the lane's hidden units.
 template <int NTH>
-__device__ inline void mlp_epilogue(const MlpArgs& a, floatx4 (&acc)[4][NTH], int tile, int U,
-                                    float (*red)[64][2]) {
+struct Layer2 {
+  float b[NTH], w0[NTH], w1[NTH];
+  __device__ void load(const MlpArgs& a) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int nt = 0; nt < NTH; ++nt) {
+      const int c = wid * NTH * 16 + nt * 16 + (lane & 15);
+      b[nt] = a.b1[c];
+      w0[nt] = a.W2[c];
+      w1[nt] = a.W2[a.hidden + c];
+    }
+  }
+};
+
+// Layer-2 epilogue.  acc[mt][nt][i] is the pre-activation of row
+// 16*mt + 4*(lane>>4) + i of the tile, hidden unit col0 + 16*nt + (lane&15).
+template <int NTH>
+__device__ inline void mlp_epilogue(const MlpArgs& a, const Layer2<NTH>& l2, floatx4 (&acc)[4][NTH],
+                                    int tile, int U, float (*red)[64][2]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int col0 = wid * NTH * 16;
   float p0[4][4], p1[4][4];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
@@ -58,8 +77,7 @@ __device__ inline void mlp_epilogue(const MlpArgs& a, floatx4 (&acc)[4][NTH], in
     for (int i = 0; i < 4; ++i) p0[mt][i] = p1[mt][i] = 0.f;
 #pragma unroll
   for (int nt = 0; nt < NTH; ++nt) {
-    const int c = col0 + nt * 16 + (lane & 15);
-    const float bb = a.b1[c], w0 = a.W2[c], w1 = a.W2[a.hidden + c];
+    const float bb = l2.b[nt], w0 = l2.w0[nt], w1 = l2.w1[nt];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -91,14 +109,198 @@ __device__ inline void mlp_epilogue(const MlpArgs& a, floatx4 (&acc)[4][NTH], in
     const float v = red[0][r][o] + red[1][r][o] + red[2][r][o] + red[3][r][o] + a.b2[o];
     if (row < U) a.out[(int64_t)row * 2 + o] = v;
   }
-  __syncthreads();
 }
 
-template <int NTH>
+// Starts the copy of x tile `tile` (64 rows of RB bytes) into an LDS buffer:
+// LDS chunk p of row r holds global chunk p ^ (r & 15) (16-byte chunks).
+// Rows past U repeat row U - 1 (their results are dropped).
+template <int RB>
+__device__ inline void issue_tile(const unsigned char* x, int tile, int U, uint4* buf, int wid,
+                                  int lane) {
+  constexpr int CPR = RB / 16;          // chunks per row
+  constexpr int RPI = 64 / CPR;         // rows per wave instruction
+  static_assert(64 % CPR == 0, "row size");
+#pragma unroll
+  for (int u = 0; u < 64 / RPI / 4; ++u) {
+    const int rb = (u * 4 + wid) * RPI;  // first row of this instruction
+    const int r = rb + lane / CPR, p = lane % CPR;
+    int row = tile * 64 + r;
+    row = row < U ? row : U - 1;
+    const uint4* src = reinterpret_cast<const uint4*>(x + (int64_t)row * RB) + (p ^ (r & 15));
+    __builtin_amdgcn_global_load_lds(src, buf + rb * CPR, 16, 0, 0);
+  }
+}
+
+// fp32: A from the LDS tile, B (W1) from L2 one k-slice ahead.
+template <int NTH, int K2>
 __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs a) {
+  constexpr int RB = K2 * 4, CPR = RB / 16;
+  extern __shared__ __align__(16) unsigned char smem_mlp[];
+  uint4* tbuf = reinterpret_cast<uint4*>(smem_mlp);  // 2 x 64 rows
   __shared__ float red[4][64][2];
   const int U = a.plan[0];
   const int ntiles = (U + 63) / 64;
+  Layer2<NTH> l2;
+  l2.load(a);
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const unsigned char* X = static_cast<const unsigned char*>(a.x);
+  const float* wr[NTH];
+#pragma unroll
+  for (int nt = 0; nt < NTH; ++nt)
+    wr[nt] = a.W1 + (int64_t)(wid * NTH * 16 + nt * 16 + r16) * K2 + 4 * g;
+  int tile = blockIdx.x;
+  if (tile < ntiles) issue_tile<RB>(X, tile, U, tbuf, wid, lane);
+  for (int it = 0; tile < ntiles; tile += gridDim.x, ++it) {
+    uint4* cur = tbuf + (it & 1) * 64 * CPR;
+    const int next = tile + gridDim.x;
+    __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
+    __syncthreads();  // tile `tile` is in `cur`; the other buffer is free
+    if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
+    floatx4 acc[4][NTH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float4 bv[NTH], bn[NTH];
+#pragma unroll
+    for (int nt = 0; nt < NTH; ++nt) bv[nt] = *reinterpret_cast<const float4*>(wr[nt]);
+#pragma unroll 2
+    for (int kq = 0; kq < K2 / 16; ++kq) {
+      if (kq + 1 < K2 / 16) {
+#pragma unroll
+        for (int nt = 0; nt < NTH; ++nt)
+          bn[nt] = *reinterpret_cast<const float4*>(wr[nt] + (kq + 1) * 16);
+      }
+      float4 av[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int r = mt * 16 + r16, c = kq * 4 + g;
+        av[mt] = *reinterpret_cast<const float4*>(cur + r * CPR + (c ^ (r & 15)));
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTH; ++nt) {
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt].x, bv[nt].x, acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt].y, bv[nt].y, acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt].z, bv[nt].z, acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt].w, bv[nt].w, acc[mt][nt], 0, 0, 0);
+        }
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) bv[nt] = bn[nt];
+    }
+    mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
+  }
+}
+
+// bf16: A from the LDS tile, B (W1) resident in registers.
+template <int NTH, int K2>
+__global__ __launch_bounds__(256) void k_mlp_bf16_res(MlpArgs a) {
+  constexpr int RB = K2 * 2, CPR = RB / 16, KQ = K2 / 32;
+  extern __shared__ __align__(16) unsigned char smem_mlp[];
+  uint4* tbuf = reinterpret_cast<uint4*>(smem_mlp);
+  __shared__ float red[4][64][2];
+  const int U = a.plan[0];
+  const int ntiles = (U + 63) / 64;
+  Layer2<NTH> l2;
+  l2.load(a);
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const unsigned char* X = static_cast<const unsigned char*>(a.x);
+  bf16x8 w[KQ][NTH];
+#pragma unroll
+  for (int nt = 0; nt < NTH; ++nt) {
+    const uint16_t* wr = a.W1b + (int64_t)(wid * NTH * 16 + nt * 16 + r16) * K2 + 8 * g;
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) w[kq][nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wr + kq * 32));
+  }
+  int tile = blockIdx.x;
+  if (tile < ntiles) issue_tile<RB>(X, tile, U, tbuf, wid, lane);
+  for (int it = 0; tile < ntiles; tile += gridDim.x, ++it) {
+    uint4* cur = tbuf + (it & 1) * 64 * CPR;
+    const int next = tile + gridDim.x;
+    __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
+    __syncthreads();
+    if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
+    floatx4 acc[4][NTH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+      bf16x8 av[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int r = mt * 16 + r16, c = kq * 4 + g;
+        av[mt] = as_bf16x8(cur[r * CPR + (c ^ (r & 15))]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTH; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], w[kq][nt], acc[mt][nt], 0, 0, 0);
+    }
+    mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
+  }
+}
+
+// bf16 fallback (any K2 multiple of 32, any hidden): operands from L2.
+template <int NTH>
+__global__ __launch_bounds__(256) void k_mlp_bf16(MlpArgs a) {
+  __shared__ float red[4][64][2];
+  const int U = a.plan[0];
+  const int ntiles = (U + 63) / 64;
+  Layer2<NTH> l2;
+  l2.load(a);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint16_t* X = static_cast<const uint16_t*>(a.x);
+  const int g = lane >> 4;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    floatx4 acc[4][NTH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* xr[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      int row = tile * 64 + mt * 16 + (lane & 15);
+      row = row < U ? row : U - 1;
+      xr[mt] = X + (int64_t)row * a.K2 + 8 * g;
+    }
+    const uint16_t* wr[NTH];
+#pragma unroll
+    for (int nt = 0; nt < NTH; ++nt)
+      wr[nt] = a.W1b + (int64_t)(wid * NTH * 16 + nt * 16 + (lane & 15)) * a.K2 + 8 * g;
+    for (int kq = 0; kq < a.K2; kq += 32) {
+      bf16x8 av[4], bv[NTH];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) av[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(xr[mt] + kq));
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wr[nt] + kq));
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTH; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+    }
+    mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
+    __syncthreads();
+  }
+}
+
+// fp32 fallback (K2 not specialised): operands from L2.
+template <int NTH>
+__global__ __launch_bounds__(256) void k_mlp_f32_any(MlpArgs a) {
+  __shared__ float red[4][64][2];
+  const int U = a.plan[0];
+  const int ntiles = (U + 63) / 64;
+  Layer2<NTH> l2;
+  l2.load(a);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const float* X = static_cast<const float*>(a.x);
   const int g = lane >> 4;
@@ -135,62 +337,41 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs a) {
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt].w, bv[nt].w, acc[mt][nt], 0, 0, 0);
         }
     }
-    mlp_epilogue<NTH>(a, acc, tile, U, red);
+    mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
+    __syncthreads();
   }
 }
 
+template <typename K>
+static int launch_lds(K kern, const MlpArgs& a, size_t lds, int per_cu, int num_cus, hipStream_t s) {
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return VECKM_E_HIP;
+  hipLaunchKernelGGL(kern, dim3(num_cus * per_cu), dim3(256), lds, s, a);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
 template <int NTH>
-__global__ __launch_bounds__(256) void k_mlp_bf16(MlpArgs a) {
-  __shared__ float red[4][64][2];
-  const int U = a.plan[0];
-  const int ntiles = (U + 63) / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint16_t* X = static_cast<const uint16_t*>(a.x);
-  const int g = lane >> 4;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    floatx4 acc[4][NTH];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t* xr[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      int row = tile * 64 + mt * 16 + (lane & 15);
-      row = row < U ? row : U - 1;
-      xr[mt] = X + (int64_t)row * a.K2 + 8 * g;
+static int launch_nth(const MlpArgs& a, bool bf16, int num_cus, hipStream_t s) {
+  if (bf16) {
+    // W1 of the wave's hidden units in registers when it fits (<= 128 VGPRs)
+    if constexpr (NTH <= 4) {
+      if (a.K2 == 256 && (a.K2 / 32) * NTH <= 32)
+        return launch_lds(k_mlp_bf16_res<NTH, 256>, a, 2 * 64 * 256 * 2, 1, num_cus, s);
+      if (a.K2 == 128)
+        return launch_lds(k_mlp_bf16_res<NTH, 128>, a, 2 * 64 * 128 * 2, 1, num_cus, s);
     }
-    const uint16_t* wr[NTH];
-#pragma unroll
-    for (int nt = 0; nt < NTH; ++nt)
-      wr[nt] = a.W1b + (int64_t)(wid * NTH * 16 + nt * 16 + (lane & 15)) * a.K2 + 8 * g;
-    for (int kq = 0; kq < a.K2; kq += 32) {
-      bf16x8 av[4], bv[NTH];
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) av[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(xr[mt] + kq));
-#pragma unroll
-      for (int nt = 0; nt < NTH; ++nt) bv[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wr[nt] + kq));
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NTH; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
-    }
-    mlp_epilogue<NTH>(a, acc, tile, U, red);
+    hipLaunchKernelGGL(k_mlp_bf16<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
+  } else {
+    if (a.K2 == 256) return launch_lds(k_mlp_f32<NTH, 256>, a, 2 * 64 * 256 * 4, 1, num_cus, s);
+    if (a.K2 == 128) return launch_lds(k_mlp_f32<NTH, 128>, a, 2 * 64 * 128 * 4, 2, num_cus, s);
+    hipLaunchKernelGGL(k_mlp_f32_any<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
   }
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-template <int NTH>
-static void launch_nth(const MlpArgs& a, bool bf16, int grid, hipStream_t s) {
-  if (bf16)
-    hipLaunchKernelGGL(k_mlp_bf16<NTH>, dim3(grid), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_mlp_f32<NTH>, dim3(grid), dim3(256), 0, s, a);
-}
-
-int launch_mlp(const SliceGeom& g, const Workspace& w, const MlpWeights& mw, int d, bool bf16,
-               int num_cus, void* stream) {
-  (void)g;
+int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int num_cus,
+               void* stream) {
   MlpArgs a;
   a.x = w.rows;
   a.W1 = mw.W1;
@@ -202,21 +383,19 @@ int launch_mlp(const SliceGeom& g, const Workspace& w, const MlpWeights& mw, int
   a.plan = w.plan;
   a.K2 = 2 * d;
   a.hidden = mw.hidden;
-  if (bf16 && (a.K2 % 32)) return VECKM_E_INVAL;
-  const int grid = num_cus * 4;
+  if (a.K2 % 32) return VECKM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   switch (mw.hidden / 64) {
-    case 1: launch_nth<1>(a, bf16, grid, s); break;
-    case 2: launch_nth<2>(a, bf16, grid, s); break;
-    case 3: launch_nth<3>(a, bf16, grid, s); break;
-    case 4: launch_nth<4>(a, bf16, grid, s); break;
-    case 5: launch_nth<5>(a, bf16, grid, s); break;
-    case 6: launch_nth<6>(a, bf16, grid, s); break;
-    case 7: launch_nth<7>(a, bf16, grid, s); break;
-    case 8: launch_nth<8>(a, bf16, grid, s); break;
+    case 1: return launch_nth<1>(a, bf16, num_cus, s);
+    case 2: return launch_nth<2>(a, bf16, num_cus, s);
+    case 3: return launch_nth<3>(a, bf16, num_cus, s);
+    case 4: return launch_nth<4>(a, bf16, num_cus, s);
+    case 5: return launch_nth<5>(a, bf16, num_cus, s);
+    case 6: return launch_nth<6>(a, bf16, num_cus, s);
+    case 7: return launch_nth<7>(a, bf16, num_cus, s);
+    case 8: return launch_nth<8>(a, bf16, num_cus, s);
     default: return VECKM_E_INVAL;
   }
-  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
 }  // namespace veckm

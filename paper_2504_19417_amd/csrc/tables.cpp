@@ -123,6 +123,8 @@ int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {
   return (b.bx + 2 * rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
 }
 
+
+
 SlotTable make_slots(int rx, int ry, int rt) {
   SlotTable t;
   auto row = [&](int dx0, int dx1, int dy, int dt, bool centre) {
@@ -172,7 +174,7 @@ std::vector<uint16_t> make_slot_fragments(const SlotTable& t, const double* A, i
 }
 
 std::vector<int32_t> make_run_offsets(const SlotTable& t, const Brick& b, int rx, int ry) {
-  const int SX = b.bx + 2 * rx, SY = b.by + 2 * ry;
+  const int SX = box_sx(b, rx), SY = b.by + 2 * ry;
   std::vector<int32_t> runs(t.KP / 4, 0);
   for (int r = 0; r < t.KP / 4; ++r) {
     const int* s = &t.slot[4 * 4 * r];
@@ -201,7 +203,7 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
   const bool even = (na * (d / 16) * 64) % 512 == 0;
   for (int nb = even ? 3 : 2; nb >= 2; --nb)
     for (const Brick& b : cand)
-      if (encode_lds_need(d, precision, nb, kp, lds_volume_halves(b, rx, ry, rt)) <= 160 * 1024) {
+      if (encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024) {
         *brick = b;
         *nbuf = nb;
         return;

@@ -60,35 +60,60 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol);
 int encode_rows_per_chunk(int d);
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
+// The encoder's LDS box of a brick: the brick plus the window halo, widened
+// by kRunPad columns on each side in x so that no 4-offset run of the slot
+// layout ever leaves a box row.
+constexpr int kRunPad = 3;
+inline int box_sx(const Brick& b, int rx) { return b.bx + 2 * rx + 2 * kRunPad; }
+inline int box_dwords(const Brick& b, int rx, int ry, int rt) {
+  return box_sx(b, rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
+}
 uint16_t fp16_bits_rne(double v);
 uint16_t bf16_bits_rne(float v);
 
 // ---------------------------------------------------------------- launches
-// Every slice-level argument the kernels need, passed by value.
-struct SliceGeom {
-  int W, H, T;         // grid extent (T = nbins)
-  int t0;              // time of bin 0
-  int nbx, nby, nbt;   // bricks per axis
-  int nbricks;
-  int n;               // events
-  int m;               // queries
+// One slice of a call: its sensor, time window, events and its region of the
+// shared grids and brick list.  Slices lie back to back in every array.
+struct SliceDesc {
+  int W, H, T;        // grid extent (T = nbins)
+  int t0;             // time of bin 0
+  int nbx, nby, nbt;  // bricks per axis
+  int brick_off;      // first global brick
+  int64_t grid_off;   // first voxel in the count / rank / mark grids
+  int64_t pair_off;   // first entry in the pair grid (rows of W + 1 entries)
+  int ev_off, n;      // events [ev_off, ev_off + n)
+};
+
+// Everything the kernels need to know about the slices of one call.
+struct Batch {
+  SliceDesc s0;              // the slice when nslices == 1
+  const SliceDesc* table;    // device copy of all slices when nslices > 1
+  int nslices;
+  int nbricks;               // total bricks
+  int n;                     // total events
+  int m;                     // total queries
+  int64_t nvox;              // total voxels
+  int64_t npairs;            // total pair-grid entries (sum of (W + 1) H T)
 };
 
 struct Workspace {
-  int32_t* count = nullptr;     // V int32 event counts per voxel [T][H][W]
-  int32_t* rank = nullptr;      // V int32 brick-local rank of query voxels
-  uint8_t* qmark = nullptr;     // V bytes, query-voxel marks (query subsets)
-  int32_t* ulist = nullptr;     // nbricks * brick volume: brick-local voxel of each rank
-  int32_t* brick_nq = nullptr;  // nbricks
-  int32_t* brick_off = nullptr; // nbricks + 1 (exclusive scan)
-  int32_t* order = nullptr;     // nbricks: non-empty bricks, most encoder chunks first
-  int32_t* vox = nullptr;       // n: voxel of each event, -1 if invalid
+  int32_t* count = nullptr;     // voxels: int32 event counts, slices back to back
+  uint32_t* pairs = nullptr;    // (W + 1) H T per slice: entry x + 1 of a row holds the fp16
+                                // counts of voxels x and x + 1 of that row, x in [-1, W)
+  const uint32_t* zeros = nullptr;  // 64 zero dwords (out-of-grid reads)
+  int32_t* rank = nullptr;      // voxels: brick-local rank of query voxels
+  uint8_t* qmark = nullptr;     // voxels: query-voxel marks (query subsets)
+  int32_t* ulist = nullptr;     // bricks * brick volume: brick-local voxel of each rank
+  int32_t* brick_nq = nullptr;  // bricks
+  int32_t* brick_off = nullptr; // bricks + 1 (exclusive scan)
+  int32_t* order = nullptr;     // bricks: non-empty bricks, most encoder chunks first
+  int32_t* vox = nullptr;       // n: slice-local voxel of each event, -1 if invalid
   int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
   void* rows = nullptr;         // U x 2D encodings (fp32 or bf16)
   float* rowflow = nullptr;     // U x 2
   int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2] = non-empty bricks
   int32_t* err = nullptr;       // error bits
-  int64_t vmax = 0, nmax = 0, bmax = 0;
+  int64_t vmax = 0, pmax = 0, nmax = 0, bmax = 0;
 };
 
 struct EncodeTables {
@@ -111,14 +136,13 @@ struct MlpWeights {
   const float* b2 = nullptr;
 };
 
-int launch_prepare(const SliceGeom& g, const Workspace& w, const veckm_event* ev,
+int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, void* stream);
-int launch_encode(const SliceGeom& g, const Workspace& w, const EncodeTables& et,
-                  bool bf16_rows, int num_cus, void* stream);
-int launch_expand_emb(const SliceGeom& g, const Workspace& w, int d, float* emb,
-                      void* stream);
-int launch_mlp(const SliceGeom& g, const Workspace& w, const MlpWeights& mw, int d,
-               bool bf16, int num_cus, void* stream);
-int launch_expand_flow(const SliceGeom& g, const Workspace& w, float* flow, void* stream);
+int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, bool bf16_rows,
+                  int num_cus, void* stream);
+int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream);
+int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int num_cus,
+               void* stream);
+int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream);
 
 }  // namespace veckm

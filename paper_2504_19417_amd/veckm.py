@@ -49,6 +49,16 @@ class veckm_params(ctypes.Structure):
         ("d", ctypes.c_int32), ("max_bins", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("max_events", ctypes.c_int64),
         ("A", ctypes.POINTER(ctypes.c_double)),
+        ("max_slices", ctypes.c_int32),
+        ("max_voxels", ctypes.c_int64),
+    ]
+
+
+class veckm_slice(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("t0", ctypes.c_int32), ("nbins", ctypes.c_int32),
+        ("offset", ctypes.c_int64), ("n", ctypes.c_int64),
     ]
 
 
@@ -77,6 +87,8 @@ _sig = {
                                     ctypes.c_int64, _P, _P]),
     "veckm_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P, _P]),
+    "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
+    "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
     "veckm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "veckm_profile_read": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
@@ -88,7 +100,8 @@ for _name, (_res, _args) in _sig.items():
     _f.argtypes = _args
 
 
-def make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32"):
+def make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32",
+                max_slices=0, max_voxels=0):
     """Build a veckm_params; the returned object keeps A alive."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
     p = veckm_params()
@@ -98,8 +111,22 @@ def make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision="f
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.max_events = int(max_events)
     p.A = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.max_slices = int(max_slices)
+    p.max_voxels = int(max_voxels)
     p._A_keepalive = A
     return p
+
+
+def make_slices(specs):
+    """A veckm_slice array from (width, height, t0, nbins, n) tuples, events
+    back to back in the given order."""
+    arr = (veckm_slice * len(specs))()
+    off = 0
+    for k, (w, h, t0, nbins, n) in enumerate(specs):
+        arr[k].width, arr[k].height, arr[k].t0, arr[k].nbins = int(w), int(h), int(t0), int(nbins)
+        arr[k].offset, arr[k].n = off, int(n)
+        off += int(n)
+    return arr
 
 
 def veckm_params_check(params):
@@ -158,6 +185,16 @@ def veckm_flow(ctx, events_ptr, n, t0, nbins, queries_ptr, m, flow_ptr, stream):
                            flow_ptr, stream)
 
 
+def veckm_encode_batch(ctx, slices, count, events_ptr, emb_ptr, stream):
+    return _lib.veckm_encode_batch(ctx, ctypes.cast(slices, _P), int(count), events_ptr, emb_ptr,
+                                   stream)
+
+
+def veckm_flow_batch(ctx, slices, count, events_ptr, flow_ptr, stream):
+    return _lib.veckm_flow_batch(ctx, ctypes.cast(slices, _P), int(count), events_ptr, flow_ptr,
+                                 stream)
+
+
 def veckm_status(ctx, stream):
     return _lib.veckm_status(ctx, stream)
 
@@ -189,8 +226,10 @@ def veckm_last_rows(ctx, stream):
 class Context:
     """A veckm context driven with torch CUDA tensors."""
 
-    def __init__(self, width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32"):
-        self.params = make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision)
+    def __init__(self, width, height, rx, ry, rt, A, max_bins, max_events, precision="fp32",
+                 max_slices=0, max_voxels=0):
+        self.params = make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision,
+                                  max_slices, max_voxels)
         self.d = self.params.d
         self.handle = veckm_create(self.params)
         self.hidden = 0
@@ -253,6 +292,29 @@ class Context:
         if rc:
             raise VeckmError(rc, "veckm_flow")
         return out
+
+    def _batch(self, fn, name, width, slices, events, out, stream):
+        import torch
+        self._check_inputs(events, None)
+        arr = make_slices(slices)
+        n = sum(int(s[4]) for s in slices)
+        if n != events.shape[0]:
+            raise ValueError("slice sizes add up to %d events, got %d" % (n, events.shape[0]))
+        if out is None:
+            out = torch.empty((n, width), dtype=torch.float32, device=events.device)
+        rc = fn(self.handle, arr, len(slices), events.data_ptr(), out.data_ptr(),
+                self._stream(stream))
+        if rc:
+            raise VeckmError(rc, name)
+        return out
+
+    def encode_batch(self, slices, events, out=None, stream=None):
+        """slices: (width, height, t0, nbins, n) per slice, events back to back."""
+        return self._batch(veckm_encode_batch, "veckm_encode_batch", 2 * self.d, slices, events,
+                           out, stream)
+
+    def flow_batch(self, slices, events, out=None, stream=None):
+        return self._batch(veckm_flow_batch, "veckm_flow_batch", 2, slices, events, out, stream)
 
     def status(self, stream=None):
         return veckm_status(self.handle, self._stream(stream))
