@@ -113,22 +113,95 @@ def sampled_error(oracle, w, ev, A, mlp, flows, seed=903, count=2048):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-def load_traffic(kernel):
-    """HBM traffic of `kernel` measured with rocprofv3 counters, if the
-    summary in profiles/ was taken on the current kernel source."""
+KERNEL_SOURCES = {  # short kernel name -> source file it is built from
+    "k_encode": "paper_2504_19417_amd/csrc/kernels_encode.hip",
+    "k_mlp_f32": "paper_2504_19417_amd/csrc/kernels_mlp.hip",
+    "k_mlp_bf16_res": "paper_2504_19417_amd/csrc/kernels_mlp.hip",
+}
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
+
+
+def source_sha(rel):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    return hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters (scaled by the copy calibration), if they were taken
+    on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
     try:
-        rec = json.load(open(path)).get(kernel)
-        src = os.path.join(ROOT, rec["source"])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        if sha != rec["source_sha"]:
+        rec = json.load(open(TRAFFIC_JSON))["kernels"][kernel]
+        if source_sha(rec["source"]) != rec["source_sha"]:
             return None
-        return rec["bytes_per_launch"]
+        return rec["hbm_bytes_per_launch"]
     except Exception:
         return None
+
+
+def copy_calibration(torch):
+    """A plain device copy of known size (elementwise negation of a 1 GiB
+    float32 buffer into another), for scaling the HBM byte counters."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def _read_counters(path):
+    """{kernel name: [mean counter value over dispatches, dispatches]} from a
+    rocprofv3 counter_collection.csv holding one counter."""
+    import csv
+    acc = {}
+    for row in csv.DictReader(open(path)):
+        name = row["Kernel_Name"]
+        a = acc.setdefault(name, [0.0, 0])
+        a[0] += float(row["Counter_Value"])
+        a[1] += 1
+    return {k: [v[0] / v[1], v[1]] for k, v in acc.items()}
+
+
+def _find_csv(d, suffix):
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError("no *%s under %s" % (suffix, d))
+
+
+def summarize_traffic(fetch_dir, write_dir, command):
+    """Writes the traffic summary: per-launch FETCH_SIZE and WRITE_SIZE (KiB)
+    of each kernel, scaled by what the same counters read for the 1 GiB
+    calibration copy."""
+    fetch = _read_counters(_find_csv(fetch_dir, "counter_collection.csv"))
+    write = _read_counters(_find_csv(write_dir, "counter_collection.csv"))
+    copy = [k for k in fetch if "neg" in k.lower()]
+    if len(copy) != 1:
+        raise RuntimeError("calibration copy kernel not found uniquely: %s" % copy)
+    kib = COPY_BYTES / 1024.0
+    f_scale = kib / fetch[copy[0]][0]
+    w_scale = kib / write[copy[0]][0]
+    out = {"command": command, "copy_kernel": copy[0], "copy_bytes": COPY_BYTES,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}, "all": {}}
+    for name in sorted(fetch):
+        if name not in write:
+            continue
+        fk, wk = fetch[name][0], write[name][0]
+        out["all"][name] = {"fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                            "dispatches": fetch[name][1],
+                            "hbm_bytes": int(round((fk * f_scale + wk * w_scale) * 1024))}
+        for short, src in KERNEL_SOURCES.items():
+            if ("veckm::%s<" % short) in name or name.startswith("%s<" % short):
+                out["kernels"].setdefault(short, {
+                    "kernel": name, "source": src, "source_sha": source_sha(src),
+                    "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
+                    "hbm_bytes_per_launch": out["all"][name]["hbm_bytes"]})
+    return out
 
 
 def main():
@@ -138,7 +211,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 1 GiB on the device (counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
+                         "into profiles/traffic.json and exit (no GPU needed)")
+    ap.add_argument("--command", default="", help="command recorded with --summarize-traffic")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        rec = summarize_traffic(*args.summarize_traffic, args.command)
+        with open(TRAFFIC_JSON, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec["kernels"], indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(independent slices shard across GPUs with no exchange); run with --gpus 1",
@@ -225,7 +310,9 @@ def main():
         "cpu_baseline": cpu,
         "paper_context_flows_per_s": {"rtx3070": 4e6, "rtx_a5000": 6e6},
     }
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        copy_calibration(torch)
 
 
 if __name__ == "__main__":
