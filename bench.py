@@ -113,6 +113,82 @@ def sampled_error(oracle, w, ev, A, mlp, flows, seed=903, count=2048):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
+def serving_run(vk, seconds, pool=3):
+    """The serving workload: 32 streams (346x260 or 1280x720, Poisson event
+    rates 0.5-10 Mev/s, slice windows 1-20 ms, D = 128, r = 5/3, BF16
+    perceptron 256-256-2) replayed in real time for `seconds`: each stream's
+    thread submits a slice every window (cycling over `pool` pre-generated
+    slices) and polls its previous one.  Latency is measured by the server
+    from submit to completion; flows/s is completed flows over the span from
+    the first submit to the last completion."""
+    import threading
+    from paper_2504_19417_amd import synth
+    w = synth.workloads()["slice1m"]
+    specs = synth.serving_streams()
+    slices = [synth.stream_slices(sp, pool) for sp in specs]
+    A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
+    mlp = synth.init_mlp(w.d, w.hidden)
+    per = [max(len(e) for e, _, _ in sl) for sl in slices]
+    srv = vk.Server(1280, 720, w.rx, w.ry, w.rt, A, 20, int(sum(per)), "fp16",
+                    hbm_budget_bytes=96 << 30, max_streams=len(specs), depth=4)
+    srv.set_mlp(*mlp)
+    sids = [srv.open_stream(sp.width, sp.height, sp.window_ms, n) for sp, n in zip(specs, per)]
+    # warm-up: one slice of every stream
+    for sid, sl in zip(sids, slices):
+        ev, t0, T = sl[0]
+        rc, _ = srv.poll(srv.submit(sid, ev, t0, T))
+        if rc != vk.VECKM_OK:
+            raise RuntimeError("serving warm-up failed: %d" % rc)
+    srv.stats(reset=True)
+    errors = []
+    start = time.perf_counter() + 0.05
+
+    def feed(i):
+        sp, sid, sl = specs[i], sids[i], slices[i]
+        prev, k = None, 0
+        rng = np.random.Generator(np.random.PCG64(77 + i))
+        t_next = start + rng.uniform(0.0, sp.window_ms * 1e-3)  # random phase
+        while t_next < start + seconds:
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ev, t0, T = sl[k % len(sl)]
+            try:
+                ticket = srv.submit(sid, ev, t0, T)
+            except vk.VeckmError as e:
+                errors.append(e.code)
+                break
+            if prev is not None:
+                rc, _ = srv.poll(prev)
+                if rc != vk.VECKM_OK:
+                    errors.append(rc)
+            prev, k = ticket, k + 1
+            t_next += sp.window_ms * 1e-3
+        if prev is not None:
+            rc, _ = srv.poll(prev)
+            if rc != vk.VECKM_OK:
+                errors.append(rc)
+
+    th = [threading.Thread(target=feed, args=(i,)) for i in range(len(specs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    st = srv.stats()
+    for sid in sids:
+        srv.close_stream(sid)
+    srv.close()
+    if errors:
+        raise RuntimeError("serving errors: %s" % sorted(set(errors)))
+    return {"streams": len(specs), "offered_mev_s": round(sum(sp.rate_mev_s for sp in specs), 1),
+            "seconds": seconds, "slices": st["slices"], "batches": st["batches"],
+            "flows_per_s": st["flows"] / st["busy_s"] if st["busy_s"] > 0 else None,
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "max_ms": round(st["max_ms"], 3),
+            "latency": "submit to completion (host copies and device work included)",
+            "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation"}
+
+
 KERNEL_SOURCES = {  # short kernel name -> source file it is built from
     "k_encode": "paper_2504_19417_amd/csrc/kernels_encode.hip",
     "k_mlp_f32": "paper_2504_19417_amd/csrc/kernels_mlp.hip",
@@ -211,6 +287,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
+                    help="real-time replay of the 32-stream serving workload (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB on the device (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -272,6 +350,7 @@ def main():
 
     err32 = sampled_error(oracle, w, ev, A, mlp, res["fp32"]["flows"])
     err16 = sampled_error(oracle, w, ev, A, mlp, res["fp16"]["flows"])
+    serving = serving_run(vk, args.serving_seconds) if args.serving_seconds > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, w, ev, A, mlp, args.cpu_seconds)
 
     def lat(r):
@@ -307,6 +386,7 @@ def main():
         },
         "rows": rows,
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
         "paper_context_flows_per_s": {"rtx3070": 4e6, "rtx_a5000": 6e6},
     }

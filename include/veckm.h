@@ -212,6 +212,92 @@ int veckm_profile_read(veckm_ctx* ctx, double* ms, int64_t* count, int32_t nstag
    voxels) of the last compute call enqueued on this context. */
 int veckm_last_rows(veckm_ctx* ctx, void* stream, int64_t* rows);
 
+/* ---- serving: asynchronous event streams, continuously batched -------------
+
+   A server owns one context (sized by `params`: the largest sensor, bins and
+   batch it will run), a HIP stream of its own, and two native threads: a
+   launcher that packs every waiting slice that fits into one batch call
+   (veckm_flow_batch) as soon as fewer than two batches are on the device, and
+   a completer that waits for each batch, stamps its slices' completion time
+   and wakes the pollers.  Slices that arrive while a batch runs go into the
+   next one, so work from different streams overlaps on the device; a slice's
+   result does not depend on which other slices share its batch (bit-identical
+   to veckm_flow on that slice alone).
+
+   Admission by HBM budget: the server's device memory (context workspaces,
+   phase table, perceptron, batch input/output buffers) must fit in
+   hbm_budget_bytes at create time, and every open stream reserves its share
+   of one batch (W*H*max_bins voxels and max_events events): veckm_stream_open
+   returns VECKM_E_BUDGET when the open streams' shares would exceed the batch
+   capacity, so one waiting slice of every admitted stream always fits into a
+   batch.  Batches take waiting slices in submission order while they fit.
+   Closing a stream releases its share.
+
+   Threading: veckm_submit, veckm_poll, veckm_stream_open/close and
+   veckm_server_stats may be called from any threads concurrently.
+   veckm_server_destroy must not race with other calls on the server. */
+typedef struct veckm_server veckm_server;
+
+/* Creates a server on the current HIP device.  params->max_events,
+   max_voxels and max_slices bound one batch (0 -> derived as for
+   veckm_create); `max_streams` streams may be open at once, each with up to
+   `depth` (1..16) submitted slices not yet polled.  Returns VECKM_E_BUDGET if
+   the server's device memory exceeds hbm_budget_bytes (a positive number),
+   plus the veckm_create errors. */
+int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, int32_t max_streams,
+                        int32_t depth, veckm_server** out);
+
+/* Stops the threads after the batches on the device complete, then frees
+   everything (results not yet polled are dropped). */
+void veckm_server_destroy(veckm_server* server);
+
+/* The perceptron, as veckm_set_mlp; call before the first submit. */
+int veckm_server_set_mlp(veckm_server* server, int32_t hidden, const float* W1, const float* b1,
+                         const float* W2, const float* b2);
+
+/* Opens a stream for slices of a width x height sensor with at most
+   max_bins bins and max_events events each.  *sid receives its id.
+   VECKM_E_RANGE if the sensor, bins or events exceed the server's params,
+   VECKM_E_BUDGET if the open streams' reservations would exceed the batch
+   capacity, VECKM_E_AGAIN if max_streams are open. */
+int veckm_stream_open(veckm_server* server, int32_t width, int32_t height, int32_t max_bins,
+                      int64_t max_events, int32_t* sid);
+
+/* Waits until the stream's submitted slices are complete, drops results not
+   yet polled and releases its reservation. */
+int veckm_stream_close(veckm_server* server, int32_t sid);
+
+/* Submits one slice of stream `sid`: n events (host memory, copied before
+   return, so the caller may reuse the buffer), time window [t0, t0 + nbins).
+   Non-blocking.  *ticket identifies the slice for veckm_poll.  Every event is
+   queried.  VECKM_E_AGAIN if the stream already has `depth` slices not yet
+   polled; VECKM_E_RANGE if n or nbins exceed the stream's limits. */
+int veckm_submit(veckm_server* server, int32_t sid, const veckm_event* events, int64_t n,
+                 int32_t t0, int32_t nbins, uint64_t* ticket);
+
+/* Waits up to timeout_us microseconds (< 0: without limit, 0: do not wait)
+   for the slice `ticket`; when it is complete, copies its n x 2 float32 flows
+   to `flows` (host memory, may be NULL to discard), forgets the ticket and
+   returns the slice's status: VECKM_OK, or VECKM_E_RANGE / VECKM_E_OVERFLOW
+   for a slice whose events broke the conventions (found on the device; the
+   other slices of its batch are unaffected).  VECKM_E_AGAIN if still running,
+   VECKM_E_INVAL for an unknown ticket. */
+int veckm_poll(veckm_server* server, uint64_t ticket, float* flows, int32_t timeout_us);
+
+/* Latency and throughput of the slices completed since the last reset: a
+   slice's latency is the wall-clock time from its veckm_submit call to the
+   completer observing its batch done (host copy of events, device work and
+   the copy of flows back to host included). */
+typedef struct veckm_serving_stats {
+  int64_t slices;      /* completed slices                                    */
+  int64_t flows;       /* their events (one flow per event)                   */
+  int64_t batches;     /* batch calls launched                                */
+  double p50_ms, p99_ms, max_ms;   /* slice latency percentiles               */
+  double busy_s;       /* wall-clock time from the first submit to the last completion */
+} veckm_serving_stats;
+
+int veckm_server_stats(veckm_server* server, veckm_serving_stats* out, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -263,6 +263,40 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
 
 }  // namespace
 
+namespace veckm {
+
+Capacity ctx_capacity(const veckm_ctx* c) {
+  Capacity k;
+  k.events = c->p.max_events;
+  k.voxels = c->w.vmax;
+  k.pairs = c->w.pmax;
+  k.bricks = c->w.bmax;
+  k.slices = c->max_slices;
+  return k;
+}
+
+Capacity slice_need(const veckm_ctx* c, int W, int H, int T, int64_t n) {
+  Capacity k;
+  k.events = n;
+  k.voxels = (int64_t)W * H * T;
+  k.pairs = (int64_t)(W + 1) * H * T;
+  k.bricks = bricks_of(W, H, T, c->et.brick);
+  k.slices = 1;
+  return k;
+}
+
+int ctx_take_err(veckm_ctx* c, int32_t* host, void* stream) {
+  return launch_take_err(c->w, host, stream);
+}
+
+int err_code(int32_t bits) {
+  if (bits & kErrOverflow) return VECKM_E_OVERFLOW;
+  if (bits & (kErrRange | kErrQuery)) return VECKM_E_RANGE;
+  return VECKM_OK;
+}
+
+}  // namespace veckm
+
 extern "C" {
 
 int veckm_params_check(const veckm_params* params) {
@@ -550,9 +584,7 @@ int veckm_status(veckm_ctx* ctx, void* stream) {
   int32_t bits = 0;
   if (hipMemcpy(&bits, ctx->w.err, 4, hipMemcpyDeviceToHost) != hipSuccess) return VECKM_E_HIP;
   if (bits && hipMemset(ctx->w.err, 0, 4) != hipSuccess) return VECKM_E_HIP;
-  if (bits & kErrOverflow) return VECKM_E_OVERFLOW;
-  if (bits & (kErrRange | kErrQuery)) return VECKM_E_RANGE;
-  return VECKM_OK;
+  return err_code(bits);
 }
 
 }  // extern "C"

@@ -278,6 +278,14 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
+int launch_take_err(const Workspace& w, int32_t* host, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(host, w.err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return VECKM_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, w.err, (int64_t)1, 0);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
 int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream) {
   if (bt.m <= 0) return VECKM_OK;
   hipLaunchKernelGGL(k_expand_emb, dim3(blocks_for((int64_t)bt.m * 64, 256)), dim3(256), 0,

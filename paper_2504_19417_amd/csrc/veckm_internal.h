@@ -144,5 +144,18 @@ int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, vo
 int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int num_cus,
                void* stream);
 int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream);
+// Copies the device error bits to `host` (pinned) and clears them, in stream order.
+int launch_take_err(const Workspace& w, int32_t* host, void* stream);
+
+// ------------------------------------------------- context hooks for the server
+// What one call can hold, and what one slice needs of it.
+struct Capacity {
+  int64_t events = 0, voxels = 0, pairs = 0, bricks = 0, slices = 0;
+};
+Capacity ctx_capacity(const veckm_ctx* c);
+Capacity slice_need(const veckm_ctx* c, int W, int H, int T, int64_t n);
+int ctx_take_err(veckm_ctx* c, int32_t* host, void* stream);
+// VECKM_OK, VECKM_E_OVERFLOW or VECKM_E_RANGE for a set of device error bits.
+int err_code(int32_t bits);
 
 }  // namespace veckm

@@ -99,6 +99,42 @@ def workloads() -> dict:
     return w
 
 
+@dataclass
+class StreamSpec:
+    """One event stream of the serving workload: a sensor, a Poisson event
+    rate and a slice window (the stream closes a slice every `window_ms`)."""
+    width: int
+    height: int
+    rate_mev_s: float
+    window_ms: int
+    seed: int
+
+
+def serving_streams(count: int = 32, seed: int = 1005):
+    """The serving workload: `count` streams, sensors 346x260 or 1280x720 by
+    coin, rates U[0.5, 10] Mev/s, slice windows U{1..20} ms."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        W, H = (346, 260) if rng.integers(0, 2) == 0 else (1280, 720)
+        out.append(StreamSpec(W, H, float(rng.uniform(0.5, 10.0)), int(rng.integers(1, 21)),
+                              seed=3000 + i))
+    return out
+
+
+def stream_slices(spec: StreamSpec, count: int):
+    """`count` consecutive slices of a stream: Poisson(rate x window) events
+    each over `window_ms` one-ms bins, from the moving-edge generator."""
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    out = []
+    for k in range(count):
+        n = max(1, int(rng.poisson(spec.rate_mev_s * 1e3 * spec.window_ms)))
+        sl = SliceSpec(spec.width, spec.height, spec.window_ms, n, 16,
+                       t_base=1_000_000 + k * spec.window_ms, seed=spec.seed * 100 + k)
+        out.append(make_slice(sl))
+    return out
+
+
 def _edge_events(rng, W, H, T, count, E):
     """Events of E moving edges, ``count`` in total, as float positions."""
     theta = rng.uniform(0.0, math.pi, E)

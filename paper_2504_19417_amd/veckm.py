@@ -62,6 +62,14 @@ class veckm_slice(ctypes.Structure):
     ]
 
 
+class veckm_serving_stats(ctypes.Structure):
+    _fields_ = [
+        ("slices", ctypes.c_int64), ("flows", ctypes.c_int64), ("batches", ctypes.c_int64),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+        ("busy_s", ctypes.c_double),
+    ]
+
+
 class VeckmError(RuntimeError):
     def __init__(self, code, where=""):
         self.code = code
@@ -90,6 +98,17 @@ _sig = {
     "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
+    "veckm_server_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.c_int64,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "veckm_server_destroy": (None, [_P]),
+    "veckm_server_set_mlp": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "veckm_stream_open": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    "veckm_stream_close": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "veckm_submit": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "veckm_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_int32]),
+    "veckm_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(veckm_serving_stats), ctypes.c_int32]),
     "veckm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "veckm_profile_read": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "veckm_last_rows": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -327,3 +346,125 @@ class Context:
 
     def last_rows(self, stream=None):
         return veckm_last_rows(self.handle, self._stream(stream))
+
+
+# ---------------------------------------------------------------- serving
+
+
+def veckm_server_create(params, hbm_budget_bytes, max_streams, depth):
+    h = _P()
+    rc = _lib.veckm_server_create(ctypes.byref(params), int(hbm_budget_bytes), int(max_streams),
+                                  int(depth), ctypes.byref(h))
+    if rc:
+        raise VeckmError(rc, "veckm_server_create")
+    return h
+
+
+def veckm_server_destroy(server):
+    _lib.veckm_server_destroy(server)
+
+
+def veckm_server_set_mlp(server, hidden, W1, b1, W2, b2):
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in (W1, b1, W2, b2)]
+    return _lib.veckm_server_set_mlp(server, int(hidden), *[a.ctypes.data for a in arrs])
+
+
+def veckm_stream_open(server, width, height, max_bins, max_events):
+    """(code, sid)."""
+    sid = ctypes.c_int32(-1)
+    rc = _lib.veckm_stream_open(server, int(width), int(height), int(max_bins), int(max_events),
+                                ctypes.byref(sid))
+    return rc, sid.value
+
+
+def veckm_stream_close(server, sid):
+    return _lib.veckm_stream_close(server, int(sid))
+
+
+def veckm_submit(server, sid, events, t0, nbins):
+    """events: host int32 [n, 4] (C-contiguous).  (code, ticket)."""
+    ev = np.ascontiguousarray(events, dtype=np.int32)
+    if ev.ndim != 2 or ev.shape[1] != 4:
+        raise ValueError("events must be int32 [n, 4]")
+    t = ctypes.c_uint64(0)
+    rc = _lib.veckm_submit(server, int(sid), ev.ctypes.data if len(ev) else None, len(ev),
+                           int(t0), int(nbins), ctypes.byref(t))
+    return rc, t.value
+
+
+def veckm_poll(server, ticket, flows, timeout_us):
+    """flows: host float32 [n, 2] array to fill, or None."""
+    ptr = None
+    if flows is not None:
+        if not (flows.dtype == np.float32 and flows.flags["C_CONTIGUOUS"]):
+            raise ValueError("flows must be a C-contiguous float32 array")
+        ptr = flows.ctypes.data
+    return _lib.veckm_poll(server, ctypes.c_uint64(ticket), ptr, int(timeout_us))
+
+
+def veckm_server_stats(server, reset=False):
+    st = veckm_serving_stats()
+    rc = _lib.veckm_server_stats(server, ctypes.byref(st), int(bool(reset)))
+    if rc:
+        raise VeckmError(rc, "veckm_server_stats")
+    return {f: getattr(st, f) for f, _ in veckm_serving_stats._fields_}
+
+
+class Server:
+    """A veckm server driven with numpy host arrays."""
+
+    def __init__(self, width, height, rx, ry, rt, A, max_bins, max_events, precision="fp16",
+                 hbm_budget_bytes=64 << 30, max_streams=32, depth=4, max_voxels=0):
+        self.params = make_params(width, height, rx, ry, rt, A, max_bins, max_events, precision,
+                                  max_streams, max_voxels)
+        self.handle = veckm_server_create(self.params, hbm_budget_bytes, max_streams, depth)
+        self.sizes = {}
+
+    def close(self):
+        if self.handle:
+            veckm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mlp(self, W1, b1, W2, b2):
+        rc = veckm_server_set_mlp(self.handle, np.asarray(W1).shape[0], W1, b1, W2, b2)
+        if rc:
+            raise VeckmError(rc, "veckm_server_set_mlp")
+
+    def open_stream(self, width, height, max_bins, max_events):
+        rc, sid = veckm_stream_open(self.handle, width, height, max_bins, max_events)
+        if rc:
+            raise VeckmError(rc, "veckm_stream_open")
+        return sid
+
+    def close_stream(self, sid):
+        rc = veckm_stream_close(self.handle, sid)
+        if rc:
+            raise VeckmError(rc, "veckm_stream_close")
+
+    def submit(self, sid, events, t0, nbins):
+        rc, ticket = veckm_submit(self.handle, sid, events, t0, nbins)
+        if rc:
+            raise VeckmError(rc, "veckm_submit")
+        self.sizes[ticket] = len(events)
+        return ticket
+
+    def poll(self, ticket, timeout_us=-1):
+        """(code, flows or None): code VECKM_E_AGAIN while the slice runs."""
+        n = self.sizes.get(ticket)
+        if n is None:
+            return VECKM_E_INVAL, None
+        out = np.empty((n, 2), dtype=np.float32)
+        rc = veckm_poll(self.handle, ticket, out, timeout_us)
+        if rc == VECKM_E_AGAIN:
+            return rc, None
+        del self.sizes[ticket]
+        return rc, (out if rc == VECKM_OK else None)
+
+    def stats(self, reset=False):
+        return veckm_server_stats(self.handle, reset)

@@ -24,7 +24,10 @@ def _declared_functions():
 def test_header_declares_api():
     names = _declared_functions()
     for required in ["veckm_create", "veckm_destroy", "veckm_encode", "veckm_flow",
-                     "veckm_set_mlp", "veckm_status", "veckm_strerror"]:
+                     "veckm_set_mlp", "veckm_status", "veckm_strerror", "veckm_encode_batch",
+                     "veckm_flow_batch", "veckm_server_create", "veckm_server_destroy",
+                     "veckm_server_set_mlp", "veckm_stream_open", "veckm_stream_close",
+                     "veckm_submit", "veckm_poll", "veckm_server_stats"]:
         assert required in names
 
 
@@ -132,3 +135,29 @@ def test_create_rejects_bad_params_before_device():
     with pytest.raises(veckm.VeckmError) as e:
         veckm.veckm_create(_params(rx=99))
     assert e.value.code == veckm.VECKM_E_INVAL
+
+
+def test_server_create_checks_before_device():
+    """Argument and HBM-budget checks happen on the host, before any device
+    call; without a device the server reports VECKM_E_NODEVICE."""
+    p = _params()
+    with pytest.raises(veckm.VeckmError) as e:
+        veckm.veckm_server_create(p, 1 << 20, 4, 2)  # 1 MiB cannot hold the workspaces
+    assert e.value.code == veckm.VECKM_E_BUDGET
+    for streams, depth, budget in ((0, 2, 1 << 40), (4, 0, 1 << 40), (4, 17, 1 << 40), (4, 2, 0)):
+        with pytest.raises(veckm.VeckmError) as e:
+            veckm.veckm_server_create(p, budget, streams, depth)
+        assert e.value.code == veckm.VECKM_E_INVAL
+    import torch
+    if torch.cuda.is_available():
+        return
+    with pytest.raises(veckm.VeckmError) as e:
+        veckm.veckm_server_create(p, 1 << 40, 4, 2)
+    assert e.value.code == veckm.VECKM_E_NODEVICE
+
+
+def test_server_null_handles():
+    assert veckm._lib.veckm_stream_close(None, 0) == veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_poll(None, 1, None, 0) == veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_server_set_mlp(None, 64, None, None, None, None) == veckm.VECKM_E_INVAL
+    veckm._lib.veckm_server_destroy(None)
