@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "slices.h"
+#include "sync.h"
 #include "veckm_internal.h"
 
 namespace veckm {
@@ -62,17 +63,27 @@ __device__ inline half8 as_half8(uint4 u) {
 
 // (p.lo + q.hi, p.hi + q.lo) and (p.lo - q.hi, p.hi - q.lo) on packed fp16:
 // the -o run comes out of the pair layout half-swapped, and the swap is free
-// as an operand select.  Exact for the integer counts used here (<= 2048).
+// (the compiler folds it into the packed add's operand selects).  Exact for
+// the integer counts used here (<= 2048).
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
 __device__ inline uint32_t pk_sum_swapped(uint32_t p, uint32_t q) {
-  uint32_t r;
-  asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0]" : "=v"(r) : "v"(p), "v"(q));
-  return r;
+  half2v a, b;
+  __builtin_memcpy(&a, &p, 4);
+  __builtin_memcpy(&b, &q, 4);
+  const half2v r = a + __builtin_shufflevector(b, b, 1, 0);
+  uint32_t o;
+  __builtin_memcpy(&o, &r, 4);
+  return o;
 }
 __device__ inline uint32_t pk_diff_swapped(uint32_t p, uint32_t q) {
-  uint32_t r;
-  asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[0,1]"
-      : "=v"(r) : "v"(p), "v"(q));
-  return r;
+  half2v a, b;
+  __builtin_memcpy(&a, &p, 4);
+  __builtin_memcpy(&b, &q, 4);
+  const half2v r = a - __builtin_shufflevector(b, b, 1, 0);
+  uint32_t o;
+  __builtin_memcpy(&o, &r, 4);
+  return o;
 }
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -80,19 +91,6 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
-}
-
-// Copies one k-step slab of the phase table from global memory straight into
-// LDS (gfx950 global_load_lds_dwordx4: no registers, completion tracked by
-// vmcnt).  Each wave moves 1 KB runs; the LDS base of a run is wave-uniform.
-template <int SLAB_U4>
-__device__ inline void issue_slab(const uint4* src, int, uint4* dst, int wid, int lane) {
-#pragma unroll
-  for (int u = 0; u < (SLAB_U4 + 255) / 256; ++u) {
-    const int base = u * 256 + wid * 64;
-    if (SLAB_U4 % 256 == 0 || base < SLAB_U4)
-      __builtin_amdgcn_global_load_lds(src + base + lane, dst + base, 16, 0, 0);
-  }
 }
 
 // s_waitcnt immediate (gfx9 encoding) waiting until at most n vector memory
@@ -108,20 +106,126 @@ struct EncShape {
   static constexpr int MT = NT >= 8 ? 4 : 2;    // 16-row tiles per wave
   static constexpr int CH = WM * MT * 16;       // rows per chunk
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-slot slab
-  static constexpr int PFW = SLAB_U4 / (NW * 64);  // loads per wave per slab
+  static constexpr int PFW = SLAB_U4 / (NW * 64);  // copies per wave per slab
   static constexpr bool EVEN = SLAB_U4 % (NW * 64) == 0;
 };
 
-// Copies one k-step slab of the phase table from global memory straight into
-// LDS (gfx950 global_load_lds_dwordx4: no registers, completion tracked by
-// vmcnt).  Each wave moves 1 KB runs; the LDS base of a run is wave-uniform.
+// Starts the copy of one k-step slab of the phase table from global memory
+// straight into LDS (no registers; completion tracked by vmcnt).  Each wave
+// moves 1 KB pieces.
 template <int SLAB_U4, int NW>
 __device__ inline void issue_slab(const uint4* src, uint4* dst, int wid, int lane) {
 #pragma unroll
   for (int u = 0; u < (SLAB_U4 + NW * 64 - 1) / (NW * 64); ++u) {
     const int base = u * NW * 64 + wid * 64;
     if (SLAB_U4 % (NW * 64) == 0 || base < SLAB_U4)
-      __builtin_amdgcn_global_load_lds(src + base + lane, dst + base, 16, 0, 0);
+      copy_to_lds16(src + base + lane, lds_offset(dst + base));
+  }
+}
+
+// The k-steps of one chunk for a wave that holds MTV valid 16-row tiles
+// (0 <= MTV <= MT; no per-tile branches inside).  Every wave runs it: a wave
+// without rows still moves its share of each slab and meets every barrier.
+// On entry the first slab is in LDS and the next NBUF - 2 are in flight.
+template <int NA, int NT, int NBUF, int MTV>
+__device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab, const int32_t* runs_l,
+                                    const uint16_t* wts_l, const uint32_t* vol2,
+                                    const int (&rb)[EncShape<NA, NT>::MT],
+                                    floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                    floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                    floatx4 (&accN)[EncShape<NA, NT>::MT], int wn, int wid,
+                                    int lane) {
+  using S = EncShape<NA, NT>;
+  constexpr int NW = S::NW, NTW = S::NTW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
+  constexpr int AHEAD = NBUF - 1;
+  for (int ks = 0; ks < nsteps; ++ks) {
+    const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
+    if constexpr (MTV > 0) {
+      // A operands: pair sums and differences of counts at +o / -o.  The
+      // lane's 8 slots are two runs of 4 consecutive dx; a +o run starts at
+      // voxel base + off (ascending), its -o partner ends at base - off
+      // (descending), read as dwords and half-swapped.
+      const int g = lane >> 4;
+      const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
+      const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
+      const uint4* sb = slab + buf * SLAB_U4;
+      half8 aS[MTV], aD[MTV];
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt) {
+        const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
+        const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
+        const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
+        const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
+        const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
+        const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
+        uint4 s4, d4;
+        s4.x = pk_sum_swapped(P[0], Qr[0]);
+        s4.y = pk_sum_swapped(P[1], Qr[1]);
+        s4.z = pk_sum_swapped(P[2], Qr[2]);
+        s4.w = pk_sum_swapped(P[3], Qr[3]);
+        d4.x = pk_diff_swapped(P[0], Qr[0]);
+        d4.y = pk_diff_swapped(P[1], Qr[1]);
+        d4.z = pk_diff_swapped(P[2], Qr[2]);
+        d4.w = pk_diff_swapped(P[3], Qr[3]);
+        aS[mt] = as_half8(s4);
+        aD[mt] = as_half8(d4);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NTW; ++nt) {
+        half8 bf[NA];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) bf[q] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
+#pragma unroll
+        for (int mt = 0; mt < MTV; ++mt) {
+          if constexpr (NA == 4) {
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2], accI[mt][nt], 0, 0, 0);
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3], accI[mt][nt], 0, 0, 0);
+          } else {
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1], accI[mt][nt], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt)
+        accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
+    }
+    // every LDS read of this step is issued: start the slab AHEAD steps out
+    // (its buffer was last read in step ks - 1, before the last barrier),
+    // then make sure the slab of step ks + 1 has landed
+    const bool more = ks + AHEAD < nsteps;
+    if (more)
+      issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
+                              slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
+    if (NBUF == 3 && more)
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
+    else
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    lds_barrier();
+  }
+}
+
+// Dispatches on the wave's number of valid row tiles (wave-uniform).
+template <int NA, int NT, int NBUF, int M>
+__device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, uint4* slab,
+                                      const int32_t* runs_l, const uint16_t* wts_l,
+                                      const uint32_t* vol2, const int (&rb)[EncShape<NA, NT>::MT],
+                                      floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                      floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                      floatx4 (&accN)[EncShape<NA, NT>::MT], int wn, int wid,
+                                      int lane) {
+  if constexpr (M == 0) {
+    chunk_ksteps<NA, NT, NBUF, 0>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, accN,
+                                  wn, wid, lane);
+  } else {
+    if (mtv == M)
+      chunk_ksteps<NA, NT, NBUF, M>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, accN,
+                                    wn, wid, lane);
+    else
+      chunk_ksteps_n<NA, NT, NBUF, M - 1>(mtv, nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR,
+                                          accI, accN, wn, wid, lane);
   }
 }
 
@@ -158,7 +262,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
       const int it = atomicAdd(&a.plan[1], 1);
       item[0] = it < a.plan[2] ? a.order[it] : -1;
     }
-    __syncthreads();
+    lds_barrier();
     const int bid = item[0];
     if (bid < 0) break;
     const int nq = a.brick_nq[bid];
@@ -182,7 +286,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         const uint32_t* src =
             in ? a.pairs + sl.pair_off + ((int64_t)t * sl.H + y) * (sl.W + 1) + (x + 1)
                : a.zeros + lane;
-        if (lane < a.SX) __builtin_amdgcn_global_load_lds(src, vol2 + rr * a.SX, 4, 0, 0);
+        if (lane < a.SX) copy_to_lds4(src, lds_offset(vol2 + rr * a.SX));
         sy += NW;
         while (sy >= a.SY) {
           sy -= a.SY;
@@ -210,7 +314,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
       else
         __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-      __syncthreads();
+      lds_barrier();
 
       // tiles are dealt round-robin over the row waves, so a short chunk
       // spreads evenly and fully padded tiles are skipped
@@ -222,6 +326,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         if (q < ntiles) mtv = mt + 1;
         rb[mt] = rowbase[q * 16 + (lane & 15)];
       }
+      mtv = __builtin_amdgcn_readfirstlane(mtv);
 
       floatx4 accR[MT][NTW], accI[MT][NTW], accN[MT];
 #pragma unroll
@@ -233,78 +338,8 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
           accI[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
       }
-
-      for (int ks = 0; ks < a.nsteps; ++ks) {
-        const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
-        // A operands: pair sums and differences of counts at +o / -o.  The
-        // lane's 8 slots are two runs of 4 consecutive dx; a +o run starts at
-        // voxel base + off (ascending), its -o partner ends at base - off
-        // (descending), read as dwords and half-swapped.
-        const int g = lane >> 4;
-        const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
-        half8 aS[MT], aD[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          if (mt < mtv) {
-            const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
-            const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
-            const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
-            const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
-            const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
-            const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
-            uint4 s4, d4;
-            s4.x = pk_sum_swapped(P[0], Qr[0]);
-            s4.y = pk_sum_swapped(P[1], Qr[1]);
-            s4.z = pk_sum_swapped(P[2], Qr[2]);
-            s4.w = pk_sum_swapped(P[3], Qr[3]);
-            d4.x = pk_diff_swapped(P[0], Qr[0]);
-            d4.y = pk_diff_swapped(P[1], Qr[1]);
-            d4.z = pk_diff_swapped(P[2], Qr[2]);
-            d4.w = pk_diff_swapped(P[3], Qr[3]);
-            aS[mt] = as_half8(s4);
-            aD[mt] = as_half8(d4);
-          }
-        }
-        const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
-        const uint4* sb = slab + buf * SLAB_U4;
-#pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) {
-          const int ntg = wn * NTW + nt;
-          half8 bf[NA];
-#pragma unroll
-          for (int q = 0; q < NA; ++q) bf[q] = as_half8(sb[(q * NT + ntg) * 64 + lane]);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            if (mt < mtv) {
-              if constexpr (NA == 4) {
-                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
-                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2], accI[mt][nt], 0, 0, 0);
-                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1], accR[mt][nt], 0, 0, 0);
-                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3], accI[mt][nt], 0, 0, 0);
-              } else {
-                accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
-                accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1], accI[mt][nt], 0, 0, 0);
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          if (mt < mtv)
-            accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
-        // every LDS read of this step is issued: start the slab AHEAD steps
-        // out (its buffer was last read in step ks - 1), then make sure the
-        // slab of step ks + 1 has landed
-        const bool more = ks + AHEAD < a.nsteps;
-        if (more)
-          issue_slab<SLAB_U4, NW>(a.frag + (size_t)(ks + AHEAD) * SLAB_U4,
-                                  slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
-        if (NBUF == 3 && more)
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
-        else
-          __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        __syncthreads();
-      }
+      chunk_ksteps_n<NA, NT, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb, accR,
+                                       accI, accN, wn, wid, lane);
 
       // ---- normalise by the neighbour count and write the rows
 #pragma unroll
@@ -342,7 +377,7 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 

@@ -20,6 +20,7 @@
 // needed between the encoder and the perceptron.
 #include <hip/hip_runtime.h>
 
+#include "sync.h"
 #include "veckm_internal.h"
 
 namespace veckm {
@@ -102,7 +103,7 @@ __device__ inline void mlp_epilogue(const MlpArgs& a, const Layer2<NTH>& l2, flo
         red[wid][r][1] = p1[mt][i];
       }
     }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x < 128) {
     const int r = threadIdx.x >> 1, o = threadIdx.x & 1;
     const int row = tile * 64 + r;
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs a) {
     uint4* cur = tbuf + (it & 1) * 64 * CPR;
     const int next = tile + gridDim.x;
     __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
-    __syncthreads();  // tile `tile` is in `cur`; the other buffer is free
+    lds_barrier();  // tile `tile` is in `cur`; the other buffer is free
     if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
     floatx4 acc[4][NTH];
 #pragma unroll
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16_res(MlpArgs a) {
     uint4* cur = tbuf + (it & 1) * 64 * CPR;
     const int next = tile + gridDim.x;
     __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
-    __syncthreads();
+    lds_barrier();
     if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
     floatx4 acc[4][NTH];
 #pragma unroll
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(MlpArgs a) {
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
     }
     mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(256) void k_mlp_f32_any(MlpArgs a) {
         }
     }
     mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
