@@ -4,6 +4,8 @@
 // host fallback.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <limits>
@@ -118,7 +120,7 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   bytes += (int64_t)kp * p->d * na * 2 + kp * 3;  // phase table, run offsets, weights
   bytes += 64 * 4 + 4 + 64 * 4;                   // plan, err, zero page
   bytes += (int64_t)kRing * slices_of(p) * (int64_t)sizeof(SliceDesc);  // slice tables
-  bytes += (int64_t)hidden * (2 * p->d) * 6 + hidden * 12 + 8;          // perceptron
+  bytes += (int64_t)hidden * (2 * p->d) * 10 + hidden * 12 + 8;  // perceptron (fp32, bf16, fp16 hi/lo W1)
   return bytes;
 }
 
@@ -240,7 +242,11 @@ struct StageTimer {
 int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* queries, float* emb,
         float* flow, void* stream) {
   if (bt.m == 0) return VECKM_OK;
-  const bool bf16 = flow && c->p.precision == VECKM_FP16;
+  // rows the encoder hands to the perceptron (encodings handed out are fp32)
+  const int rows = !flow                             ? kRowsF32
+                   : c->p.precision == VECKM_FP16     ? kRowsBF16
+                   : mlp_rows_split(c->p.d, c->mw.hidden) ? kRowsSplit16
+                                                      : kRowsF32;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
     const int rc = launch_prepare(bt, c->w, ev, queries, c->et, stream);
@@ -248,12 +254,13 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   }
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
-    const int rc = launch_encode(bt, c->w, c->et, bf16, c->num_cus, stream);
+    const int rc = launch_encode(bt, c->w, c->et, rows == kRowsBF16 ? kRowsBF16 : kRowsF32,
+                                 c->num_cus, stream);
     if (rc) return rc;
   }
   if (flow) {
     StageTimer t(c, VECKM_STAGE_MLP, stream);
-    const int rc = launch_mlp(c->w, c->mw, c->p.d, bf16, c->num_cus, stream);
+    const int rc = launch_mlp(c->w, c->mw, c->p.d, rows, c->num_cus, stream);
     if (rc) return rc;
   }
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
@@ -462,18 +469,34 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
   ctx->mlp_allocs.clear();
   ctx->mw = MlpWeights{};
   float *dW1 = nullptr, *db1 = nullptr, *dW2 = nullptr, *db2 = nullptr;
-  uint16_t* dW1b = nullptr;
+  uint16_t *dW1b = nullptr, *dW1h = nullptr, *dW1l = nullptr;
   int rc = VECKM_OK;
   rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1, (size_t)hidden * K2);
   rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1b, (size_t)hidden * K2);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1h, (size_t)hidden * K2);
+  rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW1l, (size_t)hidden * K2);
   rc = rc ? rc : dalloc(ctx->mlp_allocs, &db1, (size_t)hidden);
   rc = rc ? rc : dalloc(ctx->mlp_allocs, &dW2, (size_t)2 * hidden);
   rc = rc ? rc : dalloc(ctx->mlp_allocs, &db2, 2);
   if (rc) return rc;
-  std::vector<uint16_t> w1b((size_t)hidden * K2);
+  std::vector<uint16_t> w1b((size_t)hidden * K2), w1h(w1b.size()), w1l(w1b.size());
   for (size_t i = 0; i < w1b.size(); ++i) w1b[i] = bf16_bits_rne(W1[i]);
+  // fp16 hi/lo pair of W1 * 2^s, with s putting max |W1| * 2^s in [1, 2) so
+  // that the lo parts of all but the smallest weights stay normal
+  double wmax = 0.0;
+  for (size_t i = 0; i < w1b.size(); ++i) wmax = std::max(wmax, std::fabs((double)W1[i]));
+  int e = 0;
+  if (wmax > 0.0) std::frexp(wmax, &e);  // wmax = f 2^e, f in [0.5, 1)
+  const int shift = wmax > 0.0 ? 1 - e : 0;
+  for (size_t i = 0; i < w1b.size(); ++i) {
+    const double v = std::ldexp((double)W1[i], shift);
+    w1h[i] = fp16_bits_rne(v);
+    w1l[i] = fp16_bits_rne(v - fp16_to_double(w1h[i]));
+  }
   if (hipMemcpy(dW1, W1, (size_t)hidden * K2 * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(dW1b, w1b.data(), w1b.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dW1h, w1h.data(), w1h.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dW1l, w1l.data(), w1l.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(db1, b1, (size_t)hidden * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(dW2, W2, (size_t)2 * hidden * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(db2, b2, 8, hipMemcpyHostToDevice) != hipSuccess)
@@ -481,6 +504,9 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
   ctx->mw.hidden = hidden;
   ctx->mw.W1 = dW1;
   ctx->mw.W1b = dW1b;
+  ctx->mw.W1h = dW1h;
+  ctx->mw.W1l = dW1l;
+  ctx->mw.unscale = (float)std::ldexp(1.0, -shift);
   ctx->mw.b1 = db1;
   ctx->mw.W2 = dW2;
   ctx->mw.b2 = db2;

@@ -13,16 +13,19 @@
 // dense contractions of a [rows x |H|] matrix of small integers with a fixed
 // [|H| x D] table, which is what the matrix cores do: counts are exact in
 // fp16, the table is one fp16 term (VECKM_FP16) or an fp16 hi/lo pair
-// (VECKM_FP32), products are exact and every sum is fp32.  N(v) comes from
-// the same A operand against a weight column (1 per offset, 1/2 for the
-// centre, 0 for padding), also exact.
+// (VECKM_FP32), products are exact and every sum is fp32.  N(v) is the same
+// pair sums against slot weights (1 per offset, 1/2 for the centre, 0 for
+// padding), summed exactly in fp32 on the vector ALU.
 //
-// Work decomposition: the (x, y, t) grid is cut into bricks.  A persistent
-// block takes whole bricks from a device counter, stages the brick's counts
-// plus the window halo into LDS as fp16, and runs its query voxels in chunks
-// of up to 128/256 rows.  The table streams through LDS one 32-offset slab
-// at a time (double buffered), shared by the 4 waves of the block.  Each
-// wave owns 64 rows (4 MFMA row tiles) and up to 64 frequencies.
+// Work decomposition: the (x, y, t) grid of every slice is cut into bricks,
+// and the bricks of all slices of a call form one work list.  A persistent
+// block of 4 waves (one per SIMD) takes whole bricks from a device counter,
+// copies the brick's counts plus the window halo from the pair grid into
+// LDS, and runs the brick's query voxels in chunks of 256 rows (128 at
+// D = 256).  The table streams through LDS one 32-offset slab per MFMA
+// k-step, NBUF slabs deep, shared by the waves.  Each wave owns 64 rows
+// (4 row tiles) and every frequency (half of them at D = 256); its count
+// words for the next k-step are fetched while the current one multiplies.
 #include <hip/hip_runtime.h>
 
 #include "slices.h"
@@ -97,13 +100,19 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 // operations are outstanding; expcnt and lgkmcnt are left unconstrained.
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
+// Waves per block and the most 16-frequency tiles one wave holds.
+constexpr int kEncWaves = 8;
+constexpr int kEncMaxNtw = 4;
+// Fetch the next k-step's count words while the current step multiplies.
+constexpr bool kEncPrefetch = false;
+
 template <int NA, int NT>
 struct EncShape {
-  static constexpr int NW = 8;                  // waves per block (2 per SIMD)
-  static constexpr int NTW = NT < 4 ? NT : 4;   // 16-frequency tiles per wave
-  static constexpr int WN = NT / NTW;           // waves across frequencies
+  static constexpr int NW = kEncWaves;          // waves per block
+  static constexpr int NTW = NT < kEncMaxNtw ? NT : kEncMaxNtw;  // frequency tiles per wave
+  static constexpr int WN = NT / NTW;           // waves across frequencies (1, or 2 at D = 256)
   static constexpr int WM = NW / WN;            // waves across rows
-  static constexpr int MT = NT >= 8 ? 4 : 2;    // 16-row tiles per wave
+  static constexpr int MT = 4;                  // 16-row tiles per wave
   static constexpr int CH = WM * MT * 16;       // rows per chunk
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-slot slab
   static constexpr int PFW = SLAB_U4 / (NW * 64);  // copies per wave per slab
@@ -123,74 +132,109 @@ __device__ inline void issue_slab(const uint4* src, uint4* dst, int wid, int lan
   }
 }
 
+// The count words of one k-step for MTV row tiles: for each tile, the lane's
+// two +o runs (4 consecutive voxels each, two aligned pair dwords per run)
+// and their -o partners.  Only the brick's count box and the run offsets are
+// read, both fixed for the brick, so the next step's words can be fetched
+// while the current step multiplies.
+template <int MTV>
+struct CountWords {
+  uint32_t P[MTV > 0 ? MTV : 1][4], Q[MTV > 0 ? MTV : 1][4];
+  __device__ inline void fetch(const int32_t* runs_l, const uint32_t* vol2, const int* rb, int ks,
+                               int g) {
+    const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
+#pragma unroll
+    for (int mt = 0; mt < MTV; ++mt) {
+      const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
+      const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
+      const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
+      const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
+      P[mt][0] = p0[0];
+      P[mt][1] = p0[2];
+      P[mt][2] = p1[0];
+      P[mt][3] = p1[2];
+      Q[mt][0] = q0[2];
+      Q[mt][1] = q0[0];
+      Q[mt][2] = q1[2];
+      Q[mt][3] = q1[0];
+    }
+  }
+};
+
 // The k-steps of one chunk for a wave that holds MTV valid 16-row tiles
 // (0 <= MTV <= MT; no per-tile branches inside).  Every wave runs it: a wave
 // without rows still moves its share of each slab and meets every barrier.
 // On entry the first slab is in LDS and the next NBUF - 2 are in flight.
+//
+// The table is the MFMA A operand and the counts the B operand, so that the
+// accumulator of a lane holds 4 consecutive frequencies of one row (the
+// lane's row is lane & 15): the count of that row arrives in the same lane
+// and the row is written with 16-byte stores.
 template <int NA, int NT, int NBUF, int MTV>
-__device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab, const int32_t* runs_l,
-                                    const uint16_t* wts_l, const uint32_t* vol2,
-                                    const int (&rb)[EncShape<NA, NT>::MT],
+__device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
+                                    const int32_t* runs_l, const uint16_t* wts_l,
+                                    const uint32_t* vol2, const int (&rb)[EncShape<NA, NT>::MT],
                                     floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
                                     floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                    floatx4 (&accN)[EncShape<NA, NT>::MT], int wn, int wid,
+                                    float (&cnt)[EncShape<NA, NT>::MT], int wn, int wid,
                                     int lane) {
   using S = EncShape<NA, NT>;
   constexpr int NW = S::NW, NTW = S::NTW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
   constexpr int AHEAD = NBUF - 1;
+  const int g = lane >> 4;
+  CountWords<MTV> cw;
+  if constexpr (MTV > 0 && kEncPrefetch) cw.fetch(runs_l, vol2, rb, 0, g);
   for (int ks = 0; ks < nsteps; ++ks) {
     const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
     if constexpr (MTV > 0) {
-      // A operands: pair sums and differences of counts at +o / -o.  The
-      // lane's 8 slots are two runs of 4 consecutive dx; a +o run starts at
-      // voxel base + off (ascending), its -o partner ends at base - off
-      // (descending), read as dwords and half-swapped.
-      const int g = lane >> 4;
-      const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
-      const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
-      const uint4* sb = slab + buf * SLAB_U4;
-      half8 aS[MTV], aD[MTV];
+      if constexpr (!kEncPrefetch) cw.fetch(runs_l, vol2, rb, ks, g);
+      // pair sums and differences of counts at +o / -o: the -o run comes out
+      // of the pair layout descending and half-swapped
+      half8 cS[MTV], cD[MTV];
 #pragma unroll
       for (int mt = 0; mt < MTV; ++mt) {
-        const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
-        const uint32_t* p1 = vol2 + (rb[mt] + ro.y);
-        const uint32_t* q0 = vol2 + (rb[mt] - ro.x - 3);
-        const uint32_t* q1 = vol2 + (rb[mt] - ro.y - 3);
-        const uint32_t P[4] = {p0[0], p0[2], p1[0], p1[2]};
-        const uint32_t Qr[4] = {q0[2], q0[0], q1[2], q1[0]};
         uint4 s4, d4;
-        s4.x = pk_sum_swapped(P[0], Qr[0]);
-        s4.y = pk_sum_swapped(P[1], Qr[1]);
-        s4.z = pk_sum_swapped(P[2], Qr[2]);
-        s4.w = pk_sum_swapped(P[3], Qr[3]);
-        d4.x = pk_diff_swapped(P[0], Qr[0]);
-        d4.y = pk_diff_swapped(P[1], Qr[1]);
-        d4.z = pk_diff_swapped(P[2], Qr[2]);
-        d4.w = pk_diff_swapped(P[3], Qr[3]);
-        aS[mt] = as_half8(s4);
-        aD[mt] = as_half8(d4);
+        s4.x = pk_sum_swapped(cw.P[mt][0], cw.Q[mt][0]);
+        s4.y = pk_sum_swapped(cw.P[mt][1], cw.Q[mt][1]);
+        s4.z = pk_sum_swapped(cw.P[mt][2], cw.Q[mt][2]);
+        s4.w = pk_sum_swapped(cw.P[mt][3], cw.Q[mt][3]);
+        d4.x = pk_diff_swapped(cw.P[mt][0], cw.Q[mt][0]);
+        d4.y = pk_diff_swapped(cw.P[mt][1], cw.Q[mt][1]);
+        d4.z = pk_diff_swapped(cw.P[mt][2], cw.Q[mt][2]);
+        d4.w = pk_diff_swapped(cw.P[mt][3], cw.Q[mt][3]);
+        cS[mt] = as_half8(s4);
+        cD[mt] = as_half8(d4);
       }
+      const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
+      const uint4* sb = slab + buf * SLAB_U4;
+      if (kEncPrefetch && ks + 1 < nsteps) cw.fetch(runs_l, vol2, rb, ks + 1, g);
 #pragma unroll
       for (int nt = 0; nt < NTW; ++nt) {
-        half8 bf[NA];
+        half8 tf[NA];
 #pragma unroll
-        for (int q = 0; q < NA; ++q) bf[q] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
+        for (int q = 0; q < NA; ++q) tf[q] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
 #pragma unroll
         for (int mt = 0; mt < MTV; ++mt) {
           if constexpr (NA == 4) {
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[2], accI[mt][nt], 0, 0, 0);
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[1], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[3], accI[mt][nt], 0, 0, 0);
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[2], cD[mt], accI[mt][nt], 0, 0, 0);
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[3], cD[mt], accI[mt][nt], 0, 0, 0);
           } else {
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bf[0], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aD[mt], bf[1], accI[mt][nt], 0, 0, 0);
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cD[mt], accI[mt][nt], 0, 0, 0);
           }
         }
       }
+      // neighbour count: the slot weights (1, 1/2 for the centre, 0 for
+      // padding) against the pair sums, exact in fp32; the lane covers its 8
+      // slots of the row, the 4 lanes of a row are added after the loop
 #pragma unroll
       for (int mt = 0; mt < MTV; ++mt)
-        accN[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aS[mt], bw, accN[mt], 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          cnt[mt] = __builtin_amdgcn_fdot2(half2v{bw[2 * e], bw[2 * e + 1]},
+                                           half2v{cS[mt][2 * e], cS[mt][2 * e + 1]}, cnt[mt], false);
     }
     // every LDS read of this step is issued: start the slab AHEAD steps out
     // (its buffer was last read in step ks - 1, before the last barrier),
@@ -214,23 +258,25 @@ __device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, ui
                                       const uint32_t* vol2, const int (&rb)[EncShape<NA, NT>::MT],
                                       floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
                                       floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                      floatx4 (&accN)[EncShape<NA, NT>::MT], int wn, int wid,
+                                      float (&cnt)[EncShape<NA, NT>::MT], int wn, int wid,
                                       int lane) {
   if constexpr (M == 0) {
-    chunk_ksteps<NA, NT, NBUF, 0>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, accN,
+    chunk_ksteps<NA, NT, NBUF, 0>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
                                   wn, wid, lane);
   } else {
     if (mtv == M)
-      chunk_ksteps<NA, NT, NBUF, M>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, accN,
+      chunk_ksteps<NA, NT, NBUF, M>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
                                     wn, wid, lane);
     else
       chunk_ksteps_n<NA, NT, NBUF, M - 1>(mtv, nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR,
-                                          accI, accN, wn, wid, lane);
+                                          accI, cnt, wn, wid, lane);
   }
 }
 
-template <int NA, int NT, int NBUF, bool BF16OUT>
-__global__ __launch_bounds__(512) void k_encode(EncArgs a) {
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int NA, int NT, int NBUF, int ROWS>
+__global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
   using S = EncShape<NA, NT>;
   constexpr int NW = S::NW, NTW = S::NTW, WN = S::WN, WM = S::WM, MT = S::MT, CH = S::CH,
                 SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
@@ -328,10 +374,11 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
       }
       mtv = __builtin_amdgcn_readfirstlane(mtv);
 
-      floatx4 accR[MT][NTW], accI[MT][NTW], accN[MT];
+      floatx4 accR[MT][NTW], accI[MT][NTW];
+      float cnt[MT];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        accN[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        cnt[mt] = 0.f;
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
           accR[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -339,40 +386,50 @@ __global__ __launch_bounds__(512) void k_encode(EncArgs a) {
         }
       }
       chunk_ksteps_n<NA, NT, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb, accR,
-                                       accI, accN, wn, wid, lane);
+                                       accI, cnt, wn, wid, lane);
 
-      // ---- normalise by the neighbour count and write the rows
+      // ---- normalise by the neighbour count and write the rows: the lane
+      //      holds frequencies 16 nt + 4 (lane >> 4) + (0..3) of row lane & 15
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         if (mt >= mtv) continue;
-        const int q = mt * WM + wm;
+        const int r = (mt * WM + wm) * 16 + (lane & 15);
+        // the row's count: the partial sums of its 4 lanes (exact integers)
+        float n = cnt[mt];
+        n += __shfl_xor(n, 16);
+        n += __shfl_xor(n, 32);
+        if (r >= nr) continue;
+        const float rc = __builtin_amdgcn_rcpf(n);
+        // x / n: reciprocal estimate plus one residual correction (exact for
+        // x = n, so an all-ones feature still gives exactly 1)
+        auto div = [n, rc](float x) {
+          const float qq = x * rc;
+          return fmaf(fmaf(-qq, n, x), rc, qq);
+        };
+        const int64_t u = (int64_t)(row0 + c0 + r) * (2 * D);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = q * 16 + 4 * (lane >> 4) + i;
-          if (r >= nr) continue;
-          const float cnt = accN[mt][i];
-          const float rc = __builtin_amdgcn_rcpf(cnt);
-          // x / cnt: reciprocal estimate plus one residual correction (exact
-          // for x = cnt, so an all-ones feature still gives exactly 1)
-          auto div = [cnt, rc](float x) {
-            const float qq = x * rc;
-            return fmaf(fmaf(-qq, cnt, x), rc, qq);
-          };
-          const int64_t u = (int64_t)(row0 + c0 + r) * (2 * D);
+        for (int nt = 0; nt < NTW; ++nt) {
+          const int j = (wn * NTW + nt) * 16 + 4 * (lane >> 4);
+          floatx4 re, im;
 #pragma unroll
-          for (int nt = 0; nt < NTW; ++nt) {
-            const int j = (wn * NTW + nt) * 16 + (lane & 15);
-            const float re = div(accR[mt][nt][i]), im = div(accI[mt][nt][i]);
-            // streaming stores: the rows are read once, later; keep L2 for the table
-            if constexpr (BF16OUT) {
-              uint16_t* out = static_cast<uint16_t*>(a.rows);
-              __builtin_nontemporal_store(f32_to_bf16_rne(re), out + u + j);
-              __builtin_nontemporal_store(f32_to_bf16_rne(im), out + u + D + j);
-            } else {
-              float* out = static_cast<float*>(a.rows);
-              __builtin_nontemporal_store(re, out + u + j);
-              __builtin_nontemporal_store(im, out + u + D + j);
-            }
+          for (int i = 0; i < 4; ++i) {
+            re[i] = div(accR[mt][nt][i]);
+            im[i] = div(accI[mt][nt][i]);
+          }
+          // streaming stores: the rows are read once, later; keep L2 for the table
+          if constexpr (ROWS == kRowsBF16) {
+            uint16_t* out = static_cast<uint16_t*>(a.rows);
+            u32x2 pr, pi;
+            pr.x = f32_to_bf16_rne(re[0]) | ((uint32_t)f32_to_bf16_rne(re[1]) << 16);
+            pr.y = f32_to_bf16_rne(re[2]) | ((uint32_t)f32_to_bf16_rne(re[3]) << 16);
+            pi.x = f32_to_bf16_rne(im[0]) | ((uint32_t)f32_to_bf16_rne(im[1]) << 16);
+            pi.y = f32_to_bf16_rne(im[2]) | ((uint32_t)f32_to_bf16_rne(im[3]) << 16);
+            __builtin_nontemporal_store(pr, reinterpret_cast<u32x2*>(out + u + j));
+            __builtin_nontemporal_store(pi, reinterpret_cast<u32x2*>(out + u + D + j));
+          } else {
+            float* out = static_cast<float*>(a.rows);
+            __builtin_nontemporal_store(re, reinterpret_cast<floatx4*>(out + u + j));
+            __builtin_nontemporal_store(im, reinterpret_cast<floatx4*>(out + u + D + j));
           }
         }
       }
@@ -388,62 +445,65 @@ static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
          (size_t)S::CH * 4 + 16 + (size_t)vol * 4;
 }
 
+// Rows per chunk and LDS bytes of the encoder for a given D (mirrors EncShape).
+static int chunk_rows(int nt) {
+  const int ntw = nt < kEncMaxNtw ? nt : kEncMaxNtw, wn = nt / ntw, wm = kEncWaves / wn;
+  return wm * 4 * 16;
+}
 
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol) {
   const int na = precision == VECKM_FP32 ? 4 : 2, nt = d / 16;
-  const int ntw = nt < 4 ? nt : 4, wn = nt / ntw, wm = 8 / wn, mt = nt >= 8 ? 4 : 2;
-  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)wm * mt * 16 * 4 + 16 +
+  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)chunk_rows(nt) * 4 + 16 +
          (size_t)vol * 4;
 }
 
 template <int NA, int NT, int NBUF>
-static int launch_t(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
+static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                     hipStream_t s) {
   const size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
-  const void* fn = bf16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, true>)
-                        : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, false>);
+  const void* fn = rows == kRowsBF16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsBF16>)
+                                     : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsF32>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
-  int grid = num_cus * ((160 * 1024) / lds >= 2 ? 2 : 1);
+  const int per_cu = (int)((160 * 1024) / lds);
+  int grid = num_cus * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
   if (grid > a.bt.nbricks) grid = a.bt.nbricks;
-  if (bf16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, true>), dim3(grid), dim3(512), lds, s, a);
+  constexpr int threads = EncShape<NA, NT>::NW * 64;
+  if (rows == kRowsBF16)
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, a);
   else
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, false>), dim3(grid), dim3(512), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, a);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
 template <int NA, int NT>
-static int launch_nb(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
+static int launch_nb(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                      hipStream_t s) {
   if constexpr (EncShape<NA, NT>::EVEN) {
-    if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, bf16, num_cus, s);
+    if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, rows, num_cus, s);
   }
-  return launch_t<NA, NT, 2>(a, et, bf16, num_cus, s);
+  return launch_t<NA, NT, 2>(a, et, rows, num_cus, s);
 }
 
 template <int NA>
-static int dispatch_nt(const EncArgs& a, const EncodeTables& et, bool bf16, int num_cus,
+static int dispatch_nt(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                        hipStream_t s) {
   switch (a.D / 16) {
-    case 1: return launch_nb<NA, 1>(a, et, bf16, num_cus, s);
-    case 2: return launch_nb<NA, 2>(a, et, bf16, num_cus, s);
-    case 3: return launch_nb<NA, 3>(a, et, bf16, num_cus, s);
-    case 4: return launch_nb<NA, 4>(a, et, bf16, num_cus, s);
-    case 8: return launch_nb<NA, 8>(a, et, bf16, num_cus, s);
-    case 16: return launch_nb<NA, 16>(a, et, bf16, num_cus, s);
+    case 1: return launch_nb<NA, 1>(a, et, rows, num_cus, s);
+    case 2: return launch_nb<NA, 2>(a, et, rows, num_cus, s);
+    case 3: return launch_nb<NA, 3>(a, et, rows, num_cus, s);
+    case 4: return launch_nb<NA, 4>(a, et, rows, num_cus, s);
+    case 8: return launch_nb<NA, 8>(a, et, rows, num_cus, s);
+    case 16: return launch_nb<NA, 16>(a, et, rows, num_cus, s);
     default: return VECKM_E_INVAL;
   }
 }
 
-int encode_rows_per_chunk(int d) {
-  const int nt = d / 16;
-  const int ntw = nt < 4 ? nt : 4;
-  return (8 / (nt / ntw)) * (nt >= 8 ? 4 : 2) * 16;
-}
+int encode_rows_per_chunk(int d) { return chunk_rows(d / 16); }
+int encode_waves() { return kEncWaves; }
 
-int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, bool bf16_rows,
+int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
                   int num_cus, void* stream) {
   EncArgs a;
   a.bt = bt;
@@ -472,8 +532,8 @@ int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, b
   a.plan = w.plan;
   if (a.SX > 64) return VECKM_E_INVAL;  // one wavefront copies one box row
   hipStream_t s = (hipStream_t)stream;
-  return et.na == 4 ? dispatch_nt<4>(a, et, bf16_rows, num_cus, s)
-                    : dispatch_nt<2>(a, et, bf16_rows, num_cus, s);
+  return et.na == 4 ? dispatch_nt<4>(a, et, rows, num_cus, s)
+                    : dispatch_nt<2>(a, et, rows, num_cus, s);
 }
 
 }  // namespace veckm

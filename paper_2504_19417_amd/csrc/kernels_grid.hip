@@ -34,7 +34,8 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
 }
 
 // One thread per event: validate against its slice, histogram, remember the
-// slice-local voxel.
+// slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught by k_pairs,
+// which reads every count once.
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,8 +51,7 @@ __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __rest
     return;
   }
   const int v = ((int)dt * s.H + e.y) * s.W + e.x;
-  const int old = atomicAdd(&count[s.grid_off + v], 1);
-  if (old == VECKM_MAX_VOXEL_EVENTS) atomicOr(err, kErrOverflow);
+  atomicAdd(&count[s.grid_off + v], 1);  // result unused: a no-return atomic
   vox[i] = v;
 }
 
@@ -60,7 +60,8 @@ __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __rest
 // (0 outside [0, W)), for x in [-1, W).  Any 4 consecutive voxels of a row
 // then sit in two aligned dwords, including a run that starts at x = -1.
 // Exact: counts are at most VECKM_MAX_VOXEL_EVENTS.
-__global__ void k_pairs(Batch bt, const int32_t* __restrict__ count, uint32_t* __restrict__ pairs) {
+__global__ void k_pairs(Batch bt, const int32_t* __restrict__ count, uint32_t* __restrict__ pairs,
+                        int32_t* __restrict__ err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < bt.npairs; g += stride) {
     int64_t poff = 0, voff = 0;
@@ -79,7 +80,9 @@ __global__ void k_pairs(Batch bt, const int32_t* __restrict__ count, uint32_t* _
     const int64_t row = p / (W + 1);
     const int x = (int)(p - row * (W + 1)) - 1;
     const int32_t* c = count + voff + row * W;
-    const uint32_t lo16 = x >= 0 ? __half_as_ushort(__float2half((float)c[x])) : 0u;
+    const int cx = x >= 0 ? c[x] : 0;
+    if (cx > VECKM_MAX_VOXEL_EVENTS) atomicOr(err, kErrOverflow);
+    const uint32_t lo16 = __half_as_ushort(__float2half((float)cx));
     const uint32_t hi16 = x + 1 < W ? __half_as_ushort(__float2half((float)c[x + 1])) : 0u;
     pairs[g] = lo16 | (hi16 << 16);
   }
@@ -260,7 +263,8 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   if (bt.n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
-  hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs);
+  hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs,
+                     w.err);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);

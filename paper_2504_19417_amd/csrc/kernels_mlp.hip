@@ -1,20 +1,27 @@
 // The two-layer perceptron of Sec. 2.1 (Eqns. 5-6) on the matrix cores:
 //   flow = W2 relu(W1 x + b1) + b2,  x = [Re emb | Im emb] (K2 = 2D values).
-// Layer 1 is the dense contraction [rows x K2] x [K2 x hidden]; layer 2 is
+// Layer 1 is the dense contraction [hidden x K2] x [K2 x rows]; layer 2 is
 // two dot products per row, done in the epilogue while the hidden values
 // are still in registers (ReLU, multiply by W2, reduce across the lanes
 // and waves that hold a row's hidden units).
 //
-// A block of 4 waves owns 64-row tiles of x (persistent loop over tiles);
-// wave w owns hidden units [w*hidden/4, (w+1)*hidden/4).  The x tile of the
-// next iteration streams into LDS with global_load_lds while the current
-// one is multiplied (double buffer), 16-byte chunks XOR-swizzled by row so
-// that fragment reads hit distinct banks.  W1 operands: fp32 fragments are
-// read from L2 one k-slice ahead; bf16 fragments of the wave's hidden units
-// stay in registers for the whole kernel when they fit (else read from L2).
-// The contraction index is permuted consistently in A and B so that each
-// lane's operand is 16 contiguous bytes of a row of x and of a row of W1
-// (W1 is [hidden][K2], contiguous along the contraction).
+// Main kernel (k_mlp_res): a block of 4 waves (one per SIMD) walks 64-row
+// tiles of x; wave w owns hidden units [w hidden/4, (w+1) hidden/4) and
+// keeps their W1 fragments in registers for the whole kernel.  x tiles
+// stream into LDS with global->LDS copies NBUF - 1 tiles ahead of use,
+// 16-byte chunks XOR-swizzled by row so that fragment reads hit distinct
+// banks.  Two operand forms:
+//   * bf16 rows x bf16 W1 (the FP16 form), one product;
+//   * fp32 rows and W1, both carried as fp16 hi + lo pairs (the FP32 form:
+//     22 significant bits per operand; rows are split as their fragments
+//     are read), three products hi*hi + hi*lo + lo*hi, fp32 accumulation;
+//     W1 is scaled by a power of two so that its lo parts stay normal, and
+//     the sums are scaled back exactly.
+// The contraction index is permuted consistently in A (W1) and B (x) so that
+// each lane's operand is 16 contiguous bytes of a row of W1 and of x; with W1
+// as the A operand, a lane's accumulator holds 4 consecutive hidden units of
+// one row.  Fallbacks for shapes whose W1 does not fit in registers read W1
+// from L2 (bf16), or run fp32 rows on the fp32 matrix cores.
 //
 // The row count U is read from the device, so no host synchronisation is
 // needed between the encoder and the perceptron.
@@ -27,11 +34,15 @@ namespace veckm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 struct MlpArgs {
-  const void* x;        // U x K2 (fp32 or bf16)
+  const void* x;        // U rows of K2 values, fp32 or bf16
   const float* W1;      // hidden x K2 fp32
   const uint16_t* W1b;  // hidden x K2 bf16
+  const uint16_t* W1h;  // hidden x K2 fp16 hi of W1 * 2^s
+  const uint16_t* W1l;  // hidden x K2 fp16 lo of W1 * 2^s
+  float unscale;        // 2^-s
   const float* b1;
   const float* W2;  // 2 x hidden
   const float* b2;
@@ -47,7 +58,16 @@ __device__ inline bf16x8 as_bf16x8(uint4 u) {
   return h;
 }
 
-constexpr int mlp_vmcnt0() { return (7 << 4) | (15 << 8); }
+__device__ inline f16x8 as_f16x8(uint4 u) {
+  f16x8 h;
+  __builtin_memcpy(&h, &u, 16);
+  return h;
+}
+
+// s_waitcnt immediate (gfx9 encoding) waiting until at most n (<= 63) vector
+// memory operations are outstanding.
+constexpr int mlp_vmcnt(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int mlp_vmcnt0() { return mlp_vmcnt(0); }
 
 // Per-wave layer constants: b1, W2[0], W2[1] of the lane's hidden units.
 template <int NTH>
@@ -128,7 +148,7 @@ __device__ inline void issue_tile(const unsigned char* x, int tile, int U, uint4
     int row = tile * 64 + r;
     row = row < U ? row : U - 1;
     const uint4* src = reinterpret_cast<const uint4*>(x + (int64_t)row * RB) + (p ^ (r & 15));
-    __builtin_amdgcn_global_load_lds(src, buf + rb * CPR, 16, 0, 0);
+    copy_to_lds16(src, lds_offset(buf + rb * CPR));
   }
 }
 
@@ -191,59 +211,6 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs a) {
         }
 #pragma unroll
       for (int nt = 0; nt < NTH; ++nt) bv[nt] = bn[nt];
-    }
-    mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
-  }
-}
-
-// bf16: A from the LDS tile, B (W1) resident in registers.
-template <int NTH, int K2>
-__global__ __launch_bounds__(256) void k_mlp_bf16_res(MlpArgs a) {
-  constexpr int RB = K2 * 2, CPR = RB / 16, KQ = K2 / 32;
-  extern __shared__ __align__(16) unsigned char smem_mlp[];
-  uint4* tbuf = reinterpret_cast<uint4*>(smem_mlp);
-  __shared__ float red[4][64][2];
-  const int U = a.plan[0];
-  const int ntiles = (U + 63) / 64;
-  Layer2<NTH> l2;
-  l2.load(a);
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane >> 4, r16 = lane & 15;
-  const unsigned char* X = static_cast<const unsigned char*>(a.x);
-  bf16x8 w[KQ][NTH];
-#pragma unroll
-  for (int nt = 0; nt < NTH; ++nt) {
-    const uint16_t* wr = a.W1b + (int64_t)(wid * NTH * 16 + nt * 16 + r16) * K2 + 8 * g;
-#pragma unroll
-    for (int kq = 0; kq < KQ; ++kq) w[kq][nt] = as_bf16x8(*reinterpret_cast<const uint4*>(wr + kq * 32));
-  }
-  int tile = blockIdx.x;
-  if (tile < ntiles) issue_tile<RB>(X, tile, U, tbuf, wid, lane);
-  for (int it = 0; tile < ntiles; tile += gridDim.x, ++it) {
-    uint4* cur = tbuf + (it & 1) * 64 * CPR;
-    const int next = tile + gridDim.x;
-    __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
-    lds_barrier();
-    if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
-    floatx4 acc[4][NTH];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kq = 0; kq < KQ; ++kq) {
-      bf16x8 av[4];
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const int r = mt * 16 + r16, c = kq * 4 + g;
-        av[mt] = as_bf16x8(cur[r * CPR + (c ^ (r & 15))]);
-      }
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NTH; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mt], w[kq][nt], acc[mt][nt], 0, 0, 0);
     }
     mlp_epilogue<NTH>(a, l2, acc, tile, U, red);
   }
@@ -343,6 +310,158 @@ __global__ __launch_bounds__(256) void k_mlp_f32_any(MlpArgs a) {
   }
 }
 
+// Per-wave layer-2 constants of the lane's hidden units: unit
+// w*16*NTH + 16*nt + 4*(lane>>4) + i.
+template <int NTH>
+struct Layer2T {
+  float b[NTH][4], w0[NTH][4], w1[NTH][4];
+  __device__ void load(const MlpArgs& a, int wid, int lane) {
+#pragma unroll
+    for (int nt = 0; nt < NTH; ++nt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = wid * NTH * 16 + nt * 16 + 4 * (lane >> 4) + i;
+        b[nt][i] = a.b1[c];
+        w0[nt][i] = a.W2[c];
+        w1[nt][i] = a.W2[a.hidden + c];
+      }
+  }
+};
+
+// FORM 0: bf16 rows x bf16 W1.  FORM 1: fp32 rows and W1, both as fp16 hi/lo.
+template <int FORM, int NTH, int K2, int NBUF>
+__global__ __launch_bounds__(256) void k_mlp_res(MlpArgs a) {
+  constexpr int KQ = K2 / 32;
+  constexpr int RB = FORM == 0 ? K2 * 2 : K2 * 4;  // bytes per row
+  constexpr int CPR = RB / 16;                      // 16-byte chunks per row
+  constexpr int TILE_U4 = 64 * CPR;
+  constexpr int PFW = TILE_U4 / 256;                // copies per wave per tile
+  static_assert(CPR % 16 == 0 && CPR <= 64, "row size");
+  static_assert((NBUF - 2) * PFW <= 63, "copies in flight exceed the wait counter");
+  extern __shared__ __align__(16) unsigned char smem_mlp[];
+  uint4* tbuf = reinterpret_cast<uint4*>(smem_mlp);  // NBUF tiles of 64 rows
+  __shared__ float red[4][64][2];
+  const int U = a.plan[0];
+  const int ntiles = (U + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const unsigned char* X = static_cast<const unsigned char*>(a.x);
+  // W1 fragments (A operand: hidden unit r16 of the tile, contraction
+  // elements 32 kq + 8 g .. + 7)
+  uint4 wh[KQ][NTH], wl[FORM == 1 ? KQ : 1][NTH];
+#pragma unroll
+  for (int nt = 0; nt < NTH; ++nt) {
+    const int64_t h = wid * NTH * 16 + nt * 16 + r16;
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+      const uint16_t* src = (FORM == 0 ? a.W1b : a.W1h) + h * K2 + kq * 32 + 8 * g;
+      wh[kq][nt] = *reinterpret_cast<const uint4*>(src);
+      if constexpr (FORM == 1)
+        wl[kq][nt] = *reinterpret_cast<const uint4*>(a.W1l + h * K2 + kq * 32 + 8 * g);
+    }
+  }
+  Layer2T<NTH> l2;
+  l2.load(a, wid, lane);
+  const float unscale = FORM == 1 ? a.unscale : 1.f;
+  const int mine = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+#pragma unroll
+  for (int u = 0; u < NBUF - 1; ++u)
+    if (u < mine)
+      issue_tile<RB>(X, blockIdx.x + u * gridDim.x, U, tbuf + u * TILE_U4, wid, lane);
+  for (int it = 0; it < mine; ++it) {
+    const int tile = blockIdx.x + it * gridDim.x;
+    uint4* cur = tbuf + (it % NBUF) * TILE_U4;
+    // tile `it` has landed once only the copies of the later tiles already
+    // issued (at most NBUF - 2 of them) may be outstanding
+    const int later = mine - 1 - it < NBUF - 2 ? mine - 1 - it : NBUF - 2;
+    if (NBUF > 2 && later >= 1) {
+      if (later >= 2 && NBUF > 3)
+        __builtin_amdgcn_s_waitcnt(mlp_vmcnt((NBUF - 2) * PFW > 63 ? 63 : 2 * PFW));
+      else
+        __builtin_amdgcn_s_waitcnt(mlp_vmcnt(PFW));
+    } else {
+      __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
+    }
+    lds_barrier();  // tile `it` is in `cur`; the buffer of tile it - 1 is free
+    if (it + NBUF - 1 < mine)
+      issue_tile<RB>(X, tile + (NBUF - 1) * gridDim.x, U,
+                     tbuf + ((it + NBUF - 1) % NBUF) * TILE_U4, wid, lane);
+    floatx4 acc[4][NTH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int r = mt * 16 + r16;
+        if constexpr (FORM == 0) {
+          const int c = kq * 4 + g;  // 8 bf16 elements per 16-byte chunk
+          const uint4 xb = cur[r * CPR + (c ^ (r & 15))];
+#pragma unroll
+          for (int nt = 0; nt < NTH; ++nt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(wh[kq][nt]),
+                                                                  as_bf16x8(xb), acc[mt][nt], 0, 0, 0);
+        } else {
+          // fp32 row elements 32 kq + 8 g .. + 7 (two chunks), split into an
+          // fp16 hi + lo pair: lo = v - hi is exact in fp32, then rounded
+          const int c = kq * 8 + 2 * g;
+          const uint4 u0 = cur[r * CPR + (c ^ (r & 15))];
+          const uint4 u1 = cur[r * CPR + ((c + 1) ^ (r & 15))];
+          const float v[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                              __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                              __uint_as_float(u1.z), __uint_as_float(u1.w)};
+          f16x8 xh, xl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            xh[e] = (_Float16)v[e];
+            xl[e] = (_Float16)(v[e] - (float)xh[e]);
+          }
+#pragma unroll
+          for (int nt = 0; nt < NTH; ++nt) {
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xh,
+                                                                 acc[mt][nt], 0, 0, 0);
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wl[kq][nt]), xh,
+                                                                 acc[mt][nt], 0, 0, 0);
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xl,
+                                                                 acc[mt][nt], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // layer 2: the lane holds hidden units 16 nt + 4 g + i of row 16 mt + r16
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float h = fmaxf(fmaf(acc[mt][nt][i], unscale, l2.b[nt][i]), 0.f);
+          p0 = fmaf(l2.w0[nt][i], h, p0);
+          p1 = fmaf(l2.w1[nt][i], h, p1);
+        }
+      p0 += __shfl_xor(p0, 16);
+      p1 += __shfl_xor(p1, 16);
+      p0 += __shfl_xor(p0, 32);
+      p1 += __shfl_xor(p1, 32);
+      if (g == 0) {
+        red[wid][mt * 16 + r16][0] = p0;
+        red[wid][mt * 16 + r16][1] = p1;
+      }
+    }
+    lds_barrier();
+    if (threadIdx.x < 128) {
+      const int r = threadIdx.x >> 1, o = threadIdx.x & 1;
+      const int row = tile * 64 + r;
+      const float v = red[0][r][o] + red[1][r][o] + red[2][r][o] + red[3][r][o] + a.b2[o];
+      if (row < U) a.out[(int64_t)row * 2 + o] = v;
+    }
+  }
+}
+
 template <typename K>
 static int launch_lds(K kern, const MlpArgs& a, size_t lds, int per_cu, int num_cus, hipStream_t s) {
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -353,16 +472,28 @@ static int launch_lds(K kern, const MlpArgs& a, size_t lds, int per_cu, int num_
 }
 
 template <int NTH>
-static int launch_nth(const MlpArgs& a, bool bf16, int num_cus, hipStream_t s) {
-  if (bf16) {
+static int launch_nth(const MlpArgs& a, int rows, int num_cus, hipStream_t s) {
+  if (rows == kRowsBF16) {
     // W1 of the wave's hidden units in registers when it fits (<= 128 VGPRs)
     if constexpr (NTH <= 4) {
-      if (a.K2 == 256 && (a.K2 / 32) * NTH <= 32)
-        return launch_lds(k_mlp_bf16_res<NTH, 256>, a, 2 * 64 * 256 * 2, 1, num_cus, s);
-      if (a.K2 == 128)
-        return launch_lds(k_mlp_bf16_res<NTH, 128>, a, 2 * 64 * 128 * 2, 1, num_cus, s);
+      if (a.K2 == 256) return launch_lds(k_mlp_res<0, NTH, 256, 3>, a, 3 * 64 * 512, 1, num_cus, s);
+    }
+    if constexpr (NTH <= 8) {
+      if (a.K2 == 128) return launch_lds(k_mlp_res<0, NTH, 128, 4>, a, 4 * 64 * 256, 1, num_cus, s);
     }
     hipLaunchKernelGGL(k_mlp_bf16<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
+  } else if (rows == kRowsSplit16) {
+    // shapes admitted by mlp_rows_split()
+    if constexpr (NTH <= 4) {
+      if (a.K2 == 256) return launch_lds(k_mlp_res<1, NTH, 256, 2>, a, 2 * 64 * 1024, 1, num_cus, s);
+    }
+    if constexpr (NTH <= 6) {
+      if (a.K2 == 128) return launch_lds(k_mlp_res<1, NTH, 128, 3>, a, 3 * 64 * 512, 1, num_cus, s);
+    }
+    if constexpr (NTH <= 8) {
+      if (a.K2 == 64) return launch_lds(k_mlp_res<1, NTH, 64, 4>, a, 4 * 64 * 256, 1, num_cus, s);
+    }
+    return VECKM_E_INVAL;
   } else {
     if (a.K2 == 256) return launch_lds(k_mlp_f32<NTH, 256>, a, 2 * 64 * 256 * 4, 1, num_cus, s);
     if (a.K2 == 128) return launch_lds(k_mlp_f32<NTH, 128>, a, 2 * 64 * 128 * 4, 2, num_cus, s);
@@ -371,12 +502,20 @@ static int launch_nth(const MlpArgs& a, bool bf16, int num_cus, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int num_cus,
+bool mlp_rows_split(int d, int hidden) {
+  const int k2 = 2 * d, nth = hidden / 64;
+  return (k2 == 256 && nth <= 4) || (k2 == 128 && nth <= 6) || (k2 == 64 && nth <= 8);
+}
+
+int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int num_cus,
                void* stream) {
   MlpArgs a;
   a.x = w.rows;
   a.W1 = mw.W1;
   a.W1b = mw.W1b;
+  a.W1h = mw.W1h;
+  a.W1l = mw.W1l;
+  a.unscale = mw.unscale;
   a.b1 = mw.b1;
   a.W2 = mw.W2;
   a.b2 = mw.b2;
@@ -387,14 +526,14 @@ int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int n
   if (a.K2 % 32) return VECKM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   switch (mw.hidden / 64) {
-    case 1: return launch_nth<1>(a, bf16, num_cus, s);
-    case 2: return launch_nth<2>(a, bf16, num_cus, s);
-    case 3: return launch_nth<3>(a, bf16, num_cus, s);
-    case 4: return launch_nth<4>(a, bf16, num_cus, s);
-    case 5: return launch_nth<5>(a, bf16, num_cus, s);
-    case 6: return launch_nth<6>(a, bf16, num_cus, s);
-    case 7: return launch_nth<7>(a, bf16, num_cus, s);
-    case 8: return launch_nth<8>(a, bf16, num_cus, s);
+    case 1: return launch_nth<1>(a, rows, num_cus, s);
+    case 2: return launch_nth<2>(a, rows, num_cus, s);
+    case 3: return launch_nth<3>(a, rows, num_cus, s);
+    case 4: return launch_nth<4>(a, rows, num_cus, s);
+    case 5: return launch_nth<5>(a, rows, num_cus, s);
+    case 6: return launch_nth<6>(a, rows, num_cus, s);
+    case 7: return launch_nth<7>(a, rows, num_cus, s);
+    case 8: return launch_nth<8>(a, rows, num_cus, s);
     default: return VECKM_E_INVAL;
   }
 }

@@ -73,7 +73,7 @@ uint16_t fp16_bits_rne(double v) {
   return (uint16_t)(sign | (int)std::nearbyint(std::ldexp(a, 24)));
 }
 
-static double fp16_bits_to_double(uint16_t h) {
+double fp16_to_double(uint16_t h) {
   const int s = h >> 15, E = (h >> 10) & 31, M = h & 1023;
   double v;
   if (E == 0) v = std::ldexp((double)M, -24);
@@ -113,9 +113,9 @@ void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out
       const uint16_t ch = fp16_bits_rne(c), sh = fp16_bits_rne(s);
       uint16_t* o = out + ((size_t)k * d + j) * 4;
       o[0] = ch;
-      o[1] = fp16_bits_rne(c - fp16_bits_to_double(ch));
+      o[1] = fp16_bits_rne(c - fp16_to_double(ch));
       o[2] = sh;
-      o[3] = fp16_bits_rne(s - fp16_bits_to_double(sh));
+      o[3] = fp16_bits_rne(s - fp16_to_double(sh));
     }
 }
 
@@ -168,7 +168,7 @@ std::vector<uint16_t> make_slot_fragments(const SlotTable& t, const double* A, i
             const double v = (na == 4 ? (a < 2) : (a == 0)) ? c : sn;
             const uint16_t hi = fp16_bits_rne(v);
             const bool lo = na == 4 && (a & 1);
-            frag[idx] = lo ? fp16_bits_rne(v - fp16_bits_to_double(hi)) : hi;
+            frag[idx] = lo ? fp16_bits_rne(v - fp16_to_double(hi)) : hi;
           }
   return frag;
 }
@@ -200,7 +200,7 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
                         {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}, {4, 4, 1}};
   const int na = precision == VECKM_FP32 ? 4 : 2;
-  const bool even = (na * (d / 16) * 64) % 512 == 0;
+  const bool even = (na * (d / 16) * 64) % (encode_waves() * 64) == 0;  // copies split evenly
   for (int nb = even ? 3 : 2; nb >= 2; --nb)
     for (const Brick& b : cand)
       if (encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024) {

@@ -59,6 +59,7 @@ void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out
 void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick, int* nbuf);
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol);
 int encode_rows_per_chunk(int d);
+int encode_waves();  // waves per encoder block
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
 // The encoder's LDS box of a brick: the brick plus the window halo, widened
 // by kRunPad columns on each side in x so that no 4-offset run of the slot
@@ -69,6 +70,7 @@ inline int box_dwords(const Brick& b, int rx, int ry, int rt) {
   return box_sx(b, rx) * (b.by + 2 * ry) * (b.bt + 2 * rt);
 }
 uint16_t fp16_bits_rne(double v);
+double fp16_to_double(uint16_t h);
 uint16_t bf16_bits_rne(float v);
 
 // ---------------------------------------------------------------- launches
@@ -127,10 +129,19 @@ struct EncodeTables {
   int d = 0;
 };
 
+// Row formats the encoder writes (one row of 2D values per query voxel) and
+// the perceptron forms that read them.
+constexpr int kRowsF32 = 0;      // fp32 rows; perceptron on fp32 matrix cores
+constexpr int kRowsBF16 = 1;     // bf16 rows; bf16 perceptron (FP16 form)
+constexpr int kRowsSplit16 = 2;  // fp32 rows split into fp16 hi/lo in the perceptron (FP32 form)
+
 struct MlpWeights {
   int hidden = 0;
   const float* W1 = nullptr;       // hidden x 2D fp32
   const uint16_t* W1b = nullptr;   // hidden x 2D bf16
+  const uint16_t* W1h = nullptr;   // hidden x 2D fp16 hi of W1 * 2^s
+  const uint16_t* W1l = nullptr;   // hidden x 2D fp16 lo of W1 * 2^s
+  float unscale = 1.f;             // 2^-s
   const float* b1 = nullptr;
   const float* W2 = nullptr;       // 2 x hidden
   const float* b2 = nullptr;
@@ -138,11 +149,14 @@ struct MlpWeights {
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, void* stream);
-int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, bool bf16_rows,
+int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
                   int num_cus, void* stream);
 int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream);
-int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, bool bf16, int num_cus,
+int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int num_cus,
                void* stream);
+// Whether the FP32-form perceptron runs on fp16 hi/lo operand pairs for
+// this shape (W1 fragments fit in registers); else on the fp32 matrix cores.
+bool mlp_rows_split(int d, int hidden);
 int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
 int launch_take_err(const Workspace& w, int32_t* host, void* stream);
