@@ -132,6 +132,19 @@ __device__ inline void issue_slab(const uint4* src, uint4* dst, int wid, int lan
   }
 }
 
+// Waits until every slab copy of this wave except those of the newest
+// `newer` slabs (0..2) has landed; vector memory loads complete in order.
+template <int PFW>
+__device__ inline void wait_slabs(int newer) {
+  static_assert(2 * PFW <= 63, "copies in flight exceed the wait counter");
+  if (newer >= 2)
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * PFW));
+  else if (newer == 1)
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
+  else
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+}
+
 // The count words of one k-step for MTV row tiles: for each tile, the lane's
 // two +o runs (4 consecutive voxels each, two aligned pair dwords per run)
 // and their -o partners.  Only the brick's count box and the run offsets are
@@ -185,7 +198,7 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
   CountWords<MTV> cw;
   if constexpr (MTV > 0 && kEncPrefetch) cw.fetch(runs_l, vol2, rb, 0, g);
   for (int ks = 0; ks < nsteps; ++ks) {
-    const int buf = NBUF == 3 ? ks % 3 : (ks & 1);
+    const int buf = ks % NBUF;
     if constexpr (MTV > 0) {
       if constexpr (!kEncPrefetch) cw.fetch(runs_l, vol2, rb, ks, g);
       // pair sums and differences of counts at +o / -o: the -o run comes out
@@ -238,15 +251,13 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
     }
     // every LDS read of this step is issued: start the slab AHEAD steps out
     // (its buffer was last read in step ks - 1, before the last barrier),
-    // then make sure the slab of step ks + 1 has landed
-    const bool more = ks + AHEAD < nsteps;
-    if (more)
+    // then make sure the slab of step ks + 1 has landed (slabs ks + 2 ..
+    // ks + AHEAD may stay in flight)
+    if (ks + AHEAD < nsteps)
       issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
                               slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
-    if (NBUF == 3 && more)
-      __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
-    else
-      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    const int last = ks + AHEAD < nsteps - 1 ? ks + AHEAD : nsteps - 1;  // newest slab issued
+    wait_slabs<PFW>(last - ks - 1 > 0 ? last - ks - 1 : 0);
     lds_barrier();
   }
 }
@@ -280,7 +291,8 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
   using S = EncShape<NA, NT>;
   constexpr int NW = S::NW, NTW = S::NTW, WN = S::WN, WM = S::WM, MT = S::MT, CH = S::CH,
                 SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
-  static_assert(NBUF == 2 || (NBUF == 3 && S::EVEN), "three slab buffers need even slab loads");
+  static_assert(NBUF == 2 || ((NBUF == 3 || NBUF == 4) && S::EVEN),
+                "three or four slab buffers need slab copies split evenly over the waves");
   constexpr int AHEAD = NBUF - 1;  // slabs in flight beyond the one in use
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* slab = reinterpret_cast<uint4*>(smem);
@@ -356,10 +368,7 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
       for (int u = 0; u < AHEAD; ++u)
         if (u < a.nsteps)
           issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
-      if (NBUF == 3 && a.nsteps > 1)
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm(PFW));
-      else
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      wait_slabs<PFW>((a.nsteps < AHEAD ? a.nsteps : AHEAD) - 1);  // slab 0 (and the box) landed
       lds_barrier();
 
       // tiles are dealt round-robin over the row waves, so a short chunk
@@ -481,6 +490,7 @@ template <int NA, int NT>
 static int launch_nb(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                      hipStream_t s) {
   if constexpr (EncShape<NA, NT>::EVEN) {
+    if (et.nbuf == 4) return launch_t<NA, NT, 4>(a, et, rows, num_cus, s);
     if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, rows, num_cus, s);
   }
   return launch_t<NA, NT, 2>(a, et, rows, num_cus, s);

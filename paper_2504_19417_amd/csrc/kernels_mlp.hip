@@ -135,15 +135,15 @@ __device__ inline void mlp_epilogue(const MlpArgs& a, const Layer2<NTH>& l2, flo
 // Starts the copy of x tile `tile` (64 rows of RB bytes) into an LDS buffer:
 // LDS chunk p of row r holds global chunk p ^ (r & 15) (16-byte chunks).
 // Rows past U repeat row U - 1 (their results are dropped).
-template <int RB>
+template <int RB, int NW>
 __device__ inline void issue_tile(const unsigned char* x, int tile, int U, uint4* buf, int wid,
                                   int lane) {
   constexpr int CPR = RB / 16;          // chunks per row
   constexpr int RPI = 64 / CPR;         // rows per wave instruction
-  static_assert(64 % CPR == 0, "row size");
+  static_assert(64 % CPR == 0 && (64 / RPI) % NW == 0, "row size");
 #pragma unroll
-  for (int u = 0; u < 64 / RPI / 4; ++u) {
-    const int rb = (u * 4 + wid) * RPI;  // first row of this instruction
+  for (int u = 0; u < 64 / RPI / NW; ++u) {
+    const int rb = (u * NW + wid) * RPI;  // first row of this instruction
     const int r = rb + lane / CPR, p = lane % CPR;
     int row = tile * 64 + r;
     row = row < U ? row : U - 1;
@@ -172,13 +172,13 @@ __global__ __launch_bounds__(256) void k_mlp_f32(MlpArgs a) {
   for (int nt = 0; nt < NTH; ++nt)
     wr[nt] = a.W1 + (int64_t)(wid * NTH * 16 + nt * 16 + r16) * K2 + 4 * g;
   int tile = blockIdx.x;
-  if (tile < ntiles) issue_tile<RB>(X, tile, U, tbuf, wid, lane);
+  if (tile < ntiles) issue_tile<RB, 4>(X, tile, U, tbuf, wid, lane);
   for (int it = 0; tile < ntiles; tile += gridDim.x, ++it) {
     uint4* cur = tbuf + (it & 1) * 64 * CPR;
     const int next = tile + gridDim.x;
     __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
     lds_barrier();  // tile `tile` is in `cur`; the other buffer is free
-    if (next < ntiles) issue_tile<RB>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
+    if (next < ntiles) issue_tile<RB, 4>(X, next, U, tbuf + ((it + 1) & 1) * 64 * CPR, wid, lane);
     floatx4 acc[4][NTH];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -329,18 +329,19 @@ struct Layer2T {
 };
 
 // FORM 0: bf16 rows x bf16 W1.  FORM 1: fp32 rows and W1, both as fp16 hi/lo.
-template <int FORM, int NTH, int K2, int NBUF>
-__global__ __launch_bounds__(256) void k_mlp_res(MlpArgs a) {
+// NW waves per block, each owning 16 NTH hidden units.
+template <int FORM, int NW, int NTH, int K2, int NBUF>
+__global__ __launch_bounds__(NW * 64) void k_mlp_res(MlpArgs a) {
   constexpr int KQ = K2 / 32;
   constexpr int RB = FORM == 0 ? K2 * 2 : K2 * 4;  // bytes per row
   constexpr int CPR = RB / 16;                      // 16-byte chunks per row
   constexpr int TILE_U4 = 64 * CPR;
-  constexpr int PFW = TILE_U4 / 256;                // copies per wave per tile
+  constexpr int PFW = TILE_U4 / (NW * 64);          // copies per wave per tile
   static_assert(CPR % 16 == 0 && CPR <= 64, "row size");
   static_assert((NBUF - 2) * PFW <= 63, "copies in flight exceed the wait counter");
   extern __shared__ __align__(16) unsigned char smem_mlp[];
   uint4* tbuf = reinterpret_cast<uint4*>(smem_mlp);  // NBUF tiles of 64 rows
-  __shared__ float red[4][64][2];
+  __shared__ float red[NW][64][2];
   const int U = a.plan[0];
   const int ntiles = (U + 63) / 64;
   const int lane = threadIdx.x & 63;
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(256) void k_mlp_res(MlpArgs a) {
 #pragma unroll
   for (int u = 0; u < NBUF - 1; ++u)
     if (u < mine)
-      issue_tile<RB>(X, blockIdx.x + u * gridDim.x, U, tbuf + u * TILE_U4, wid, lane);
+      issue_tile<RB, NW>(X, blockIdx.x + u * gridDim.x, U, tbuf + u * TILE_U4, wid, lane);
   for (int it = 0; it < mine; ++it) {
     const int tile = blockIdx.x + it * gridDim.x;
     uint4* cur = tbuf + (it % NBUF) * TILE_U4;
@@ -385,8 +386,8 @@ __global__ __launch_bounds__(256) void k_mlp_res(MlpArgs a) {
     }
     lds_barrier();  // tile `it` is in `cur`; the buffer of tile it - 1 is free
     if (it + NBUF - 1 < mine)
-      issue_tile<RB>(X, tile + (NBUF - 1) * gridDim.x, U,
-                     tbuf + ((it + NBUF - 1) % NBUF) * TILE_U4, wid, lane);
+      issue_tile<RB, NW>(X, tile + (NBUF - 1) * gridDim.x, U,
+                         tbuf + ((it + NBUF - 1) % NBUF) * TILE_U4, wid, lane);
     floatx4 acc[4][NTH];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -456,47 +457,198 @@ __global__ __launch_bounds__(256) void k_mlp_res(MlpArgs a) {
     if (threadIdx.x < 128) {
       const int r = threadIdx.x >> 1, o = threadIdx.x & 1;
       const int row = tile * 64 + r;
-      const float v = red[0][r][o] + red[1][r][o] + red[2][r][o] + red[3][r][o] + a.b2[o];
+      float v = a.b2[o];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += red[w][r][o];
+      if (row < U) a.out[(int64_t)row * 2 + o] = v;
+    }
+  }
+}
+
+// FP32 form with the split done once per tile: the fp32 tile lands in a
+// staging buffer, the block splits it into fp16 hi/lo pairs in a second
+// buffer (each element converted once), and the next tile's copy into the
+// staging buffer overlaps the products.  Split layout per row: chunks
+// [0, K2/8) hold the hi halves of elements 8c .. 8c + 7, chunks [K2/8, K2/4)
+// the lo halves; chunk p of row r sits at p ^ (r & 15).
+template <int NW, int NTH, int K2>
+__global__ __launch_bounds__(NW * 64) void k_mlp_split(MlpArgs a) {
+  constexpr int KQ = K2 / 32;
+  constexpr int RB = K2 * 4;        // bytes per fp32 row (and per split row)
+  constexpr int CPR = RB / 16;      // 16-byte chunks per row
+  constexpr int TILE_U4 = 64 * CPR;
+  constexpr int PFW = TILE_U4 / (NW * 64);
+  constexpr int HALF = CPR / 2;     // first lo chunk of a split row
+  static_assert(CPR % 16 == 0 && CPR <= 64, "row size");
+  static_assert(PFW <= 63, "copies in flight exceed the wait counter");
+  static_assert((64 * HALF) % (NW * 64) == 0, "split work per thread");
+  extern __shared__ __align__(16) unsigned char smem_mlp[];
+  uint4* stage = reinterpret_cast<uint4*>(smem_mlp);  // fp32 tile being copied in
+  uint4* split = stage + TILE_U4;                      // the current tile as hi/lo
+  __shared__ float red[NW][64][2];
+  const int U = a.plan[0];
+  const int ntiles = (U + 63) / 64;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, r16 = lane & 15;
+  const unsigned char* X = static_cast<const unsigned char*>(a.x);
+  uint4 wh[KQ][NTH], wl[KQ][NTH];
+#pragma unroll
+  for (int nt = 0; nt < NTH; ++nt) {
+    const int64_t h = wid * NTH * 16 + nt * 16 + r16;
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+      wh[kq][nt] = *reinterpret_cast<const uint4*>(a.W1h + h * K2 + kq * 32 + 8 * g);
+      wl[kq][nt] = *reinterpret_cast<const uint4*>(a.W1l + h * K2 + kq * 32 + 8 * g);
+    }
+  }
+  Layer2T<NTH> l2;
+  l2.load(a, wid, lane);
+  const float unscale = a.unscale;
+  const int mine = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  if (mine > 0) issue_tile<RB, NW>(X, blockIdx.x, U, stage, wid, lane);
+  for (int it = 0; it < mine; ++it) {
+    const int tile = blockIdx.x + it * gridDim.x;
+    __builtin_amdgcn_s_waitcnt(mlp_vmcnt0());
+    lds_barrier();  // tile `it` is in `stage`; `split` is free (previous products done)
+    // ---- split: work item (row r, output chunk q) covers elements 8q .. 8q + 7
+#pragma unroll
+    for (int w = 0; w < 64 * HALF / (NW * 64); ++w) {
+      const int item = w * NW * 64 + tid;
+      const int r = item / HALF, q = item % HALF;
+      const uint4 u0 = stage[r * CPR + ((2 * q) ^ (r & 15))];
+      const uint4 u1 = stage[r * CPR + ((2 * q + 1) ^ (r & 15))];
+      const float v[8] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                          __uint_as_float(u0.w), __uint_as_float(u1.x), __uint_as_float(u1.y),
+                          __uint_as_float(u1.z), __uint_as_float(u1.w)};
+      f16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        hi[e] = (_Float16)v[e];
+        lo[e] = (_Float16)(v[e] - (float)hi[e]);
+      }
+      uint4 hu, lu;
+      __builtin_memcpy(&hu, &hi, 16);
+      __builtin_memcpy(&lu, &lo, 16);
+      split[r * CPR + (q ^ (r & 15))] = hu;
+      split[r * CPR + ((q + HALF) ^ (r & 15))] = lu;
+    }
+    lds_barrier();  // `split` holds the tile; `stage` is free
+    if (it + 1 < mine) issue_tile<RB, NW>(X, tile + gridDim.x, U, stage, wid, lane);
+    floatx4 acc[4][NTH];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int r = mt * 16 + r16, c = kq * 4 + g;
+        const f16x8 xh = as_f16x8(split[r * CPR + (c ^ (r & 15))]);
+        const f16x8 xl = as_f16x8(split[r * CPR + ((c + HALF) ^ (r & 15))]);
+#pragma unroll
+        for (int nt = 0; nt < NTH; ++nt) {
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xh,
+                                                               acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wl[kq][nt]), xh,
+                                                               acc[mt][nt], 0, 0, 0);
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xl,
+                                                               acc[mt][nt], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < NTH; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float h = fmaxf(fmaf(acc[mt][nt][i], unscale, l2.b[nt][i]), 0.f);
+          p0 = fmaf(l2.w0[nt][i], h, p0);
+          p1 = fmaf(l2.w1[nt][i], h, p1);
+        }
+      p0 += __shfl_xor(p0, 16);
+      p1 += __shfl_xor(p1, 16);
+      p0 += __shfl_xor(p0, 32);
+      p1 += __shfl_xor(p1, 32);
+      if (g == 0) {
+        red[wid][mt * 16 + r16][0] = p0;
+        red[wid][mt * 16 + r16][1] = p1;
+      }
+    }
+    lds_barrier();
+    if (tid < 128) {
+      const int r = tid >> 1, o = tid & 1;
+      const int row = tile * 64 + r;
+      float v = a.b2[o];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += red[w][r][o];
       if (row < U) a.out[(int64_t)row * 2 + o] = v;
     }
   }
 }
 
 template <typename K>
-static int launch_lds(K kern, const MlpArgs& a, size_t lds, int per_cu, int num_cus, hipStream_t s) {
+static int launch_lds(K kern, const MlpArgs& a, size_t lds, int per_cu, int num_cus, hipStream_t s,
+                      int threads) {
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
-  hipLaunchKernelGGL(kern, dim3(num_cus * per_cu), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(num_cus * per_cu), dim3(threads), lds, s, a);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+// Waves per block of the register-resident perceptron: 8 (two per SIMD, so
+// that one wave's conversions and LDS reads overlap the other's matrix
+// operations) when the hidden units split evenly, else 4.
+constexpr int kMlpWaves = 8;
+
+template <int NTH4, int K2>
+static int launch_split(const MlpArgs& a, int num_cus, hipStream_t s) {
+  constexpr size_t lds = 2 * (size_t)64 * K2 * 4;
+  if constexpr (kMlpWaves == 8 && NTH4 % 2 == 0)
+    return launch_lds(k_mlp_split<8, NTH4 / 2, K2>, a, lds, 1, num_cus, s, 512);
+  else
+    return launch_lds(k_mlp_split<4, NTH4, K2>, a, lds, 1, num_cus, s, 256);
+}
+
+template <int FORM, int NTH4, int K2, int NBUF>
+static int launch_res(const MlpArgs& a, int num_cus, hipStream_t s) {
+  constexpr size_t lds = (size_t)NBUF * 64 * (FORM == 0 ? K2 * 2 : K2 * 4);
+  if constexpr (kMlpWaves == 8 && NTH4 % 2 == 0)
+    return launch_lds(k_mlp_res<FORM, 8, NTH4 / 2, K2, NBUF>, a, lds, 1, num_cus, s, 512);
+  else
+    return launch_lds(k_mlp_res<FORM, 4, NTH4, K2, NBUF>, a, lds, 1, num_cus, s, 256);
 }
 
 template <int NTH>
 static int launch_nth(const MlpArgs& a, int rows, int num_cus, hipStream_t s) {
   if (rows == kRowsBF16) {
-    // W1 of the wave's hidden units in registers when it fits (<= 128 VGPRs)
+    // W1 of the wave's hidden units in registers when it fits
     if constexpr (NTH <= 4) {
-      if (a.K2 == 256) return launch_lds(k_mlp_res<0, NTH, 256, 3>, a, 3 * 64 * 512, 1, num_cus, s);
+      if (a.K2 == 256) return launch_res<0, NTH, 256, 3>(a, num_cus, s);
     }
     if constexpr (NTH <= 8) {
-      if (a.K2 == 128) return launch_lds(k_mlp_res<0, NTH, 128, 4>, a, 4 * 64 * 256, 1, num_cus, s);
+      if (a.K2 == 128) return launch_res<0, NTH, 128, 4>(a, num_cus, s);
     }
     hipLaunchKernelGGL(k_mlp_bf16<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
   } else if (rows == kRowsSplit16) {
     // shapes admitted by mlp_rows_split()
     if constexpr (NTH <= 4) {
-      if (a.K2 == 256) return launch_lds(k_mlp_res<1, NTH, 256, 2>, a, 2 * 64 * 1024, 1, num_cus, s);
+      if (a.K2 == 256) return launch_split<NTH, 256>(a, num_cus, s);
     }
     if constexpr (NTH <= 6) {
-      if (a.K2 == 128) return launch_lds(k_mlp_res<1, NTH, 128, 3>, a, 3 * 64 * 512, 1, num_cus, s);
+      if (a.K2 == 128) return launch_split<NTH, 128>(a, num_cus, s);
     }
     if constexpr (NTH <= 8) {
-      if (a.K2 == 64) return launch_lds(k_mlp_res<1, NTH, 64, 4>, a, 4 * 64 * 256, 1, num_cus, s);
+      if (a.K2 == 64) return launch_split<NTH, 64>(a, num_cus, s);
     }
     return VECKM_E_INVAL;
   } else {
-    if (a.K2 == 256) return launch_lds(k_mlp_f32<NTH, 256>, a, 2 * 64 * 256 * 4, 1, num_cus, s);
-    if (a.K2 == 128) return launch_lds(k_mlp_f32<NTH, 128>, a, 2 * 64 * 128 * 4, 2, num_cus, s);
+    if (a.K2 == 256) return launch_lds(k_mlp_f32<NTH, 256>, a, 2 * 64 * 256 * 4, 1, num_cus, s, 256);
+    if (a.K2 == 128) return launch_lds(k_mlp_f32<NTH, 128>, a, 2 * 64 * 128 * 4, 2, num_cus, s, 256);
     hipLaunchKernelGGL(k_mlp_f32_any<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
   }
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;

@@ -193,21 +193,33 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t) {
 }
 
 // Brick and number of phase-table slabs buffered in LDS: the largest brick
-// that fits beside three slabs, else beside two.  Larger bricks amortise the
-// window halo and give longer chunks of rows.
+// that fits beside at least three slabs (with as many as fit, up to four),
+// else the largest beside two.  Larger bricks amortise the window halo and
+// give longer chunks of rows; deeper slab buffering hides the latency of the
+// table copies.
 void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick,
                    int* nbuf) {
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
                         {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}, {4, 4, 1}};
   const int na = precision == VECKM_FP32 ? 4 : 2;
   const bool even = (na * (d / 16) * 64) % (encode_waves() * 64) == 0;  // copies split evenly
-  for (int nb = even ? 3 : 2; nb >= 2; --nb)
+  auto fits = [&](const Brick& b, int nb) {
+    return encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
+  };
+  if (even)
     for (const Brick& b : cand)
-      if (encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024) {
-        *brick = b;
-        *nbuf = nb;
-        return;
-      }
+      for (int nb = kMaxSlabBuffers; nb >= 3; --nb)
+        if (fits(b, nb)) {
+          *brick = b;
+          *nbuf = nb;
+          return;
+        }
+  for (const Brick& b : cand)
+    if (fits(b, 2)) {
+      *brick = b;
+      *nbuf = 2;
+      return;
+    }
   *brick = Brick{4, 4, 1};
   *nbuf = 2;
 }

@@ -13,6 +13,7 @@ namespace veckm {
 constexpr int kMaxRxy = 12;
 constexpr int kMaxRt = 6;
 constexpr int kKStep = 32;  // K elements per MFMA k-step (16x16x32 f16)
+constexpr int kMaxSlabBuffers = 4;  // phase-table slabs the encoder keeps in LDS (2..4)
 
 // Device-side input error bits (OR-ed into a device int).
 constexpr int kErrRange = 1;     // event outside sensor / time window, or |p| != 1
