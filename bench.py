@@ -192,7 +192,7 @@ def serving_run(vk, seconds, pool=3):
 KERNEL_SOURCES = {  # kernel name prefix (template form) -> source file it is built from
     "k_encode<4": "paper_2504_19417_amd/csrc/kernels_encode.hip",   # FP32 form encoder
     "k_encode<2": "paper_2504_19417_amd/csrc/kernels_encode.hip",   # FP16 form encoder
-    "k_mlp_res<1": "paper_2504_19417_amd/csrc/kernels_mlp.hip",     # FP32 form perceptron
+    "k_mlp_split<": "paper_2504_19417_amd/csrc/kernels_mlp.hip",    # FP32 form perceptron
     "k_mlp_res<0": "paper_2504_19417_amd/csrc/kernels_mlp.hip",     # FP16 form perceptron
 }
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
@@ -251,6 +251,49 @@ def _find_csv(d, suffix):
     raise FileNotFoundError("no *%s under %s" % (suffix, d))
 
 
+PROFILE_WORKLOAD = ("1M-event slice (346x260x50, D=128, r=5/3, perceptron 256-256-2), "
+                    "FP32 and FP16/BF16 forms")
+
+
+def summarize_kernels(stats_dir, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    rows = list(csv.DictReader(open(_find_csv(stats_dir, "kernel_stats.csv"))))
+    out = ["# Kernel times: " + PROFILE_WORKLOAD, "",
+           "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
+    out += ["    " + c for c in command.split(" ; ")]
+    out += ["", "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `<4, ...>` "
+            "encoder and `k_mlp_split` belong to the FP32 form, `<2, ...>` encoder and "
+            "`k_mlp_res<0, ...>` to the FP16/BF16 form; the small kernels serve both.  "
+            "`__amd_rocclr_*` are runtime copies and fills outside the steps.", "",
+            "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+            "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f %% |" % (
+            r["Name"].replace("|", "\\|"), r["Calls"], float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def traffic_markdown(rec):
+    out = ["# HBM traffic per launch: " + PROFILE_WORKLOAD, "",
+           "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
+    out += ["    " + c for c in rec["command"].split(" ; ")]
+    out += ["", "Calibration: the same counters on a plain device copy of known size "
+            "(`torch.neg` of a 1 GiB float32 buffer into another: 1 GiB read, 1 GiB written) "
+            "read FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per dispatch, so fetched "
+            "bytes are scaled by %.4f and written bytes by %.4f.  The counters see the L2's "
+            "traffic to the memory fabric (Infinity Cache hits included)."
+            % (rec["copy_bytes"] / 1024 / rec["fetch_scale"], rec["copy_bytes"] / 1024 / rec["write_scale"],
+               rec["fetch_scale"], rec["write_scale"]), "",
+            "| kernel | dispatches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | bytes, scaled |",
+            "|---|---:|---:|---:|---:|"]
+    for k, v in rec["all"].items():
+        out.append("| `%s` | %d | %.1f | %.1f | %d |" % (k.replace("|", "\\|")[:110], v["dispatches"],
+                                                      v["fetch_kib"], v["write_kib"], v["hbm_bytes"]))
+    return "\n".join(out) + "\n"
+
+
 def summarize_traffic(fetch_dir, write_dir, command):
     """Writes the traffic summary: per-launch FETCH_SIZE and WRITE_SIZE (KiB)
     of each kernel, scaled by what the same counters read for the 1 GiB
@@ -295,13 +338,23 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
                          "into profiles/traffic.json and exit (no GPU needed)")
-    ap.add_argument("--command", default="", help="command recorded with --summarize-traffic")
+    ap.add_argument("--summarize-kernels", metavar="STATS_DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run into "
+                         "profiles/kernels_slice1m.md and exit (no GPU needed)")
+    ap.add_argument("--command", default="", help="commands recorded with the summaries "
+                                                  "(separated by ' ; ')")
     args = ap.parse_args()
-    if args.summarize_traffic:
-        rec = summarize_traffic(*args.summarize_traffic, args.command)
-        with open(TRAFFIC_JSON, "w") as f:
-            json.dump(rec, f, indent=1)
-        print(json.dumps(rec["kernels"], indent=1))
+    if args.summarize_traffic or args.summarize_kernels:
+        if args.summarize_traffic:
+            rec = summarize_traffic(*args.summarize_traffic, args.command)
+            with open(TRAFFIC_JSON, "w") as f:
+                json.dump(rec, f, indent=1)
+            with open(os.path.join(ROOT, "profiles", "traffic_slice1m.md"), "w") as f:
+                f.write(traffic_markdown(rec))
+            print(json.dumps(rec["kernels"], indent=1))
+        if args.summarize_kernels:
+            with open(os.path.join(ROOT, "profiles", "kernels_slice1m.md"), "w") as f:
+                f.write(summarize_kernels(args.summarize_kernels, args.command))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -339,7 +392,7 @@ def main():
                        peak=PEAK["fp16_TFLOPs"], kernel="k_encode<4"),
         # FP32-form perceptron: fp16 hi/lo operand pairs on the fp16 matrix cores
         "mlp": dict(ms=st32["mlp"], flops=mlp_flops_per_row(w.d, w.hidden) * rows,
-                    peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_res<1"),
+                    peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_split<"),
     }
     dom = max(cand, key=lambda k: cand[k]["ms"])
     c = cand[dom]
