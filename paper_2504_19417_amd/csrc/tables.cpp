@@ -193,10 +193,11 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t) {
 }
 
 // Brick and number of phase-table slabs buffered in LDS: the largest brick
-// that fits beside at least three slabs (with as many as fit, up to four),
-// else the largest beside two.  Larger bricks amortise the window halo and
-// give longer chunks of rows; deeper slab buffering hides the latency of the
-// table copies.
+// that fits beside two slabs, then as many slabs (up to four) as fit beside
+// it.  Larger bricks amortise the window halo, fill the row chunks better and
+// cut the number of passes over the table; extra slabs hide the latency of
+// the table copies (three or four need the copies split evenly over the
+// waves).
 void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick,
                    int* nbuf) {
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
@@ -206,18 +207,15 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
   auto fits = [&](const Brick& b, int nb) {
     return encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
   };
-  if (even)
-    for (const Brick& b : cand)
-      for (int nb = kMaxSlabBuffers; nb >= 3; --nb)
-        if (fits(b, nb)) {
-          *brick = b;
-          *nbuf = nb;
-          return;
-        }
   for (const Brick& b : cand)
     if (fits(b, 2)) {
       *brick = b;
       *nbuf = 2;
+      for (int nb = even ? kMaxSlabBuffers : 2; nb > 2; --nb)
+        if (fits(b, nb)) {
+          *nbuf = nb;
+          break;
+        }
       return;
     }
   *brick = Brick{4, 4, 1};
