@@ -76,9 +76,13 @@ typedef struct veckm_params {
   int32_t rx, ry;        /* spatial window radii delta-x, delta-y in pixels (Eqn. 1),
                             each in [0, 12]                                       */
   int32_t rt;            /* temporal window radius in bins, in [0, 6]: neighbours
-                            also satisfy |t_k - t_q| <= rt.  The paper's Eqn. 1
-                            bounds only x and y (the whole slice in time); a slice
-                            of nbins <= rt + 1 bins reproduces that exactly       */
+                            also satisfy |t_k - t_q| <= rt.  -1: no temporal
+                            bound, the neighbourhood of Eqn. 1 as written (the
+                            whole slice in time), computed in the staged 2-D
+                            form of Algorithm 1 (per-pixel temporal phase sums,
+                            Eqns. 14-15; separable window sums, Eqns. 16-17), in
+                            fp32 in both precisions, with max_bins <= 1024, no
+                            per-voxel event limit, single-slice calls only      */
   int32_t d;             /* complex RFF dimension D: 16, 32, 48, 64, 128 or 256   */
   int32_t max_bins;      /* largest nbins accepted by a compute call               */
   int32_t precision;     /* VECKM_FP32 or VECKM_FP16                               */
@@ -125,7 +129,8 @@ int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden);
    receives k_count x d x 4 uint16 fp16 bit patterns (cos hi, cos lo, sin hi,
    sin lo) of theta = A[j] . (dx, dy, dt), with hi = fp16(cos) rounded to
    nearest even and lo = fp16(cos - hi); the centre entry stores cos = 1/2
-   (it is met twice, as +o and -o).  Returns VECKM_OK or VECKM_E_INVAL. */
+   (it is met twice, as +o and -o).  Returns VECKM_OK or VECKM_E_INVAL (also
+   for rt = -1, whose form has no such table). */
 int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* offsets,
                        uint16_t* phase_bits);
 
@@ -173,9 +178,9 @@ int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
    event order (emb: device, total n x 2D float32; flow: device, total n x 2
    float32).  The result for each slice is bit-identical to encoding that
    slice alone.  `slices` is host memory and is copied before return.
-   Returns VECKM_E_INVAL for non-contiguous slices or bad sizes, VECKM_E_RANGE
-   when the batch exceeds max_events, max_voxels or the sensor / max_bins
-   limits. */
+   Returns VECKM_E_INVAL for non-contiguous slices or bad sizes, or for a
+   context with rt = -1, VECKM_E_RANGE when the batch exceeds max_events,
+   max_voxels or the sensor / max_bins limits. */
 int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                        const veckm_event* events, float* emb, void* stream);
 int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
@@ -243,7 +248,8 @@ typedef struct veckm_server veckm_server;
    veckm_create); `max_streams` streams may be open at once, each with up to
    `depth` (1..16) submitted slices not yet polled.  Returns VECKM_E_BUDGET if
    the server's device memory exceeds hbm_budget_bytes (a positive number),
-   plus the veckm_create errors. */
+   VECKM_E_INVAL for rt = -1 (batches need the bounded window), plus the
+   veckm_create errors. */
 int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, int32_t max_streams,
                         int32_t depth, veckm_server** out);
 

@@ -29,6 +29,8 @@ struct veckm_ctx {
   EncodeTables et;
   Workspace w;
   MlpWeights mw;
+  bool paper = false;  // no temporal bound: the staged 2-D pooling encoder
+  PaperTables pt;
   int max_slices = 1;
   std::vector<void*> allocs;
   std::vector<void*> mlp_allocs;
@@ -112,7 +114,13 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   const Sizes s = sizes_for(p, b);
   const int na = p->precision == VECKM_FP32 ? 4 : 2;
   int64_t bytes = 0;
-  bytes += s.V * (4 + 4 + 1) + s.P * 4;          // count, rank, qmark, pairs
+  if (p->rt < 0) {  // paper form: G, Hx, S grids, pixel counts, phase tables
+    const int64_t V2 = (int64_t)p->width * p->height;
+    bytes += 3 * 2 * (int64_t)p->d * V2 * 4 + 3 * V2 * 4;
+    bytes += (int64_t)(p->max_bins + 2 * p->rx + 2 * p->ry + 2) * p->d * 8;
+  }
+  bytes += s.V * (4 + 4 + 1);                     // count, rank, qmark
+  if (p->rt >= 0) bytes += s.P * 4;               // pair grid
   bytes += s.nb * s.bv * 4;                       // ulist
   bytes += (3 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
   bytes += s.n * (4 + 4);                         // vox, qmap
@@ -249,13 +257,14 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
                                                       : kRowsF32;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
-    const int rc = launch_prepare(bt, c->w, ev, queries, c->et, stream);
+    const int rc = launch_prepare(bt, c->w, ev, queries, c->et, !c->paper, stream);
     if (rc) return rc;
   }
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
-    const int rc = launch_encode(bt, c->w, c->et, rows == kRowsBF16 ? kRowsBF16 : kRowsF32,
-                                 c->num_cus, stream);
+    const int erows = rows == kRowsBF16 ? kRowsBF16 : kRowsF32;
+    const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, stream)
+                            : launch_encode(bt, c->w, c->et, erows, c->num_cus, stream);
     if (rc) return rc;
   }
   if (flow) {
@@ -320,8 +329,10 @@ int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
   if (hidden < 0) return VECKM_E_INVAL;
   Brick b;
   int nbuf;
-  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
-  choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &b, &nbuf);
+  const int rt_enc = params->rt < 0 ? 0 : params->rt;
+  const SlotTable st = make_slots(params->rx, params->ry, rt_enc);
+  choose_layout(params->rx, params->ry, rt_enc, params->d, params->precision, st.KP, &b, &nbuf);
+  if (params->rt < 0) b = Brick{32, 16, 8};
   return bytes_for(params, b, st.KP, hidden);
 }
 
@@ -329,7 +340,7 @@ int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* of
                        uint16_t* phase_bits) {
   const int rc = check_params(params);
   if (rc) return rc;
-  if (!k_count) return VECKM_E_INVAL;
+  if (!k_count || params->rt < 0) return VECKM_E_INVAL;
   const OffsetTable t = make_offsets(params->rx, params->ry, params->rt);
   *k_count = t.K;
   if (offsets) std::memcpy(offsets, t.off.data(), t.off.size() * sizeof(int32_t));
@@ -370,16 +381,21 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   c->p.A = c->A.data();
   c->max_slices = slices_of(params);
   EncodeTables& et = c->et;
-  const SlotTable st = make_slots(params->rx, params->ry, params->rt);
+  c->paper = params->rt < 0;
+  // the 3-D window tables (the paper form never runs that encoder: its
+  // tables are built with rt = 0 and only the brick numbering is used)
+  const int rt_enc = c->paper ? 0 : params->rt;
+  const SlotTable st = make_slots(params->rx, params->ry, rt_enc);
   et.K = st.K;
   et.KP = st.KP;
   et.na = params->precision == VECKM_FP32 ? 4 : 2;
   et.rx = params->rx;
   et.ry = params->ry;
-  et.rt = params->rt;
+  et.rt = rt_enc;
   et.d = params->d;
-  choose_layout(params->rx, params->ry, params->rt, params->d, params->precision, st.KP, &et.brick,
+  choose_layout(params->rx, params->ry, rt_enc, params->d, params->precision, st.KP, &et.brick,
                 &et.nbuf);
+  if (c->paper) et.brick = Brick{32, 16, 8};
   const std::vector<uint16_t> frag = make_slot_fragments(st, c->A.data(), params->d, et.na);
   const std::vector<int32_t> runs = make_run_offsets(st, et.brick, params->rx, params->ry);
   const std::vector<uint16_t> wts = make_slot_weights(st);
@@ -396,7 +412,7 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &dwts, wts.size());
   rc = rc ? rc : dalloc(c->allocs, &dzeros, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
-  rc = rc ? rc : dalloc(c->allocs, &w.pairs, (size_t)s.P);
+  if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &w.pairs, (size_t)s.P);
   rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
@@ -410,6 +426,32 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.plan, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.err, 1);
   rc = rc ? rc : dalloc(c->allocs, &c->table_dev, (size_t)kRing * c->max_slices);
+  std::vector<float> ttab, pxt, pyt;
+  float *dtt = nullptr, *dpx = nullptr, *dpy = nullptr;
+  if (!rc && c->paper) {
+    const int64_t V2 = (int64_t)params->width * params->height;
+    const int D = params->d;
+    make_paper_tables(c->A.data(), D, params->rx, params->ry, params->max_bins, &ttab, &pxt, &pyt);
+    rc = rc ? rc : dalloc(c->allocs, &w.G, (size_t)(2 * D * V2));
+    rc = rc ? rc : dalloc(c->allocs, &w.Hx, (size_t)(2 * D * V2));
+    rc = rc ? rc : dalloc(c->allocs, &w.S, (size_t)(2 * D * V2));
+    rc = rc ? rc : dalloc(c->allocs, &w.cnt2, (size_t)V2);
+    rc = rc ? rc : dalloc(c->allocs, &w.nbx, (size_t)V2);
+    rc = rc ? rc : dalloc(c->allocs, &w.nbox, (size_t)V2);
+    rc = rc ? rc : dalloc(c->allocs, &dtt, ttab.size());
+    rc = rc ? rc : dalloc(c->allocs, &dpx, pxt.size());
+    rc = rc ? rc : dalloc(c->allocs, &dpy, pyt.size());
+    if (!rc && (hipMemcpy(dtt, ttab.data(), ttab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dpx, pxt.data(), pxt.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dpy, pyt.data(), pyt.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+      rc = VECKM_E_HIP;
+    c->pt.ttab = dtt;
+    c->pt.pxt = dpx;
+    c->pt.pyt = dpy;
+    c->pt.d = D;
+    c->pt.rx = params->rx;
+    c->pt.ry = params->ry;
+  }
   if (!rc && hipHostMalloc(reinterpret_cast<void**>(&c->table_host),
                            (size_t)kRing * c->max_slices * sizeof(SliceDesc)) != hipSuccess) {
     c->table_host = nullptr;
@@ -534,7 +576,7 @@ int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
 
 int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                        const veckm_event* events, float* emb, void* stream) {
-  if (!ctx) return VECKM_E_INVAL;
+  if (!ctx || ctx->paper) return VECKM_E_INVAL;
   Batch bt;
   int slot;
   int rc = multi_batch(ctx, slices, count, events, emb, stream, &bt, &slot);
@@ -546,7 +588,7 @@ int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
 
 int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                      const veckm_event* events, float* flow, void* stream) {
-  if (!ctx) return VECKM_E_INVAL;
+  if (!ctx || ctx->paper) return VECKM_E_INVAL;
   if (ctx->mw.hidden == 0) return VECKM_E_STATE;
   Batch bt;
   int slot;

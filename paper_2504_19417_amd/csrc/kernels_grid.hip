@@ -255,7 +255,7 @@ static int fill_grid(int64_t n) {
 }
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
-                   const int32_t* queries, const EncodeTables& et, void* stream) {
+                   const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
   if (queries)
@@ -263,8 +263,9 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   if (bt.n > 0)
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
-  hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs,
-                     w.err);
+  if (pairs)
+    hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs,
+                       w.err);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);

@@ -281,6 +281,7 @@ int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, in
   if (p.max_slices < max_streams) p.max_slices = max_streams;
   int rc = veckm_params_check(&p);
   if (rc) return rc;
+  if (p.rt < 0) return VECKM_E_INVAL;  // batches need the temporally bounded encoder
   const int64_t ws = veckm_workspace_bytes(&p, 512);
   if (ws < 0) return (int)ws;
   const int64_t bytes = ws + p.max_events * (int64_t)(sizeof(veckm_event) + 2 * sizeof(float));

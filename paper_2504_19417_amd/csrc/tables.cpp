@@ -27,7 +27,8 @@ int check_params(const veckm_params* p) {
   if (!p || !p->A) return VECKM_E_INVAL;
   if (p->width < 1 || p->height < 1 || p->max_bins < 1) return VECKM_E_INVAL;
   if (p->rx < 0 || p->rx > kMaxRxy || p->ry < 0 || p->ry > kMaxRxy) return VECKM_E_INVAL;
-  if (p->rt < 0 || p->rt > kMaxRt) return VECKM_E_INVAL;
+  if (p->rt < -1 || p->rt > kMaxRt) return VECKM_E_INVAL;
+  if (p->rt == -1 && p->max_bins > kMaxPaperBins) return VECKM_E_INVAL;
   if (!valid_d(p->d)) return VECKM_E_INVAL;
   if (p->precision != VECKM_FP32 && p->precision != VECKM_FP16) return VECKM_E_INVAL;
   if (p->max_events < 1 || p->max_events > (int64_t)std::numeric_limits<int32_t>::max())
@@ -117,6 +118,23 @@ void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out
       o[2] = sh;
       o[3] = fp16_bits_rne(s - fp16_to_double(sh));
     }
+}
+
+void make_paper_tables(const double* A, int d, int rx, int ry, int max_bins,
+                       std::vector<float>* ttab, std::vector<float>* pxt,
+                       std::vector<float>* pyt) {
+  auto fill = [&](std::vector<float>* out, int lo, int hi, int col) {
+    out->assign((size_t)(hi - lo + 1) * d * 2, 0.f);
+    for (int o = lo; o <= hi; ++o)
+      for (int j = 0; j < d; ++j) {
+        const double th = A[3 * j + col] * (double)o;
+        (*out)[((size_t)(o - lo) * d + j) * 2 + 0] = (float)std::cos(th);
+        (*out)[((size_t)(o - lo) * d + j) * 2 + 1] = (float)std::sin(th);
+      }
+  };
+  fill(ttab, 0, max_bins - 1, 2);
+  fill(pxt, -rx, rx, 0);
+  fill(pyt, -ry, ry, 1);
 }
 
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {

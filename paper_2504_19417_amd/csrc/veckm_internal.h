@@ -117,6 +117,22 @@ struct Workspace {
   int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2] = non-empty bricks
   int32_t* err = nullptr;       // error bits
   int64_t vmax = 0, pmax = 0, nmax = 0, bmax = 0;
+  // paper form (no temporal bound) only
+  float* G = nullptr;           // [2D][H][W] per-pixel temporal phase sums (Re planes, Im planes)
+  float* Hx = nullptr;          // [2D][H][W] after the x pass
+  float* S = nullptr;           // [H][W][2D] window sums, pixel-major
+  int32_t* cnt2 = nullptr;      // [H][W] events per pixel
+  int32_t* nbx = nullptr;       // [H][W] x box sums of cnt2
+  int32_t* nbox = nullptr;      // [H][W] window counts
+};
+
+// Phase tables of the paper form: (cos, sin) of A_t[j] t for the bins of a
+// slice, of A_x[j] dx and of A_y[j] dy over the window (FP64 on the host).
+struct PaperTables {
+  const float* ttab = nullptr;  // [max_bins][D][cos, sin]
+  const float* pxt = nullptr;   // [2 rx + 1][D][cos, sin]
+  const float* pyt = nullptr;   // [2 ry + 1][D][cos, sin]
+  int d = 0, rx = 0, ry = 0;
 };
 
 struct EncodeTables {
@@ -149,7 +165,15 @@ struct MlpWeights {
 };
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
-                   const int32_t* queries, const EncodeTables& et, void* stream);
+                   const int32_t* queries, const EncodeTables& et, bool pairs, void* stream);
+int launch_paper_encode(const Batch& bt, const Workspace& w, const PaperTables& pt,
+                        const Brick& brick, int rows, void* stream);
+size_t paper_pooly_lds(int d);
+// (cos, sin) tables of the paper form, FP64 then rounded to fp32: time bins
+// 0 .. max_bins - 1, dx in [-rx, rx], dy in [-ry, ry]; each [offset][d][2].
+void make_paper_tables(const double* A, int d, int rx, int ry, int max_bins,
+                       std::vector<float>* ttab, std::vector<float>* pxt, std::vector<float>* pyt);
+constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
                   int num_cus, void* stream);
 int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream);

@@ -69,8 +69,12 @@ def _lognormal_sizes(rng, count, median, sigma, lo, hi):
 
 
 def workloads() -> dict:
-    """The five workloads: tiny CPU case, 1M-event FP32 slice, 5M-event
-    precision slice, 64-slice batch and the 32-stream serving mix."""
+    """The workloads: tiny CPU case, 1M-event FP32 slice, 5M-event precision
+    slice, 64-slice batch (the 32-stream serving mix is `serving_streams`),
+    and the paper's own form at its training recipes (640x480, D=64, no
+    temporal bound, delta-t = half the slice): radius 8 over 32 ms and radius
+    10 over 24 ms, each 0.5M events (the size of the paper's worked timing
+    example)."""
     w = {}
     w["tiny"] = Workload(
         "tiny", [SliceSpec(346, 260, 25, 20_000, 8, seed=1001)],
@@ -96,6 +100,16 @@ def workloads() -> dict:
     w["batch64"] = Workload("batch64", slices, d=128, rx=5, ry=5, rt=3, hidden=256,
                             precision="fp16",
                             notes="64 slices, lognormal 10k-500k events, 346x260 / 640x480")
+    w["paper_k8"] = Workload(
+        "paper_k8", [SliceSpec(640, 480, 32, 500_000, 32, seed=1006)],
+        d=64, rx=8, ry=8, rt=-1, hidden=128,
+        notes="640x480, 0.5M events, 32 edges, 32 bins (32 ms, delta-t 16 ms), D=64, "
+              "delta-x = delta-y = 8, no temporal bound, MLP 128-128-2 FP32")
+    w["paper_k10"] = Workload(
+        "paper_k10", [SliceSpec(640, 480, 24, 500_000, 32, seed=1007)],
+        d=64, rx=10, ry=10, rt=-1, hidden=128,
+        notes="640x480, 0.5M events, 32 edges, 24 bins (24 ms, delta-t 12 ms), D=64, "
+              "delta-x = delta-y = 10, no temporal bound, MLP 128-128-2 FP32")
     return w
 
 

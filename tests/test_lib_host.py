@@ -48,8 +48,12 @@ def test_params_check():
     assert veckm.veckm_params_check(_params()) == veckm.VECKM_OK
     for d in (16, 32, 48, 64, 128, 256):
         assert veckm.veckm_params_check(_params(d=d)) == veckm.VECKM_OK
-    bad = [dict(width=0), dict(height=-1), dict(rx=-1), dict(ry=13), dict(rt=7), dict(rt=-1),
-           dict(max_bins=0), dict(max_events=0), dict(max_events=1 << 40), dict(precision=5)]
+    # rt = -1 is the paper's unbounded window (up to 1024 bins per slice)
+    assert veckm.veckm_params_check(_params(rt=-1)) == veckm.VECKM_OK
+    assert veckm.veckm_params_check(_params(rt=-1, max_bins=1024)) == veckm.VECKM_OK
+    bad = [dict(width=0), dict(height=-1), dict(rx=-1), dict(ry=13), dict(rt=7), dict(rt=-2),
+           dict(rt=-1, max_bins=1025), dict(max_bins=0), dict(max_events=0),
+           dict(max_events=1 << 40), dict(precision=5)]
     for b in bad:
         assert veckm.veckm_params_check(_params(**b)) == veckm.VECKM_E_INVAL, b
     for d in (8, 40, 96, 512):
@@ -120,6 +124,18 @@ def test_workspace_bytes():
     big = veckm.veckm_workspace_bytes(_params(max_events=1_000_000), 0)
     assert big > b0
     assert veckm.veckm_workspace_bytes(_params(d=8), 0) == veckm.VECKM_E_INVAL
+    # the paper form holds three D-wide complex fp32 pixel grids (G, x pass, S)
+    bp = veckm.veckm_workspace_bytes(_params(rt=-1), 0)
+    assert bp > 3 * 2 * 64 * 346 * 260 * 4
+
+
+def test_paper_form_has_no_offset_table_and_no_server():
+    with pytest.raises(veckm.VeckmError) as e:
+        veckm.veckm_offset_table(_params(rt=-1), with_phases=False)
+    assert e.value.code == veckm.VECKM_E_INVAL
+    with pytest.raises(veckm.VeckmError) as e:
+        veckm.veckm_server_create(_params(rt=-1), 1 << 40, 4, 2)
+    assert e.value.code == veckm.VECKM_E_INVAL
 
 
 def test_create_without_device():

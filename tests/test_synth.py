@@ -15,6 +15,11 @@ def test_workload_table():
     sizes = np.array([s.n for s in b])
     assert sizes.min() >= 10_000 and sizes.max() <= 500_000
     assert {(s.width, s.height) for s in b} == {(346, 260), (640, 480)}
+    for name, r, T in (("paper_k8", 8, 32), ("paper_k10", 10, 24)):
+        p = w[name]
+        assert (p.rx, p.ry, p.rt, p.d) == (r, r, -1, 64)
+        s = p.slices[0]
+        assert (s.width, s.height, s.nbins, s.n) == (640, 480, T, 500_000)
 
 
 def test_slice_is_deterministic_and_in_range():
