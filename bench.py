@@ -49,12 +49,12 @@ def mlp_flops_per_row(d, hidden):
 def paper_encode_bytes(W, H, T, d, rows, row_bytes):
     """Algorithmic HBM bytes of the paper form's encode stage (no temporal
     bound): the temporal phase pass reads the T x H x W count grid and writes
-    the complex D-wide pixel grid G; the x and y window passes each read and
-    write one such grid; the box sums read and write four int32 pixel grids;
-    the row pass reads S (8D bytes) and writes one row per query voxel."""
+    the complex D-wide fp32 pixel grid G; the fused window pass reads G and
+    writes S; the box sums read and write four int32 pixel grids; the row
+    pass reads S (8D bytes) and writes one row per query voxel."""
     V2 = W * H
     grid = 2 * d * 4 * V2
-    return 4 * T * V2 + grid + 2 * grid + 2 * grid + 4 * 4 * V2 + rows * (2 * d * 4 + row_bytes)
+    return 4 * T * V2 + grid + 2 * grid + 4 * 4 * V2 + rows * (2 * d * 4 + row_bytes)
 
 
 def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=None):
@@ -367,7 +367,7 @@ def paper_main(args, name):
     cand = {
         "encode": dict(ms=st32["encode"], bound="hbm", amount=enc_bytes / 1e9,
                        peak=PEAK["hbm_GBps"], unit="GB/s",
-                       kernel="paper encode stage (k_tphase, k_poolx, k_pooly, k_boxx, k_boxy, "
+                       kernel="paper encode stage (k_tphase, k_pool2d, k_boxx, k_boxy, "
                               "k_paper_rows)"),
         "mlp": dict(ms=st32["mlp"], bound="mfma", amount=mlp_flops_per_row(w.d, w.hidden) * rows / 1e12,
                     peak=PEAK["fp16_TFLOPs"], unit="TFLOP/s", kernel="k_mlp_split<"),

@@ -32,9 +32,14 @@ CFLAGS = [
 ]
 
 
+# Per-source additions: the paper-form window pass unrolls its row loop once
+# per ring slot (up to 25), beyond the default limit of a forced full unroll.
+EXTRA_FLAGS = {"kernels_paper.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + CFLAGS + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

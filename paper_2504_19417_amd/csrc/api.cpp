@@ -114,10 +114,10 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   const Sizes s = sizes_for(p, b);
   const int na = p->precision == VECKM_FP32 ? 4 : 2;
   int64_t bytes = 0;
-  if (p->rt < 0) {  // paper form: G, Hx, S grids, pixel counts, phase tables
+  if (p->rt < 0) {  // paper form: G, S grids, pixel counts, phase tables
     const int64_t V2 = (int64_t)p->width * p->height;
-    bytes += 3 * 2 * (int64_t)p->d * V2 * 4 + 3 * V2 * 4;
-    bytes += (int64_t)(p->max_bins + 2 * p->rx + 2 * p->ry + 2) * p->d * 8;
+    bytes += 2 * 2 * (int64_t)p->d * V2 * 4 + 3 * V2 * 4 + s.U * 4;
+    bytes += (int64_t)(p->max_bins + p->width + p->height) * p->d * 8;
   }
   bytes += s.V * (4 + 4 + 1);                     // count, rank, qmark
   if (p->rt >= 0) bytes += s.P * 4;               // pair grid
@@ -263,7 +263,7 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
     const int erows = rows == kRowsBF16 ? kRowsBF16 : kRowsF32;
-    const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, stream)
+    const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, c->num_cus, stream)
                             : launch_encode(bt, c->w, c->et, erows, c->num_cus, stream);
     if (rc) return rc;
   }
@@ -426,28 +426,29 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.plan, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.err, 1);
   rc = rc ? rc : dalloc(c->allocs, &c->table_dev, (size_t)kRing * c->max_slices);
-  std::vector<float> ttab, pxt, pyt;
-  float *dtt = nullptr, *dpx = nullptr, *dpy = nullptr;
+  std::vector<float> ttab, xtab, ytab;
+  float *dtt = nullptr, *dxt = nullptr, *dyt = nullptr;
   if (!rc && c->paper) {
     const int64_t V2 = (int64_t)params->width * params->height;
     const int D = params->d;
-    make_paper_tables(c->A.data(), D, params->rx, params->ry, params->max_bins, &ttab, &pxt, &pyt);
+    make_paper_tables(c->A.data(), D, params->width, params->height, params->max_bins, &ttab,
+                      &xtab, &ytab);
     rc = rc ? rc : dalloc(c->allocs, &w.G, (size_t)(2 * D * V2));
-    rc = rc ? rc : dalloc(c->allocs, &w.Hx, (size_t)(2 * D * V2));
     rc = rc ? rc : dalloc(c->allocs, &w.S, (size_t)(2 * D * V2));
     rc = rc ? rc : dalloc(c->allocs, &w.cnt2, (size_t)V2);
     rc = rc ? rc : dalloc(c->allocs, &w.nbx, (size_t)V2);
     rc = rc ? rc : dalloc(c->allocs, &w.nbox, (size_t)V2);
+    rc = rc ? rc : dalloc(c->allocs, &w.rowvox, (size_t)s.U);
     rc = rc ? rc : dalloc(c->allocs, &dtt, ttab.size());
-    rc = rc ? rc : dalloc(c->allocs, &dpx, pxt.size());
-    rc = rc ? rc : dalloc(c->allocs, &dpy, pyt.size());
+    rc = rc ? rc : dalloc(c->allocs, &dxt, xtab.size());
+    rc = rc ? rc : dalloc(c->allocs, &dyt, ytab.size());
     if (!rc && (hipMemcpy(dtt, ttab.data(), ttab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemcpy(dpx, pxt.data(), pxt.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemcpy(dpy, pyt.data(), pyt.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+                hipMemcpy(dxt, xtab.data(), xtab.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(dyt, ytab.data(), ytab.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       rc = VECKM_E_HIP;
     c->pt.ttab = dtt;
-    c->pt.pxt = dpx;
-    c->pt.pyt = dpy;
+    c->pt.xtab = dxt;
+    c->pt.ytab = dyt;
     c->pt.d = D;
     c->pt.rx = params->rx;
     c->pt.ry = params->ry;

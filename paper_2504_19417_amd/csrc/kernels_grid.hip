@@ -206,7 +206,8 @@ __global__ __launch_bounds__(1024) void k_brick_scan(const int32_t* __restrict__
 // One thread per query: the row of its voxel (or -1 for an invalid event).
 __global__ void k_qmap(const int32_t* __restrict__ queries, Batch bt, Brick b,
                        const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
-                       const int32_t* __restrict__ brick_off, int32_t* __restrict__ qmap) {
+                       const int32_t* __restrict__ brick_off, int32_t* __restrict__ qmap,
+                       int32_t* __restrict__ rowvox) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= bt.m) return;
   const int e = queries ? queries[i] : i;
@@ -222,7 +223,9 @@ __global__ void k_qmap(const int32_t* __restrict__ queries, Batch bt, Brick b,
   const SliceDesc s = slice_by_event(bt, e);
   const int x = v % s.W, y = (v / s.W) % s.H, t = v / (s.W * s.H);
   const int lb = ((t / b.bt) * s.nby + y / b.by) * s.nbx + x / b.bx;
-  qmap[i] = brick_off[s.brick_off + lb] + rank[s.grid_off + v];
+  const int r = brick_off[s.brick_off + lb] + rank[s.grid_off + v];
+  qmap[i] = r;
+  if (rowvox) rowvox[r] = v;  // every query of the voxel writes the same value
 }
 
 // One wavefront per query: copy its voxel's encoding row.
@@ -279,7 +282,8 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                      encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
-                       et.brick, w.vox, w.rank, w.brick_off, w.qmap);
+                       et.brick, w.vox, w.rank, w.brick_off, w.qmap,
+                       pairs ? nullptr : w.rowvox);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

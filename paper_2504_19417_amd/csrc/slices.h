@@ -8,7 +8,7 @@
 
 namespace veckm {
 
-__device__ inline SliceDesc slice_by_event(const Batch& b, int i) {
+__device__ inline SliceDesc slice_by_event(Batch b, int i) {  // by value: no private copy
   if (b.nslices == 1) return b.s0;
   int lo = 0, hi = b.nslices - 1;
   while (lo < hi) {
@@ -18,7 +18,7 @@ __device__ inline SliceDesc slice_by_event(const Batch& b, int i) {
   return b.table[lo];
 }
 
-__device__ inline SliceDesc slice_by_brick(const Batch& b, int gb) {
+__device__ inline SliceDesc slice_by_brick(Batch b, int gb) {
   if (b.nslices == 1) return b.s0;
   int lo = 0, hi = b.nslices - 1;
   while (lo < hi) {

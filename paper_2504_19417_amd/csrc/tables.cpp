@@ -120,9 +120,9 @@ void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out
     }
 }
 
-void make_paper_tables(const double* A, int d, int rx, int ry, int max_bins,
-                       std::vector<float>* ttab, std::vector<float>* pxt,
-                       std::vector<float>* pyt) {
+void make_paper_tables(const double* A, int d, int width, int height, int max_bins,
+                       std::vector<float>* ttab, std::vector<float>* xtab,
+                       std::vector<float>* ytab) {
   auto fill = [&](std::vector<float>* out, int lo, int hi, int col) {
     out->assign((size_t)(hi - lo + 1) * d * 2, 0.f);
     for (int o = lo; o <= hi; ++o)
@@ -133,8 +133,8 @@ void make_paper_tables(const double* A, int d, int rx, int ry, int max_bins,
       }
   };
   fill(ttab, 0, max_bins - 1, 2);
-  fill(pxt, -rx, rx, 0);
-  fill(pyt, -ry, ry, 1);
+  fill(xtab, 0, width - 1, 0);
+  fill(ytab, 0, height - 1, 1);
 }
 
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt) {

@@ -112,26 +112,27 @@ struct Workspace {
   int32_t* order = nullptr;     // bricks: non-empty bricks, most encoder chunks first
   int32_t* vox = nullptr;       // n: slice-local voxel of each event, -1 if invalid
   int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
+  int32_t* rowvox = nullptr;    // U: voxel of each row (paper form only)
   void* rows = nullptr;         // U x 2D encodings (fp32 or bf16)
   float* rowflow = nullptr;     // U x 2
   int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2] = non-empty bricks
   int32_t* err = nullptr;       // error bits
   int64_t vmax = 0, pmax = 0, nmax = 0, bmax = 0;
   // paper form (no temporal bound) only
-  float* G = nullptr;           // [2D][H][W] per-pixel temporal phase sums (Re planes, Im planes)
-  float* Hx = nullptr;          // [2D][H][W] after the x pass
-  float* S = nullptr;           // [H][W][2D] window sums, pixel-major
+  float* G = nullptr;           // [D/8][H][W][8] complex: per-pixel temporal phase sums
+  float* S = nullptr;           // [D/8][H][W][8] complex: window sums
   int32_t* cnt2 = nullptr;      // [H][W] events per pixel
   int32_t* nbx = nullptr;       // [H][W] x box sums of cnt2
   int32_t* nbox = nullptr;      // [H][W] window counts
 };
 
 // Phase tables of the paper form: (cos, sin) of A_t[j] t for the bins of a
-// slice, of A_x[j] dx and of A_y[j] dy over the window (FP64 on the host).
+// slice, of A_x[j] x over the sensor columns and of A_y[j] y over its rows
+// (FP64 on the host, rounded to fp32).
 struct PaperTables {
   const float* ttab = nullptr;  // [max_bins][D][cos, sin]
-  const float* pxt = nullptr;   // [2 rx + 1][D][cos, sin]
-  const float* pyt = nullptr;   // [2 ry + 1][D][cos, sin]
+  const float* xtab = nullptr;  // [width][D][cos, sin]
+  const float* ytab = nullptr;  // [height][D][cos, sin]
   int d = 0, rx = 0, ry = 0;
 };
 
@@ -167,12 +168,12 @@ struct MlpWeights {
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream);
 int launch_paper_encode(const Batch& bt, const Workspace& w, const PaperTables& pt,
-                        const Brick& brick, int rows, void* stream);
-size_t paper_pooly_lds(int d);
+                        const Brick& brick, int rows, int num_cus, void* stream);
 // (cos, sin) tables of the paper form, FP64 then rounded to fp32: time bins
-// 0 .. max_bins - 1, dx in [-rx, rx], dy in [-ry, ry]; each [offset][d][2].
-void make_paper_tables(const double* A, int d, int rx, int ry, int max_bins,
-                       std::vector<float>* ttab, std::vector<float>* pxt, std::vector<float>* pyt);
+// 0 .. max_bins - 1, columns 0 .. width - 1, rows 0 .. height - 1; each
+// [coordinate][d][2].
+void make_paper_tables(const double* A, int d, int width, int height, int max_bins,
+                       std::vector<float>* ttab, std::vector<float>* xtab, std::vector<float>* ytab);
 constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
                   int num_cus, void* stream);

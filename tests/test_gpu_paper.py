@@ -111,10 +111,11 @@ def test_paper_form_query_subset_and_empty(vk):
     c.close()
 
 
-def test_paper_form_isolated_and_single_pixel_exact(vk):
-    """An isolated event encodes to exactly (1, ..., 1 | 0, ..., 0); events
-    alone in one pixel at several bins give the mean of their relative
-    temporal phases (checked against the oracle)."""
+def test_paper_form_isolated_and_single_pixel(vk):
+    """An isolated event encodes to (1, ..., 1 | 0, ..., 0) up to the rounding
+    of its phase and the conjugate one (a few fp32 ulps); events alone in one
+    pixel at several bins give the mean of their relative temporal phases
+    (checked against the oracle)."""
     ev = np.array([[5, 5, 100, 1], [60, 40, 103, 1], [60, 40, 107, -1], [60, 40, 107, 1]],
                   np.int32)
     A = synth.draw_frequencies(16, 4, 4, -1, nbins=10)
@@ -122,7 +123,7 @@ def test_paper_form_isolated_and_single_pixel_exact(vk):
     c = vk.Context(80, 50, 4, 4, -1, A, 10, 4)
     emb, st = _run(c, ev, 100, 10)
     assert st == vk.VECKM_OK
-    assert np.array_equal(emb[0], np.r_[np.ones(16), np.zeros(16)].astype(np.float32))
+    assert np.abs(emb[0] - np.r_[np.ones(16), np.zeros(16)]).max() <= 4e-7
     emb_o, _ = oracle.encode(ev, A, 4, 4, -1)
     assert np.abs(emb[1:] - emb_o[1:]).max() <= 1e-6
     c.close()

@@ -124,9 +124,9 @@ def test_workspace_bytes():
     big = veckm.veckm_workspace_bytes(_params(max_events=1_000_000), 0)
     assert big > b0
     assert veckm.veckm_workspace_bytes(_params(d=8), 0) == veckm.VECKM_E_INVAL
-    # the paper form holds three D-wide complex fp32 pixel grids (G, x pass, S)
+    # the paper form holds two D-wide complex fp32 pixel grids (G, S)
     bp = veckm.veckm_workspace_bytes(_params(rt=-1), 0)
-    assert bp > 3 * 2 * 64 * 346 * 260 * 4
+    assert bp > 2 * 2 * 64 * 346 * 260 * 4
 
 
 def test_paper_form_has_no_offset_table_and_no_server():
