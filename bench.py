@@ -408,6 +408,8 @@ def paper_main(args, name):
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        copy_calibration(torch)
 
 
 def main():

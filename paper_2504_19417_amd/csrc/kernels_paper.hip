@@ -32,14 +32,15 @@
 
 namespace veckm {
 
-constexpr int kPF = 8;        // frequencies per group of the blocked pixel grids
-constexpr int kPoolW = 64;    // pixels per tile row of the window pass
+constexpr int kPF = 16;       // frequencies per group of the blocked pixel grids
+constexpr int kPoolW = 32;    // pixels per tile row of the window pass
+constexpr int kXcds = 8;      // workgroups are dealt round-robin to the 8 XCDs (own L2 each)
 constexpr int kPoolThreads = 256;
 constexpr int kStageF2 = (kPoolW + 2 * kMaxRxy) * kPF;  // complex values of one staged row
-constexpr int kPoolMaxTY = 256;  // output rows per column tile, at most
+constexpr int kPoolMaxTY = 128;  // output rows per column tile, at most
 
 // Blocked pixel grids (G and S): [D / kPF][H][W][kPF] complex (re, im
-// interleaved), so that one group of one pixel is 64 contiguous bytes and one
+// interleaved), so that one group of one pixel is one 128-byte line and one
 // tile row of one group is a contiguous run.
 
 __device__ inline uint16_t bf16_rne(float f) {
@@ -58,20 +59,23 @@ __device__ inline float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 
-// G per pixel: thread per (pixel, chunk of CF frequencies); the chunks of one
-// pixel run are adjacent blocks, so they share the count reads in the cache.
-// Most voxels are empty, and the loop skips them.  Chunk 0 also writes the
-// pixel's event count.
+// G per pixel: thread per (pixel, chunk of CF frequencies).  The chunks of
+// one pixel run go to the same XCD (block b runs on XCD b mod 8), so they
+// share the count reads in its L2.  Most voxels are empty, and the loop skips
+// them.  Chunk 0 also writes the pixel's event count.
 template <int CF>
-__global__ __launch_bounds__(256) void k_tphase(int W, int V2, int T, int D,
+__global__ __launch_bounds__(256) void k_tphase(int W, int V2, int T, int D, int npb,
                                                 const int32_t* __restrict__ count,
                                                 const float2* __restrict__ ttab,
                                                 const float2* __restrict__ xtab,
                                                 const float2* __restrict__ ytab,
                                                 float4* __restrict__ G, int32_t* __restrict__ cnt2) {
   const int nc = D / CF;
-  const int ch = blockIdx.x % nc;
-  const int p = (blockIdx.x / nc) * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x / kXcds;
+  const int ch = i % nc;
+  const int pb = (i / nc) * kXcds + blockIdx.x % kXcds;  // pixel block
+  if (pb >= npb) return;
+  const int p = pb * blockDim.x + threadIdx.x;
   if (p >= V2) return;
   float re[CF], im[CF];
 #pragma unroll
@@ -123,7 +127,7 @@ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x
 // zero outside the image) in LDS, takes its x sum, and keeps it in a register
 // ring of the last 2 RY + 1 rows; the y sum over the ring gives one output
 // row, turned back by the output pixel's conjugate spatial phase.  Thread t
-// owns frequency t % 8 of pixels (t / 8) % 32 and that + 32.
+// owns frequency t % 16 of pixels (t / 16) % 16 and that + 16.
 template <int RY>
 __global__ __launch_bounds__(kPoolThreads) void k_pool2d(int W, int H, int D, int rx, int TY,
                                                          int ng, int nxt,
@@ -141,18 +145,18 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool2d(int W, int H, int D, in
   const int y1 = min(y0 + TY, H);
   const int tid = threadIdx.x;
   const int f = tid & (kPF - 1);
-  const int px = (tid >> 3) & 31;
+  const int px = (tid >> 4) & 15;
   const int64_t V2 = (int64_t)W * H;
   const float4* Gg = G + (int64_t)g * V2 * (kPF / 2);
   float2* Sg = S + (int64_t)g * V2 * kPF;
   const int j = g * kPF + f;
   // x phases of the thread's two columns (fixed along the walk)
   const float2 cx0 = x0 + px < W ? xtab[(int64_t)(x0 + px) * D + j] : make_float2(1.f, 0.f);
-  const float2 cx1 = x0 + px + 32 < W ? xtab[(int64_t)(x0 + px + 32) * D + j] : make_float2(1.f, 0.f);
+  const float2 cx1 = x0 + px + 16 < W ? xtab[(int64_t)(x0 + px + 16) * D + j] : make_float2(1.f, 0.f);
   for (int i = tid; i < (y1 - y0) * kPF; i += kPoolThreads)
     yph[i] = ytab[(int64_t)(y0 + i / kPF) * D + g * kPF + i % kPF];
 
-  // staged row: (64 + 2 rx) pixels x 4 float4; two loads per thread cover it.
+  // staged row: (32 + 2 rx) pixels x 8 float4; two loads per thread cover it.
   // The next row is fetched into registers while the current one is used.
   const int seg = (kPoolW + 2 * rx) * (kPF / 2);
   float4 ld[2];
@@ -160,10 +164,10 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool2d(int W, int H, int D, in
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int idx = tid + k * kPoolThreads;
-      const int x = x0 - rx + (idx >> 2);
+      const int x = x0 - rx + idx / (kPF / 2);
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (idx < seg && yi >= 0 && yi < H && x >= 0 && x < W)
-        v = Gg[((int64_t)yi * W + x) * (kPF / 2) + (idx & 3)];
+        v = Gg[((int64_t)yi * W + x) * (kPF / 2) + idx % (kPF / 2)];
       ld[k] = v;
     }
   };
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool2d(int W, int H, int D, in
           const float2* s2 = reinterpret_cast<const float2*>(st);
           for (int m = 0; m <= 2 * rx; ++m) {
             a0 = cadd(a0, s2[(px + m) * kPF + f]);
-            a1 = cadd(a1, s2[(px + 32 + m) * kPF + f]);
+            a1 = cadd(a1, s2[(px + 16 + m) * kPF + f]);
           }
         }
         h0[k] = a0;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kPoolThreads) void k_pool2d(int W, int H, int D, in
           const float2 ey = yph[(yo - y0) * kPF + f];
           const int64_t row = (int64_t)yo * W;
           if (x0 + px < W) Sg[(row + x0 + px) * kPF + f] = cmulc(s0, cmul(cx0, ey));
-          if (x0 + px + 32 < W) Sg[(row + x0 + px + 32) * kPF + f] = cmulc(s1, cmul(cx1, ey));
+          if (x0 + px + 16 < W) Sg[(row + x0 + px + 16) * kPF + f] = cmulc(s1, cmul(cx1, ey));
         }
       }
     }
@@ -331,8 +335,9 @@ int launch_paper_encode(const Batch& bt, const Workspace& w, const PaperTables& 
   const float2* xtab = reinterpret_cast<const float2*>(pt.xtab);
   const float2* ytab = reinterpret_cast<const float2*>(pt.ytab);
   float4* G4 = reinterpret_cast<float4*>(w.G);
-  hipLaunchKernelGGL(k_tphase<16>, dim3(blocks(V2, 256) * (D / 16)), dim3(256), 0, s, sl.W,
-                     (int)V2, sl.T, D, w.count, ttab, xtab, ytab, G4, w.cnt2);
+  const int npb = blocks(V2, 256);
+  hipLaunchKernelGGL(k_tphase<kPF>, dim3(blocks(npb, kXcds) * kXcds * (D / kPF)), dim3(256), 0, s,
+                     sl.W, (int)V2, sl.T, D, npb, w.count, ttab, xtab, ytab, G4, w.cnt2);
   // column tiles: enough blocks for about three per compute unit
   const int nxt = (sl.W + kPoolW - 1) / kPoolW;
   const int want = 3 * num_cus;
