@@ -207,6 +207,8 @@ KERNEL_SOURCES = {  # kernel name prefix (template form) -> source file it is bu
     "k_encode<2": "paper_2504_19417_amd/csrc/kernels_encode.hip",   # FP16 form encoder
     "k_mlp_split<": "paper_2504_19417_amd/csrc/kernels_mlp.hip",    # FP32 form perceptron
     "k_mlp_res<0": "paper_2504_19417_amd/csrc/kernels_mlp.hip",     # FP16 form perceptron
+    "k_pool2d<": "paper_2504_19417_amd/csrc/kernels_paper.hip",     # paper form window sum
+    "k_tphase<": "paper_2504_19417_amd/csrc/kernels_paper.hip",     # paper form phase sums
 }
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written
@@ -264,21 +266,39 @@ def _find_csv(d, suffix):
     raise FileNotFoundError("no *%s under %s" % (suffix, d))
 
 
-PROFILE_WORKLOAD = ("1M-event slice (346x260x50, D=128, r=5/3, perceptron 256-256-2), "
-                    "FP32 and FP16/BF16 forms")
+PROFILE_WORKLOADS = {
+    "slice1m": "1M-event slice (346x260x50, D=128, r=5/3, perceptron 256-256-2), "
+               "FP32 and FP16/BF16 forms",
+    "paper_k8": "paper form, 640x480 recipe (0.5M events, 32 bins, D=64, delta 8, no temporal "
+                "bound, perceptron 128-128-2), FP32 and FP16/BF16 forms, all events and 10k "
+                "queries",
+    "paper_k10": "paper form, 640x480 recipe (0.5M events, 24 bins, D=64, delta 10, no temporal "
+                 "bound, perceptron 128-128-2), FP32 and FP16/BF16 forms, all events and 10k "
+                 "queries",
+}
+PROFILE_NOTES = {
+    "slice1m": "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `<4, ...>` "
+               "encoder and `k_mlp_split` belong to the FP32 form, `<2, ...>` encoder and "
+               "`k_mlp_res<0, ...>` to the FP16/BF16 form; the small kernels serve both.  "
+               "`__amd_rocclr_*` are runtime copies and fills outside the steps.",
+    "paper_k8": "Three runs of 2 warm-up + 5 timed steps: FP32 form over all events, FP16/BF16 "
+                "form over all events, FP32 form over the 10k-query subset (7 calls each).  "
+                "`k_paper_rows<false>` and `k_mlp_split` serve the FP32 runs (all events and 10k "
+                "queries: hence the min/max spread), `k_paper_rows<true>` and `k_mlp_res` the "
+                "FP16/BF16 run; `k_tphase`, `k_pool2d`, the box sums and the prepare kernels "
+                "serve all three.",
+}
+PROFILE_NOTES["paper_k10"] = PROFILE_NOTES["paper_k8"]
 
 
-def summarize_kernels(stats_dir, command):
+def summarize_kernels(stats_dir, command, workload="slice1m"):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
     rows = list(csv.DictReader(open(_find_csv(stats_dir, "kernel_stats.csv"))))
-    out = ["# Kernel times: " + PROFILE_WORKLOAD, "",
+    out = ["# Kernel times: " + PROFILE_WORKLOADS[workload], "",
            "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
     out += ["    " + c for c in command.split(" ; ")]
-    out += ["", "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `<4, ...>` "
-            "encoder and `k_mlp_split` belong to the FP32 form, `<2, ...>` encoder and "
-            "`k_mlp_res<0, ...>` to the FP16/BF16 form; the small kernels serve both.  "
-            "`__amd_rocclr_*` are runtime copies and fills outside the steps.", "",
+    out += ["", PROFILE_NOTES[workload], "",
             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
             "|---|---:|---:|---:|---:|---:|"]
     for r in rows:
@@ -288,8 +308,8 @@ def summarize_kernels(stats_dir, command):
     return "\n".join(out) + "\n"
 
 
-def traffic_markdown(rec):
-    out = ["# HBM traffic per launch: " + PROFILE_WORKLOAD, "",
+def traffic_markdown(rec, workload="slice1m"):
+    out = ["# HBM traffic per launch: " + PROFILE_WORKLOADS[workload], "",
            "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
     out += ["    " + c for c in rec["command"].split(" ; ")]
     out += ["", "Calibration: the same counters on a plain device copy of known size "
@@ -429,24 +449,27 @@ def main():
                     help="after the run, copy 1 GiB on the device (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
-                         "into profiles/traffic.json and exit (no GPU needed)")
+                         "into profiles/traffic_<workload>.md (and, for slice1m, "
+                         "profiles/traffic.json) and exit (no GPU needed)")
     ap.add_argument("--summarize-kernels", metavar="STATS_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into "
-                         "profiles/kernels_slice1m.md and exit (no GPU needed)")
+                         "profiles/kernels_<workload>.md and exit (no GPU needed)")
     ap.add_argument("--command", default="", help="commands recorded with the summaries "
                                                   "(separated by ' ; ')")
     args = ap.parse_args()
     if args.summarize_traffic or args.summarize_kernels:
+        wl = args.workload
         if args.summarize_traffic:
             rec = summarize_traffic(*args.summarize_traffic, args.command)
-            with open(TRAFFIC_JSON, "w") as f:
-                json.dump(rec, f, indent=1)
-            with open(os.path.join(ROOT, "profiles", "traffic_slice1m.md"), "w") as f:
-                f.write(traffic_markdown(rec))
+            if wl == "slice1m":  # the headline line's roofline reads this record
+                with open(TRAFFIC_JSON, "w") as f:
+                    json.dump(rec, f, indent=1)
+            with open(os.path.join(ROOT, "profiles", "traffic_%s.md" % wl), "w") as f:
+                f.write(traffic_markdown(rec, wl))
             print(json.dumps(rec["kernels"], indent=1))
         if args.summarize_kernels:
-            with open(os.path.join(ROOT, "profiles", "kernels_slice1m.md"), "w") as f:
-                f.write(summarize_kernels(args.summarize_kernels, args.command))
+            with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % wl), "w") as f:
+                f.write(summarize_kernels(args.summarize_kernels, args.command, wl))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
