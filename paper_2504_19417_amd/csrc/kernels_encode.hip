@@ -199,6 +199,11 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
   if constexpr (MTV > 0 && kEncPrefetch) cw.fetch(runs_l, vol2, rb, 0, g);
   for (int ks = 0; ks < nsteps; ++ks) {
     const int buf = ks % NBUF;
+    // start the slab AHEAD steps out now, so that it lands during this step:
+    // its buffer was last read in step ks - 1, before the last barrier
+    if (ks + AHEAD < nsteps)
+      issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
+                              slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
     if constexpr (MTV > 0) {
       if constexpr (!kEncPrefetch) cw.fetch(runs_l, vol2, rb, ks, g);
       // pair sums and differences of counts at +o / -o: the -o run comes out
@@ -249,13 +254,8 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
           cnt[mt] = __builtin_amdgcn_fdot2(half2v{bw[2 * e], bw[2 * e + 1]},
                                            half2v{cS[mt][2 * e], cS[mt][2 * e + 1]}, cnt[mt], false);
     }
-    // every LDS read of this step is issued: start the slab AHEAD steps out
-    // (its buffer was last read in step ks - 1, before the last barrier),
-    // then make sure the slab of step ks + 1 has landed (slabs ks + 2 ..
-    // ks + AHEAD may stay in flight)
-    if (ks + AHEAD < nsteps)
-      issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
-                              slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
+    // make sure the slab of step ks + 1 has landed (slabs ks + 2 .. ks +
+    // AHEAD may stay in flight)
     const int last = ks + AHEAD < nsteps - 1 ? ks + AHEAD : nsteps - 1;  // newest slab issued
     wait_slabs<PFW>(last - ks - 1 > 0 ? last - ks - 1 : 0);
     lds_barrier();
