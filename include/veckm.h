@@ -191,6 +191,47 @@ int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
    VECKM_E_OVERFLOW. */
 int veckm_status(veckm_ctx* ctx, void* stream);
 
+/* ---- sliding window (streaming encoder) --------------------------------- */
+
+/* The encoder as a general-purpose per-event feature over a live event
+   stream (Sec. 1: the local event encoder is offered for other event-based
+   tasks; Eqn. 10 over the bounded window of Eqn. 1 with the context's rt).  A
+   window context keeps the integer event counts of the last Tw =
+   params->max_bins time bins of one sensor resident on the device as a ring
+   over time: pushing new bins retires the oldest ones, and query events are
+   encoded against every event resident in the window.  Encoding a window is
+   bit-identical to veckm_encode of a slice holding the window's events with
+   t0 = end - Tw and nbins = Tw.
+
+   veckm_window_create: as veckm_create (rt >= 0; max_slices 0 or 1); the
+   window starts empty.  Destroy with veckm_destroy; veckm_set_mlp and
+   veckm_status apply; veckm_encode / veckm_flow and the batch calls return
+   VECKM_E_INVAL on a window context. */
+int veckm_window_create(const veckm_params* params, veckm_ctx** out);
+
+/* Appends the events of bins [t0, t0 + nbins) (device, n events, every t in
+   that range, 1 <= nbins <= Tw, n <= max_events).  The first push fixes the
+   stream's origin; later pushes need t0 >= the previous end (skipped bins
+   are empty).  The window becomes [t0 + nbins - Tw, t0 + nbins): older bins
+   are retired.  Events outside the bins or the sensor are reported by
+   veckm_status as VECKM_E_RANGE (and not counted), voxels over
+   VECKM_MAX_VOXEL_EVENTS as VECKM_E_OVERFLOW.  Returns VECKM_E_INVAL for a
+   t0 before the previous end, VECKM_E_RANGE for n or nbins out of range. */
+int veckm_window_push(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                      int32_t nbins, void* stream);
+
+/* Encodes m query events (device, each inside the sensor and the current
+   window, else VECKM_E_RANGE via veckm_status) against the resident window:
+   emb (device, m x 2D float32, planar [Re | Im]) as veckm_encode.  A query
+   usually is a pushed event (then it counts itself); a query with no event in
+   its neighbourhood encodes to zeros.  VECKM_E_STATE before the first push.
+   veckm_window_flow adds the perceptron (flow: device, m x 2 float32;
+   VECKM_E_STATE if none was set). */
+int veckm_window_encode(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* emb,
+                        void* stream);
+int veckm_window_flow(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* flow,
+                      void* stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Stages of one compute call, in launch order. */

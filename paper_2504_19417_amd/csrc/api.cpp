@@ -30,6 +30,13 @@ struct veckm_ctx {
   Workspace w;
   MlpWeights mw;
   bool paper = false;  // no temporal bound: the staged 2-D pooling encoder
+  // sliding window (veckm_window_*): the count and pair grids are a ring of
+  // max_bins planes holding bins [wend - max_bins, wend); bin t sits in plane
+  // (t - tref) mod max_bins
+  bool window = false;
+  bool started = false;
+  int32_t tref = 0;
+  int64_t wend = 0;
   PaperTables pt;
   int max_slices = 1;
   std::vector<void*> allocs;
@@ -148,6 +155,7 @@ SliceDesc describe(const veckm_ctx* c, int W, int H, int T, int t0, int64_t bric
   s.pair_off = pair_off;
   s.ev_off = (int)ev_off;
   s.n = (int)n;
+  s.tshift = 0;
   return s;
 }
 
@@ -249,6 +257,7 @@ struct StageTimer {
 // calls (exactly one is non-NULL).
 int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* queries, float* emb,
         float* flow, void* stream) {
+  // a window's encode: ev holds the query events, the counts are resident
   if (bt.m == 0) return VECKM_OK;
   // rows the encoder hands to the perceptron (encodings handed out are fp32)
   const int rows = !flow                             ? kRowsF32
@@ -257,7 +266,8 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
                                                       : kRowsF32;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
-    const int rc = launch_prepare(bt, c->w, ev, queries, c->et, !c->paper, stream);
+    const int rc = c->window ? launch_window_prepare(bt, c->w, ev, c->et, stream)
+                             : launch_prepare(bt, c->w, ev, queries, c->et, !c->paper, stream);
     if (rc) return rc;
   }
   {
@@ -558,7 +568,7 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
 
 int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                  int32_t nbins, const int32_t* queries, int64_t m, float* emb, void* stream) {
-  if (!ctx) return VECKM_E_INVAL;
+  if (!ctx || ctx->window) return VECKM_E_INVAL;
   Batch bt;
   const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, emb, &bt);
   if (rc) return rc;
@@ -567,7 +577,7 @@ int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t
 
 int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                int32_t nbins, const int32_t* queries, int64_t m, float* flow, void* stream) {
-  if (!ctx) return VECKM_E_INVAL;
+  if (!ctx || ctx->window) return VECKM_E_INVAL;
   Batch bt;
   const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, flow, &bt);
   if (rc) return rc;
@@ -575,9 +585,93 @@ int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
   return run(ctx, bt, events, queries, nullptr, flow, stream);
 }
 
+// ---- sliding window ------------------------------------------------------
+
+int veckm_window_create(const veckm_params* params, veckm_ctx** out) {
+  if (!out) return VECKM_E_INVAL;
+  *out = nullptr;
+  if (!params || params->rt < 0 || params->max_slices > 1) return VECKM_E_INVAL;
+  veckm_ctx* c = nullptr;
+  int rc = veckm_create(params, &c);
+  if (rc) return rc;
+  c->window = true;
+  // an empty window: every plane of the ring holds zero counts
+  const int64_t V = (int64_t)params->width * params->height * params->max_bins;
+  const int64_t P = (int64_t)(params->width + 1) * params->height * params->max_bins;
+  if (hipMemset(c->w.count, 0, (size_t)V * 4) != hipSuccess ||
+      hipMemset(c->w.pairs, 0, (size_t)P * 4) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    veckm_destroy(c);
+    return VECKM_E_HIP;
+  }
+  *out = c;
+  return VECKM_OK;
+}
+
+int veckm_window_push(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                      int32_t nbins, void* stream) {
+  if (!ctx || !ctx->window || n < 0 || (n > 0 && !events)) return VECKM_E_INVAL;
+  if (n > ctx->p.max_events) return VECKM_E_RANGE;
+  const int T = ctx->p.max_bins;
+  if (nbins < 1 || nbins > T) return VECKM_E_RANGE;
+  if (ctx->started && (int64_t)t0 < ctx->wend) return VECKM_E_INVAL;  // bins arrive in order
+  const int32_t tref = ctx->started ? ctx->tref : t0;
+  const int64_t wend0 = ctx->started ? ctx->wend : (int64_t)t0;
+  const int64_t end = (int64_t)t0 + nbins;
+  const int64_t b0 = end - T > wend0 ? end - T : wend0;  // bins entering the window
+  const int rc = launch_window_push(ctx->w, events, n, ctx->p.width, ctx->p.height, T, t0, nbins,
+                                    tref, b0, (int)(end - b0), stream);
+  if (rc) return rc;
+  ctx->started = true;
+  ctx->tref = tref;
+  ctx->wend = end;
+  return VECKM_OK;
+}
+
+namespace {
+
+int window_batch(veckm_ctx* c, const veckm_event* queries, int64_t m, const void* out,
+                 Batch* bt) {
+  if (!c || !c->window || m < 0 || (m > 0 && (!queries || !out))) return VECKM_E_INVAL;
+  if (!c->started) return VECKM_E_STATE;
+  if (m > c->p.max_events) return VECKM_E_RANGE;
+  const int T = c->p.max_bins;
+  const int64_t start = c->wend - T;  // may precede the first push: those planes are empty
+  if (start < INT32_MIN) return VECKM_E_RANGE;
+  bt->s0 = describe(c, c->p.width, c->p.height, T, (int32_t)start, 0, 0, 0, 0, m);
+  bt->s0.tshift = (int)(((start - c->tref) % T + T) % T);
+  bt->table = nullptr;
+  bt->nslices = 1;
+  bt->nbricks = bt->s0.nbx * bt->s0.nby * bt->s0.nbt;
+  bt->n = (int)m;
+  bt->m = (int)m;
+  bt->nvox = (int64_t)c->p.width * c->p.height * T;
+  bt->npairs = (int64_t)(c->p.width + 1) * c->p.height * T;
+  return VECKM_OK;
+}
+
+}  // namespace
+
+int veckm_window_encode(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* emb,
+                        void* stream) {
+  Batch bt;
+  const int rc = window_batch(ctx, queries, m, emb, &bt);
+  if (rc) return rc;
+  return run(ctx, bt, queries, nullptr, emb, nullptr, stream);
+}
+
+int veckm_window_flow(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* flow,
+                      void* stream) {
+  Batch bt;
+  const int rc = window_batch(ctx, queries, m, flow, &bt);
+  if (rc) return rc;
+  if (ctx->mw.hidden == 0) return VECKM_E_STATE;
+  return run(ctx, bt, queries, nullptr, nullptr, flow, stream);
+}
+
 int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                        const veckm_event* events, float* emb, void* stream) {
-  if (!ctx || ctx->paper) return VECKM_E_INVAL;
+  if (!ctx || ctx->paper || ctx->window) return VECKM_E_INVAL;
   Batch bt;
   int slot;
   int rc = multi_batch(ctx, slices, count, events, emb, stream, &bt, &slot);
@@ -589,7 +683,7 @@ int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
 
 int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                      const veckm_event* events, float* flow, void* stream) {
-  if (!ctx || ctx->paper) return VECKM_E_INVAL;
+  if (!ctx || ctx->paper || ctx->window) return VECKM_E_INVAL;
   if (ctx->mw.hidden == 0) return VECKM_E_STATE;
   Batch bt;
   int slot;

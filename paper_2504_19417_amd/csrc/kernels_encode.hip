@@ -341,8 +341,9 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
       for (int rr = wid; rr < nrows; rr += NW) {
         const int y = y0 + sy, t = tb + st;
         const bool in = xin && (unsigned)y < (unsigned)sl.H && (unsigned)t < (unsigned)sl.T;
+        const int tp = t + sl.tshift < sl.T ? t + sl.tshift : t + sl.tshift - sl.T;  // ring plane
         const uint32_t* src =
-            in ? a.pairs + sl.pair_off + ((int64_t)t * sl.H + y) * (sl.W + 1) + (x + 1)
+            in ? a.pairs + sl.pair_off + ((int64_t)tp * sl.H + y) * (sl.W + 1) + (x + 1)
                : a.zeros + lane;
         if (lane < a.SX) copy_to_lds4(src, lds_offset(vol2 + rr * a.SX));
         sy += NW;
@@ -410,10 +411,12 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
         if (r >= nr) continue;
         const float rc = __builtin_amdgcn_rcpf(n);
         // x / n: reciprocal estimate plus one residual correction (exact for
-        // x = n, so an all-ones feature still gives exactly 1)
+        // x = n, so an all-ones feature still gives exactly 1).  A query of a
+        // sliding window can have no event in its neighbourhood (n = 0): its
+        // encoding is zero.
         auto div = [n, rc](float x) {
           const float qq = x * rc;
-          return fmaf(fmaf(-qq, n, x), rc, qq);
+          return n > 0.f ? fmaf(fmaf(-qq, n, x), rc, qq) : 0.f;
         };
         const int64_t u = (int64_t)(row0 + c0 + r) * (2 * D);
 #pragma unroll

@@ -33,9 +33,10 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 
-// One thread per event: validate against its slice, histogram, remember the
-// slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught by k_pairs,
-// which reads every count once.
+// One thread per event: validate against its slice, histogram (ADD), remember
+// the slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught by
+// k_pairs, which reads every count once.
+template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,8 +52,26 @@ __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __rest
     return;
   }
   const int v = ((int)dt * s.H + e.y) * s.W + e.x;
-  atomicAdd(&count[s.grid_off + v], 1);  // result unused: a no-return atomic
+  if (ADD) atomicAdd(&count[s.grid_off + v], 1);  // result unused: a no-return atomic
   vox[i] = v;
+}
+
+// A sliding window's new bins: validate each event against [t0, t0 + nbins)
+// and the sensor, and count it in ring plane (t - tref) mod T.
+__global__ void k_push(const int4* __restrict__ ev, int n, int W, int H, int T, int t0, int nbins,
+                       int tref, int32_t* __restrict__ count, int32_t* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int4 e = ev[i];
+  const int64_t dt = (int64_t)e.z - (int64_t)t0;
+  const bool ok = e.x >= 0 && e.x < W && e.y >= 0 && e.y < H && dt >= 0 && dt < nbins &&
+                  (e.w == 1 || e.w == -1);
+  if (!ok) {
+    atomicOr(err, kErrRange);
+    return;
+  }
+  const int plane = (int)(((int64_t)e.z - tref) % T);
+  atomicAdd(&count[((int64_t)plane * H + e.y) * W + e.x], 1);
 }
 
 // The encoder's view of the counts: per slice, rows of W + 1 dwords; entry
@@ -94,7 +113,7 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
                        int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= bt.m) return;
-  const int q = queries[i];
+  const int q = queries ? queries[i] : i;
   if (q < 0 || q >= bt.n) {
     atomicOr(err, kErrQuery);
     return;
@@ -264,7 +283,7 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   if (queries)
     hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.qmark, bt.nvox);
   if (bt.n > 0)
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
   if (pairs)
     hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs,
@@ -284,6 +303,55 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
                        et.brick, w.vox, w.rank, w.brick_off, w.qmap,
                        pairs ? nullptr : w.rowvox);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int launch_window_push(const Workspace& w, const veckm_event* ev, int64_t n, int W, int H, int T,
+                       int t0, int nbins, int tref, int64_t clear_b0, int clear_nb, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t plane = (int64_t)W * H, pplane = (int64_t)(W + 1) * H;
+  // the planes of the bins that enter the window: clear them, count the new
+  // events, rebuild their pairs
+  const int p0 = (int)((clear_b0 - tref) % T);
+  const int first = clear_nb < T - p0 ? clear_nb : T - p0;  // planes before the ring wraps
+  const int span[2][2] = {{p0, first}, {0, clear_nb - first}};
+  for (const auto& sp : span)
+    if (sp[1] > 0)
+      hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(sp[1] * plane)), dim3(256), 0, s,
+                         w.count + sp[0] * plane, sp[1] * plane, 0);
+  if (n > 0)
+    hipLaunchKernelGGL(k_push, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const int4*>(ev), (int)n, W, H, T, t0, nbins, tref,
+                       w.count, w.err);
+  for (const auto& sp : span)
+    if (sp[1] > 0) {
+      Batch pb{};
+      pb.s0.W = W;
+      pb.nslices = 1;
+      pb.npairs = sp[1] * pplane;
+      hipLaunchKernelGGL(k_pairs, dim3(fill_grid(pb.npairs)), dim3(256), 0, s, pb,
+                         w.count + sp[0] * plane, w.pairs + sp[0] * pplane, w.err);
+    }
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event* queries,
+                          const EncodeTables& et, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.qmark, bt.nvox);
+  if (bt.n > 0) {
+    hipLaunchKernelGGL(k_scatter<false>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err);
+    hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt, w.vox,
+                       w.qmark, w.err);
+  }
+  hipLaunchKernelGGL(k_rank<false>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
+                     w.qmark, w.rank, w.ulist, w.brick_nq);
+  hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, bt.nbricks,
+                     encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
+  if (bt.m > 0)
+    hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt,
+                       et.brick, w.vox, w.rank, w.brick_off, w.qmap, nullptr);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

@@ -85,6 +85,8 @@ struct SliceDesc {
   int64_t grid_off;   // first voxel in the count / rank / mark grids
   int64_t pair_off;   // first entry in the pair grid (rows of W + 1 entries)
   int ev_off, n;      // events [ev_off, ev_off + n)
+  int tshift;         // the count / pair grids hold bin t in plane (t + tshift) mod T (a
+                      // sliding window's ring; 0 otherwise)
 };
 
 // Everything the kernels need to know about the slices of one call.
@@ -186,6 +188,14 @@ bool mlp_rows_split(int d, int hidden);
 int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
 int launch_take_err(const Workspace& w, int32_t* host, void* stream);
+// Sliding window: the bins [clear_b0, clear_b0 + clear_nb) enter the ring of
+// T planes (bin b in plane (b - tref) mod T, clear_nb <= T); the events of
+// bins [t0, t0 + nbins) among them are counted.  Then an encode of query
+// events against the resident window (bt describes the window, tshift set).
+int launch_window_push(const Workspace& w, const veckm_event* ev, int64_t n, int W, int H, int T,
+                       int t0, int nbins, int tref, int64_t clear_b0, int clear_nb, void* stream);
+int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event* queries,
+                          const EncodeTables& et, void* stream);
 
 // ------------------------------------------------- context hooks for the server
 // What one call can hold, and what one slice needs of it.

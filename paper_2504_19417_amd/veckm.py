@@ -98,6 +98,11 @@ _sig = {
     "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
+    "veckm_window_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.POINTER(_P)]),
+    "veckm_window_push": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                         _P]),
+    "veckm_window_encode": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "veckm_window_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "veckm_server_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.c_int64,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     "veckm_server_destroy": (None, [_P]),
@@ -216,6 +221,26 @@ def veckm_flow_batch(ctx, slices, count, events_ptr, flow_ptr, stream):
 
 def veckm_status(ctx, stream):
     return _lib.veckm_status(ctx, stream)
+
+
+def veckm_window_create(params):
+    h = _P()
+    rc = _lib.veckm_window_create(ctypes.byref(params), ctypes.byref(h))
+    if rc:
+        raise VeckmError(rc, "veckm_window_create")
+    return h
+
+
+def veckm_window_push(ctx, events_ptr, n, t0, nbins, stream):
+    return _lib.veckm_window_push(ctx, events_ptr, int(n), int(t0), int(nbins), stream)
+
+
+def veckm_window_encode(ctx, queries_ptr, m, emb_ptr, stream):
+    return _lib.veckm_window_encode(ctx, queries_ptr, int(m), emb_ptr, stream)
+
+
+def veckm_window_flow(ctx, queries_ptr, m, flow_ptr, stream):
+    return _lib.veckm_window_flow(ctx, queries_ptr, int(m), flow_ptr, stream)
 
 
 def veckm_profile_enable(ctx, enable):
@@ -408,6 +433,48 @@ def veckm_server_stats(server, reset=False):
     if rc:
         raise VeckmError(rc, "veckm_server_stats")
     return {f: getattr(st, f) for f, _ in veckm_serving_stats._fields_}
+
+
+class Window(Context):
+    """A sliding-window (streaming) encoder: push the events of new time bins,
+    encode query events against the resident window."""
+
+    def __init__(self, width, height, rx, ry, rt, A, window_bins, max_events, precision="fp32"):
+        self.params = make_params(width, height, rx, ry, rt, A, window_bins, max_events, precision)
+        self.d = self.params.d
+        self.handle = veckm_window_create(self.params)
+        self.hidden = 0
+
+    def push(self, events, t0, nbins, stream=None):
+        self._check_inputs(events, None)
+        rc = veckm_window_push(self.handle, events.data_ptr(), events.shape[0], t0, nbins,
+                               self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_window_push")
+
+    def encode_window(self, queries, out=None, stream=None):
+        import torch
+        self._check_inputs(queries, None)
+        m = queries.shape[0]
+        if out is None:
+            out = torch.empty((m, 2 * self.d), dtype=torch.float32, device=queries.device)
+        rc = veckm_window_encode(self.handle, queries.data_ptr(), m, out.data_ptr(),
+                                 self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_window_encode")
+        return out
+
+    def flow_window(self, queries, out=None, stream=None):
+        import torch
+        self._check_inputs(queries, None)
+        m = queries.shape[0]
+        if out is None:
+            out = torch.empty((m, 2), dtype=torch.float32, device=queries.device)
+        rc = veckm_window_flow(self.handle, queries.data_ptr(), m, out.data_ptr(),
+                               self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_window_flow")
+        return out
 
 
 class Server:

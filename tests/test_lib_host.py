@@ -27,7 +27,8 @@ def test_header_declares_api():
                      "veckm_set_mlp", "veckm_status", "veckm_strerror", "veckm_encode_batch",
                      "veckm_flow_batch", "veckm_server_create", "veckm_server_destroy",
                      "veckm_server_set_mlp", "veckm_stream_open", "veckm_stream_close",
-                     "veckm_submit", "veckm_poll", "veckm_server_stats"]:
+                     "veckm_submit", "veckm_poll", "veckm_server_stats", "veckm_window_create",
+                     "veckm_window_push", "veckm_window_encode", "veckm_window_flow"]:
         assert required in names
 
 
@@ -170,6 +171,16 @@ def test_server_create_checks_before_device():
     with pytest.raises(veckm.VeckmError) as e:
         veckm.veckm_server_create(p, 1 << 40, 4, 2)
     assert e.value.code == veckm.VECKM_E_NODEVICE
+
+
+def test_window_checks_before_device():
+    for bad in (dict(rt=-1), dict(max_slices=2)):
+        with pytest.raises(veckm.VeckmError) as e:
+            veckm.veckm_window_create(_params(**bad))
+        assert e.value.code == veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_window_push(None, None, 0, 0, 1, None) == veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_window_encode(None, None, 0, None, None) == veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_window_flow(None, None, 0, None, None) == veckm.VECKM_E_INVAL
 
 
 def test_server_null_handles():
