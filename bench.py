@@ -57,6 +57,15 @@ def paper_encode_bytes(W, H, T, d, rows, row_bytes):
     return 4 * T * V2 + grid + 2 * grid + 4 * 4 * V2 + rows * (2 * d * 4 + row_bytes)
 
 
+def eqn18_split(n, m_small, ms_small, ms_all):
+    """The runtime model of Eqn. 18, time = c n + C m, fitted through the
+    all-events point (m = n) and a sparse point (m = m_small)."""
+    C = (ms_all - ms_small) / (n - m_small)       # ms per flow
+    c = (ms_small - C * m_small) / n              # ms per event
+    return {"c_ns_per_event": round(c * 1e6, 4), "C_ns_per_flow": round(C * 1e6, 4),
+            "points": [[m_small, round(ms_small, 4)], [n, round(ms_all, 4)]]}
+
+
 def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=None):
     ctx = vk.Context(w.slices[0].width, w.slices[0].height, w.rx, w.ry, w.rt, A, T, len(ev),
                      precision)
@@ -423,6 +432,7 @@ def paper_main(args, name):
         "worked_example_10k_flows": {"ms_per_call": round(ms_sparse, 4),
                                      "stages_ms": stages(sparse),
                                      "paper_estimate_ms_rtx2080ti_r8": 7.04},
+        "eqn18": eqn18_split(n, 10_000, ms_sparse, res["fp32"]["elapsed"] / args.steps * 1e3),
         "rows": rows,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -587,6 +597,11 @@ def main():
     res = {}
     for form in ("fp32", "fp16"):
         res[form] = run_form(vk, torch, w, ev, t0, T, A, mlp, form, args.steps, args.warmup)
+    # sparse query set (Eqn. 18's C m term shrinks, the c n term stays)
+    q10k = synth.sample_queries(n, 10_000, 79)
+    sparse = run_form(vk, torch, w, ev, t0, T, A, mlp, "fp32", args.steps, args.warmup,
+                      queries=q10k)
+    ms_sparse = sparse["elapsed"] / args.steps * 1e3
 
     def summary(r):
         ms = r["elapsed"] / args.steps * 1e3
@@ -651,6 +666,10 @@ def main():
             "err_vs_oracle": {"flow_relL2_sampled": err16},
             "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
         },
+        "sparse_10k_queries": {"ms_per_call": round(ms_sparse, 4),
+                               "stages_ms": {k: (round(v[0] / v[1], 4) if v[1] else None)
+                                             for k, v in sparse["stages"].items()},
+                               "eqn18": eqn18_split(n, 10_000, ms_sparse, ms32)},
         "rows": rows,
         "roofline": roofline,
         "serving": serving,
