@@ -19,13 +19,13 @@
 //
 // Work decomposition: the (x, y, t) grid of every slice is cut into bricks,
 // and the bricks of all slices of a call form one work list.  A persistent
-// block of 4 waves (one per SIMD) takes whole bricks from a device counter,
+// block of 16 waves (4 per SIMD) takes whole bricks from a device counter,
 // copies the brick's counts plus the window halo from the pair grid into
-// LDS, and runs the brick's query voxels in chunks of 256 rows (128 at
-// D = 256).  The table streams through LDS one 32-offset slab per MFMA
-// k-step, NBUF slabs deep, shared by the waves.  Each wave owns 64 rows
-// (4 row tiles) and every frequency (half of them at D = 256); its count
-// words for the next k-step are fetched while the current one multiplies.
+// LDS, and runs the brick's query voxels in chunks of up to 512 rows (256
+// at D = 128, 128 at D = 256).  The table streams through LDS one 32-offset
+// slab per MFMA k-step, NBUF slabs deep, shared by the waves.  Each wave
+// owns 2 row tiles of 16 rows and up to 64 frequencies; with four waves per
+// SIMD, one wave's count gathers overlap another's matrix products.
 #include <hip/hip_runtime.h>
 
 #include "slices.h"
@@ -101,7 +101,7 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 // Waves per block and the most 16-frequency tiles one wave holds.
-constexpr int kEncWaves = 8;
+constexpr int kEncWaves = 16;
 constexpr int kEncMaxNtw = 4;
 // Fetch the next k-step's count words while the current step multiplies.
 constexpr bool kEncPrefetch = false;
@@ -112,7 +112,7 @@ struct EncShape {
   static constexpr int NTW = NT < kEncMaxNtw ? NT : kEncMaxNtw;  // frequency tiles per wave
   static constexpr int WN = NT / NTW;           // waves across frequencies (1, or 2 at D = 256)
   static constexpr int WM = NW / WN;            // waves across rows
-  static constexpr int MT = 4;                  // 16-row tiles per wave
+  static constexpr int MT = 2;                  // 16-row tiles per wave
   static constexpr int CH = WM * MT * 16;       // rows per chunk
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-slot slab
   static constexpr int PFW = SLAB_U4 / (NW * 64);  // copies per wave per slab
