@@ -262,8 +262,9 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   // rows the encoder hands to the perceptron (encodings handed out are fp32)
   const int rows = !flow                             ? kRowsF32
                    : c->p.precision == VECKM_FP16     ? kRowsBF16
-                   : mlp_rows_split(c->p.d, c->mw.hidden) ? kRowsSplit16
-                                                      : kRowsF32;
+                   : !mlp_rows_split(c->p.d, c->mw.hidden) ? kRowsF32
+                   : c->paper                          ? kRowsSplit16
+                                                      : kRowsHiLo16;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
     const int rc = c->window ? launch_window_prepare(bt, c->w, ev, c->et, stream)
@@ -272,7 +273,8 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   }
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
-    const int erows = rows == kRowsBF16 ? kRowsBF16 : kRowsF32;
+    // the encoder writes fp32 rows unless the perceptron takes bf16 or hi/lo rows
+    const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 ? rows : kRowsF32;
     const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, c->num_cus, stream)
                             : launch_encode(bt, c->w, c->et, erows, c->num_cus, stream);
     if (rc) return rc;

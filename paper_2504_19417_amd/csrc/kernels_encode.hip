@@ -285,6 +285,7 @@ __device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, ui
 }
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 
 template <int NA, int NT, int NBUF, int ROWS>
 __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
@@ -438,6 +439,24 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
             pi.y = f32_to_bf16_rne(im[2]) | ((uint32_t)f32_to_bf16_rne(im[3]) << 16);
             __builtin_nontemporal_store(pr, reinterpret_cast<u32x2*>(out + u + j));
             __builtin_nontemporal_store(pi, reinterpret_cast<u32x2*>(out + u + D + j));
+          } else if constexpr (ROWS == kRowsHiLo16) {
+            // fp16 hi = rne(v), lo = rne(v - hi) (v - hi is exact in fp32):
+            // 22 significant bits in the perceptron's operands.  Each group
+            // of 4 consecutive row elements becomes one 16-byte unit [hi x 4,
+            // lo x 4], so a row keeps the fp32 row's size and a lane writes
+            // one unit for its 4 real and one for its 4 imaginary parts.
+            _Float16* out = static_cast<_Float16*>(a.rows);
+            const int64_t u2 = u * 2;
+            half8 ur, ui;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              ur[i] = (_Float16)re[i];
+              ur[4 + i] = (_Float16)(re[i] - (float)ur[i]);
+              ui[i] = (_Float16)im[i];
+              ui[4 + i] = (_Float16)(im[i] - (float)ui[i]);
+            }
+            __builtin_nontemporal_store(ur, reinterpret_cast<half8*>(out + u2 + 2 * j));
+            __builtin_nontemporal_store(ui, reinterpret_cast<half8*>(out + u2 + 2 * (D + j)));
           } else {
             float* out = static_cast<float*>(a.rows);
             __builtin_nontemporal_store(re, reinterpret_cast<floatx4*>(out + u + j));
@@ -474,8 +493,12 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_
                     hipStream_t s) {
   const size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
-  const void* fn = rows == kRowsBF16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsBF16>)
-                                     : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsF32>);
+  if (rows == kRowsHiLo16 && NA != 4) return VECKM_E_INVAL;  // hi/lo rows: the FP32 form only
+  constexpr int HL = NA == 4 ? kRowsHiLo16 : kRowsF32;
+  const void* fn =
+      rows == kRowsBF16     ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsBF16>)
+      : rows == kRowsHiLo16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, HL>)
+                            : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsF32>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
   const int per_cu = (int)((160 * 1024) / lds);
@@ -484,6 +507,8 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_
   constexpr int threads = EncShape<NA, NT>::NW * 64;
   if (rows == kRowsBF16)
     hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, a);
+  else if (rows == kRowsHiLo16)
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, HL>), dim3(grid), dim3(threads), lds, s, a);
   else
     hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, a);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;

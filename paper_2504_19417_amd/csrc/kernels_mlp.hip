@@ -329,11 +329,13 @@ struct Layer2T {
 };
 
 // FORM 0: bf16 rows x bf16 W1.  FORM 1: fp32 rows and W1, both as fp16 hi/lo.
-// NW waves per block, each owning 16 NTH hidden units.
+// FORM 2: rows already split by the encoder (each group of 4 consecutive
+// elements is a 16-byte unit [hi x 4, lo x 4]) and W1 as fp16 hi/lo.  NW
+// waves per block, each owning 16 NTH hidden units.
 template <int FORM, int NW, int NTH, int K2, int NBUF>
 __global__ __launch_bounds__(NW * 64) void k_mlp_res(MlpArgs a) {
   constexpr int KQ = K2 / 32;
-  constexpr int RB = FORM == 0 ? K2 * 2 : K2 * 4;  // bytes per row
+  constexpr int RB = FORM == 0 ? K2 * 2 : K2 * 4;  // bytes per row (fp32, or hi + lo halves)
   constexpr int CPR = RB / 16;                      // 16-byte chunks per row
   constexpr int TILE_U4 = 64 * CPR;
   constexpr int PFW = TILE_U4 / (NW * 64);          // copies per wave per tile
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(NW * 64) void k_mlp_res(MlpArgs a) {
   const unsigned char* X = static_cast<const unsigned char*>(a.x);
   // W1 fragments (A operand: hidden unit r16 of the tile, contraction
   // elements 32 kq + 8 g .. + 7)
-  uint4 wh[KQ][NTH], wl[FORM == 1 ? KQ : 1][NTH];
+  uint4 wh[KQ][NTH], wl[FORM != 0 ? KQ : 1][NTH];
 #pragma unroll
   for (int nt = 0; nt < NTH; ++nt) {
     const int64_t h = wid * NTH * 16 + nt * 16 + r16;
@@ -358,13 +360,13 @@ __global__ __launch_bounds__(NW * 64) void k_mlp_res(MlpArgs a) {
     for (int kq = 0; kq < KQ; ++kq) {
       const uint16_t* src = (FORM == 0 ? a.W1b : a.W1h) + h * K2 + kq * 32 + 8 * g;
       wh[kq][nt] = *reinterpret_cast<const uint4*>(src);
-      if constexpr (FORM == 1)
+      if constexpr (FORM != 0)
         wl[kq][nt] = *reinterpret_cast<const uint4*>(a.W1l + h * K2 + kq * 32 + 8 * g);
     }
   }
   Layer2T<NTH> l2;
   l2.load(a, wid, lane);
-  const float unscale = FORM == 1 ? a.unscale : 1.f;
+  const float unscale = FORM != 0 ? a.unscale : 1.f;
   const int mine = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / gridDim.x + 1 : 0;
 #pragma unroll
   for (int u = 0; u < NBUF - 1; ++u)
@@ -405,6 +407,23 @@ __global__ __launch_bounds__(NW * 64) void k_mlp_res(MlpArgs a) {
           for (int nt = 0; nt < NTH; ++nt)
             acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(wh[kq][nt]),
                                                                   as_bf16x8(xb), acc[mt][nt], 0, 0, 0);
+        } else if constexpr (FORM == 2) {
+          // elements 32 kq + 8 g .. + 7: two units; their hi and lo halves
+          // regroup by register (no conversion)
+          const int c = kq * 8 + 2 * g;
+          const uint4 u0 = cur[r * CPR + (c ^ (r & 15))];
+          const uint4 u1 = cur[r * CPR + ((c + 1) ^ (r & 15))];
+          const f16x8 xh = as_f16x8(make_uint4(u0.x, u0.y, u1.x, u1.y));
+          const f16x8 xl = as_f16x8(make_uint4(u0.z, u0.w, u1.z, u1.w));
+#pragma unroll
+          for (int nt = 0; nt < NTH; ++nt) {
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xh,
+                                                                 acc[mt][nt], 0, 0, 0);
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wl[kq][nt]), xh,
+                                                                 acc[mt][nt], 0, 0, 0);
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_f16x8(wh[kq][nt]), xl,
+                                                                 acc[mt][nt], 0, 0, 0);
+          }
         } else {
           // fp32 row elements 32 kq + 8 g .. + 7 (two chunks), split into an
           // fp16 hi + lo pair: lo = v - hi is exact in fp32, then rounded
@@ -634,6 +653,18 @@ static int launch_nth(const MlpArgs& a, int rows, int num_cus, hipStream_t s) {
       if (a.K2 == 128) return launch_res<0, NTH, 128, 4>(a, num_cus, s);
     }
     hipLaunchKernelGGL(k_mlp_bf16<NTH>, dim3(num_cus * 4), dim3(256), 0, s, a);
+  } else if (rows == kRowsHiLo16) {
+    // shapes admitted by mlp_rows_split(); two 64-row tiles in LDS
+    if constexpr (NTH <= 4) {
+      if (a.K2 == 256) return launch_res<2, NTH, 256, 2>(a, num_cus, s);
+    }
+    if constexpr (NTH <= 6) {
+      if (a.K2 == 128) return launch_res<2, NTH, 128, 2>(a, num_cus, s);
+    }
+    if constexpr (NTH <= 8) {
+      if (a.K2 == 64) return launch_res<2, NTH, 64, 2>(a, num_cus, s);
+    }
+    return VECKM_E_INVAL;
   } else if (rows == kRowsSplit16) {
     // shapes admitted by mlp_rows_split()
     if constexpr (NTH <= 4) {

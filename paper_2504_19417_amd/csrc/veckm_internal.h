@@ -154,6 +154,9 @@ struct EncodeTables {
 constexpr int kRowsF32 = 0;      // fp32 rows; perceptron on fp32 matrix cores
 constexpr int kRowsBF16 = 1;     // bf16 rows; bf16 perceptron (FP16 form)
 constexpr int kRowsSplit16 = 2;  // fp32 rows split into fp16 hi/lo in the perceptron (FP32 form)
+constexpr int kRowsHiLo16 = 3;   // rows written as fp16 hi/lo pairs by the encoder: each group of
+                                 // 4 consecutive elements is a 16-byte unit [hi x 4, lo x 4]
+                                 // (FP32 form)
 
 struct MlpWeights {
   int hidden = 0;
