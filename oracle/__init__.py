@@ -20,6 +20,13 @@ Contents
 
 These two numpy routines are independent routes to the same numbers and
 are used to pin the C oracle (they share no code with it).
+
+  * ``mlp_train_step`` -- one training step of the perceptron on a batch of
+    encodings with target normal flows (the paper delegates its loss to its
+    predecessor, so the loss here is our own: the mean over rows of the
+    squared error of the 2-vector), with the gradients of layer 2 and layer 1
+    written out by the chain rule, then plain gradient descent or Adam.
+    FP64, numpy.
 """
 from __future__ import annotations
 
@@ -202,3 +209,54 @@ def pooling_form_3d(events, A, rx, ry, rt, queries=None):
         out[i, :D], out[i, D:] = e.real, e.imag
         cnt[i] = c
     return out, cnt
+
+
+def mlp_loss_grads(x, y, W1, b1, W2, b2):
+    """Loss and gradients of L = (1/M) sum_r ||W2 relu(W1 x_r + b1) + b2 - y_r||^2.
+
+    x: [M, K2], y: [M, 2].  The ReLU derivative at 0 is taken as 0.
+    Returns (L, dict(W1=..., b1=..., W2=..., b2=...)), all FP64."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    W1 = np.asarray(W1, np.float64); b1 = np.asarray(b1, np.float64)
+    W2 = np.asarray(W2, np.float64); b2 = np.asarray(b2, np.float64)
+    M = x.shape[0]
+    z = x @ W1.T + b1                 # pre-activations [M, hidden]
+    h = np.maximum(z, 0.0)
+    p = h @ W2.T + b2                 # predictions [M, 2]
+    r = p - y
+    L = float((r * r).sum() / M)
+    dp = 2.0 * r / M                  # dL/dp
+    gW2 = dp.T @ h
+    gb2 = dp.sum(0)
+    dz = (dp @ W2) * (z > 0)          # back through W2 and the ReLU
+    gW1 = dz.T @ x
+    gb1 = dz.sum(0)
+    return L, dict(W1=gW1, b1=gb1, W2=gW2, b2=gb2)
+
+
+def mlp_train_step(x, y, params, opt="sgd", lr=1e-3, state=None, t=1, betas=(0.9, 0.999),
+                   eps=1e-8):
+    """One step on (x, y): returns (loss, grads, new params, new state).
+
+    params: dict W1, b1, W2, b2.  opt "sgd": p - lr g.  opt "adam": the
+    moment estimates m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2 (state
+    holds them, zero before step 1), bias-corrected by 1 - b^t, and
+    p - lr m_hat / (sqrt(v_hat) + eps)."""
+    L, g = mlp_loss_grads(x, y, params["W1"], params["b1"], params["W2"], params["b2"])
+    new, st = {}, {}
+    for k in ("W1", "b1", "W2", "b2"):
+        p = np.asarray(params[k], np.float64)
+        if opt == "sgd":
+            new[k] = p - lr * g[k]
+        else:
+            m0 = np.zeros_like(p) if state is None else state["m"][k]
+            v0 = np.zeros_like(p) if state is None else state["v"][k]
+            m1 = betas[0] * m0 + (1.0 - betas[0]) * g[k]
+            v1 = betas[1] * v0 + (1.0 - betas[1]) * g[k] * g[k]
+            mh = m1 / (1.0 - betas[0] ** t)
+            vh = v1 / (1.0 - betas[1] ** t)
+            new[k] = p - lr * mh / (np.sqrt(vh) + eps)
+            st.setdefault("m", {})[k] = m1
+            st.setdefault("v", {})[k] = v1
+    return L, g, new, (st if opt == "adam" else None)

@@ -150,7 +150,9 @@ def stream_slices(spec: StreamSpec, count: int):
 
 
 def _edge_events(rng, W, H, T, count, E):
-    """Events of E moving edges, ``count`` in total, as float positions."""
+    """Events of E moving edges, ``count`` in total, and the true normal flow
+    of each (sign * speed * normal, px per bin; NaN for the noise that tops
+    up an edge that rarely crosses the sensor)."""
     theta = rng.uniform(0.0, math.pi, E)
     nu = np.stack([np.cos(theta), np.sin(theta)], 1)
     nu_perp = np.stack([-np.sin(theta), np.cos(theta)], 1)
@@ -161,7 +163,7 @@ def _edge_events(rng, W, H, T, count, E):
     pol = rng.choice([-1, 1], E)
     share = np.full(E, count // E, dtype=np.int64)
     share[: count - share.sum()] += 1
-    xs, ys, ts, ps = [], [], [], []
+    xs, ys, ts, ps, fs = [], [], [], [], []
     for e in range(E):
         need = int(share[e])
         got = 0
@@ -182,12 +184,15 @@ def _edge_events(rng, W, H, T, count, E):
             x, y, t = x[ok][: need - got], y[ok][: need - got], t[ok][: need - got]
             xs.append(x); ys.append(y); ts.append(t)
             ps.append(np.full(len(x), pol[e], dtype=np.int64))
+            fs.append(np.tile(sign[e] * speed[e] * nu[e], (len(x), 1)))
             got += len(x)
         if got < need:  # an edge that almost never crosses the sensor: top up with noise
             k = need - got
             xs.append(rng.integers(0, W, k)); ys.append(rng.integers(0, H, k))
             ts.append(rng.integers(0, T, k)); ps.append(rng.choice([-1, 1], k))
-    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), np.concatenate(ps))
+            fs.append(np.full((k, 2), np.nan))
+    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(ts), np.concatenate(ps),
+            np.concatenate(fs))
 
 
 def _blob_noise(rng, W, H, T, count, blobs=32):
@@ -217,16 +222,20 @@ def _blob_noise(rng, W, H, T, count, blobs=32):
     return x, y, t, p
 
 
-def make_slice(spec: SliceSpec):
-    """Return (events int32[n,4] as (x, y, t, p), t0, nbins).
+def make_slice(spec: SliceSpec, with_flow: bool = False):
+    """Return (events int32[n,4] as (x, y, t, p), t0, nbins), and with
+    ``with_flow`` also the true normal flow float64[n, 2] of every event (px
+    per bin; NaN for noise events).
 
     t is absolute (``t_base`` + bin); every event satisfies
-    t0 <= t < t0 + nbins and 0 <= x < width, 0 <= y < height."""
+    t0 <= t < t0 + nbins and 0 <= x < width, 0 <= y < height.  The flow is
+    computed alongside and draws no random numbers, so the events do not
+    depend on ``with_flow``."""
     rng = np.random.Generator(np.random.PCG64(spec.seed))
     W, H, T = spec.width, spec.height, spec.nbins
     n_noise = int(round(spec.noise_frac * spec.n))
     n_edge = spec.n - n_noise
-    ex, ey, et, ep = _edge_events(rng, W, H, T, n_edge, spec.edges)
+    ex, ey, et, ep, ef = _edge_events(rng, W, H, T, n_edge, spec.edges)
     if spec.blob_noise:
         nx, ny, nt, np_ = _blob_noise(rng, W, H, T, n_noise)
     else:
@@ -234,10 +243,13 @@ def make_slice(spec: SliceSpec):
         nt = rng.integers(0, T, n_noise); np_ = rng.choice([-1, 1], n_noise)
     x = np.concatenate([ex, nx]); y = np.concatenate([ey, ny])
     t = np.concatenate([et, nt]); p = np.concatenate([ep, np_])
+    f = np.concatenate([ef, np.full((len(nx), 2), np.nan)])
     perm = rng.permutation(len(x))          # seeded tie-break ...
-    x, y, t, p = x[perm], y[perm], t[perm], p[perm]
+    x, y, t, p, f = x[perm], y[perm], t[perm], p[perm], f[perm]
     order = np.argsort(t, kind="stable")    # ... then camera (time) order
     ev = np.stack([x[order], y[order], t[order] + spec.t_base, p[order]], 1).astype(np.int32)
+    if with_flow:
+        return np.ascontiguousarray(ev), int(spec.t_base), int(T), np.ascontiguousarray(f[order])
     return np.ascontiguousarray(ev), int(spec.t_base), int(T)
 
 
