@@ -232,6 +232,38 @@ int veckm_window_encode(veckm_ctx* ctx, const veckm_event* queries, int64_t m, f
 int veckm_window_flow(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* flow,
                       void* stream);
 
+/* ---- training the perceptron --------------------------------------------- */
+
+/* Trains the two-layer perceptron (Sec. 2.1, Eqns. 5-6) on encodings with
+   known normal flows.  The paper leaves its loss and sampling to its
+   predecessor; the loss here is the mean over the rows of the squared error
+   of the predicted 2-vector, L = (1/m) sum_r ||flow_r - target_r||^2, with
+   plain gradient descent or Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
+   corrected).  All arithmetic is fp32 on the device; a step is deterministic.
+   The trainer keeps its own copy of the weights: read them back with
+   veckm_trainer_get and hand them to veckm_set_mlp to use them. */
+typedef struct veckm_trainer veckm_trainer;
+
+/* Creates a trainer on the current HIP device for encodings of dimension
+   2d and `hidden` units (a multiple of 64, at most 512), initialised with the
+   host weights (layouts as veckm_set_mlp), for steps of up to max_rows rows.
+   Allocates everything up front.  VECKM_E_INVAL on bad sizes, VECKM_E_NOMEM,
+   VECKM_E_NODEVICE. */
+int veckm_trainer_create(int32_t d, int32_t hidden, int64_t max_rows, const float* W1,
+                         const float* b1, const float* W2, const float* b2, veckm_trainer** out);
+void veckm_trainer_destroy(veckm_trainer* tr);
+
+/* One step on m rows: emb device [m][2d] float32 (as veckm_encode writes
+   them), target device [m][2] float32.  optimizer 0: w -= lr g; 1: Adam.
+   loss: device float receiving this step's loss (before the update), or
+   NULL.  Asynchronous on `stream`.  VECKM_E_RANGE if m exceeds max_rows. */
+int veckm_trainer_step(veckm_trainer* tr, const float* emb, const float* target, int64_t m,
+                       int32_t optimizer, float lr, float* loss, void* stream);
+
+/* Copies the current weights to host arrays (layouts as veckm_set_mlp);
+   waits for the device. */
+int veckm_trainer_get(veckm_trainer* tr, float* W1, float* b1, float* W2, float* b2);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Stages of one compute call, in launch order. */

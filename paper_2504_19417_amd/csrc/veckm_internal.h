@@ -200,6 +200,30 @@ int launch_window_push(const Workspace& w, const veckm_event* ev, int64_t n, int
 int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event* queries,
                           const EncodeTables& et, void* stream);
 
+// ------------------------------------------------------------ perceptron training
+// Device state of a trainer: parameters and gradients in the order W1
+// [hidden][k2], b1, W2 [2][hidden], b2 (the gradient buffer has one more
+// slot: the step's loss), Adam moments, layer-1 activations and their
+// gradients for max_rows rows, and partial-sum buffers.
+struct TrainState {
+  int k2 = 0, hidden = 0;
+  int64_t max_rows = 0;
+  float* theta = nullptr;
+  float* grad = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  float* H = nullptr;
+  float* dZ = nullptr;
+  float* head_part = nullptr;  // head_blocks x (3 hidden + 3)
+  float* w1_part = nullptr;    // max_splits x hidden x k2
+  int head_blocks = 0, max_splits = 0;
+};
+// One step on m rows x [m][k2] (device) with targets y [m][2] (device):
+// forward, loss, gradients, update (adam 0: gradient descent; 1: Adam with
+// bias corrections c1, c2).  Leaves the loss in grad[n_params].
+int launch_train_step(const TrainState& s, const float* x, const float* y, int64_t m, int adam,
+                      float lr, float c1, float c2, void* stream);
+
 // ------------------------------------------------- context hooks for the server
 // What one call can hold, and what one slice needs of it.
 struct Capacity {

@@ -103,6 +103,12 @@ _sig = {
                                          _P]),
     "veckm_window_encode": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "veckm_window_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "veckm_trainer_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P,
+                                            _P, _P, ctypes.POINTER(_P)]),
+    "veckm_trainer_destroy": (None, [_P]),
+    "veckm_trainer_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_float, _P, _P]),
+    "veckm_trainer_get": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "veckm_server_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.c_int64,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]),
     "veckm_server_destroy": (None, [_P]),
@@ -475,6 +481,59 @@ class Window(Context):
         if rc:
             raise VeckmError(rc, "veckm_window_flow")
         return out
+
+
+class Trainer:
+    """Trains the perceptron on device encodings with target flows (torch
+    CUDA tensors); weights come and go as numpy float32 arrays."""
+
+    def __init__(self, d, hidden, max_rows, W1, b1, W2, b2):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in (W1, b1, W2, b2)]
+        if arrs[0].shape != (hidden, 2 * d) or arrs[1].shape != (hidden,) or \
+                arrs[2].shape != (2, hidden) or arrs[3].shape != (2,):
+            raise ValueError("perceptron shapes do not match")
+        h = _P()
+        rc = _lib.veckm_trainer_create(int(d), int(hidden), int(max_rows),
+                                       *[a.ctypes.data for a in arrs], ctypes.byref(h))
+        if rc:
+            raise VeckmError(rc, "veckm_trainer_create")
+        self.handle, self.d, self.hidden = h, d, hidden
+
+    def close(self):
+        if self.handle:
+            _lib.veckm_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, emb, target, optimizer="adam", lr=1e-3, loss=None, stream=None):
+        import torch
+        for t, w in ((emb, 2 * self.d), (target, 2)):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[1] == w
+                    and t.is_contiguous()):
+                raise ValueError("emb [m, 2d] and target [m, 2] must be contiguous float32 CUDA")
+        s = torch.cuda.current_stream() if stream is None else stream
+        rc = _lib.veckm_trainer_step(self.handle, emb.data_ptr(), target.data_ptr(),
+                                     int(emb.shape[0]), 0 if optimizer == "sgd" else 1,
+                                     float(lr), None if loss is None else loss.data_ptr(),
+                                     ctypes.c_void_p(s.cuda_stream))
+        if rc:
+            raise VeckmError(rc, "veckm_trainer_step")
+
+    def weights(self):
+        W1 = np.zeros((self.hidden, 2 * self.d), np.float32)
+        b1 = np.zeros(self.hidden, np.float32)
+        W2 = np.zeros((2, self.hidden), np.float32)
+        b2 = np.zeros(2, np.float32)
+        rc = _lib.veckm_trainer_get(self.handle, W1.ctypes.data, b1.ctypes.data, W2.ctypes.data,
+                                    b2.ctypes.data)
+        if rc:
+            raise VeckmError(rc, "veckm_trainer_get")
+        return W1, b1, W2, b2
 
 
 class Server:

@@ -28,7 +28,9 @@ def test_header_declares_api():
                      "veckm_flow_batch", "veckm_server_create", "veckm_server_destroy",
                      "veckm_server_set_mlp", "veckm_stream_open", "veckm_stream_close",
                      "veckm_submit", "veckm_poll", "veckm_server_stats", "veckm_window_create",
-                     "veckm_window_push", "veckm_window_encode", "veckm_window_flow"]:
+                     "veckm_window_push", "veckm_window_encode", "veckm_window_flow",
+                     "veckm_trainer_create", "veckm_trainer_step", "veckm_trainer_get",
+                     "veckm_trainer_destroy"]:
         assert required in names
 
 
@@ -181,6 +183,18 @@ def test_window_checks_before_device():
     assert veckm._lib.veckm_window_push(None, None, 0, 0, 1, None) == veckm.VECKM_E_INVAL
     assert veckm._lib.veckm_window_encode(None, None, 0, None, None) == veckm.VECKM_E_INVAL
     assert veckm._lib.veckm_window_flow(None, None, 0, None, None) == veckm.VECKM_E_INVAL
+
+
+def test_trainer_argument_checks():
+    z = np.zeros(1, np.float32).ctypes.data
+    h = ctypes.c_void_p()
+    for d, hidden, rows in ((0, 64, 10), (64, 32, 10), (64, 96, 10), (64, 576, 10), (64, 64, 0)):
+        assert veckm._lib.veckm_trainer_create(d, hidden, rows, z, z, z, z, ctypes.byref(h)) == \
+            veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_trainer_step(None, None, None, 1, 0, 0.1, None, None) == \
+        veckm.VECKM_E_INVAL
+    assert veckm._lib.veckm_trainer_get(None, None, None, None, None) == veckm.VECKM_E_INVAL
+    veckm._lib.veckm_trainer_destroy(None)
 
 
 def test_server_null_handles():
