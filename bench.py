@@ -214,7 +214,8 @@ def serving_run(vk, seconds, pool=3):
 KERNEL_SOURCES = {  # kernel name prefix (template form) -> source file it is built from
     "k_encode<4": "paper_2504_19417_amd/csrc/kernels_encode.hip",   # FP32 form encoder
     "k_encode<2": "paper_2504_19417_amd/csrc/kernels_encode.hip",   # FP16 form encoder
-    "k_mlp_split<": "paper_2504_19417_amd/csrc/kernels_mlp.hip",    # FP32 form perceptron
+    "k_mlp_res<2": "paper_2504_19417_amd/csrc/kernels_mlp.hip",     # FP32 form perceptron
+    "k_mlp_split<": "paper_2504_19417_amd/csrc/kernels_mlp.hip",    # FP32 form, paper form
     "k_mlp_res<0": "paper_2504_19417_amd/csrc/kernels_mlp.hip",     # FP16 form perceptron
     "k_pool2d<": "paper_2504_19417_amd/csrc/kernels_paper.hip",     # paper form window sum
     "k_tphase<": "paper_2504_19417_amd/csrc/kernels_paper.hip",     # paper form phase sums
@@ -286,8 +287,9 @@ PROFILE_WORKLOADS = {
                  "queries",
 }
 PROFILE_NOTES = {
-    "slice1m": "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `<4, ...>` "
-               "encoder and `k_mlp_split` belong to the FP32 form, `<2, ...>` encoder and "
+    "slice1m": "Each form runs 2 warm-up + 5 timed steps (7 calls per form; the 10k-query "
+               "run is skipped).  The `<4, ...>` encoder (writing fp16 hi/lo rows) and "
+               "`k_mlp_res<2, ...>` belong to the FP32 form, the `<2, ...>` encoder and "
                "`k_mlp_res<0, ...>` to the FP16/BF16 form; the small kernels serve both.  "
                "`__amd_rocclr_*` are runtime copies and fills outside the steps.",
     "paper_k8": "Three runs of 2 warm-up + 5 timed steps: FP32 form over all events, FP16/BF16 "
@@ -596,6 +598,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the 10k-query run (profiling runs: one call size per kernel)")
     ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="real-time replay of the 32-stream serving workload (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -655,10 +659,12 @@ def main():
     for form in ("fp32", "fp16"):
         res[form] = run_form(vk, torch, w, ev, t0, T, A, mlp, form, args.steps, args.warmup)
     # sparse query set (Eqn. 18's C m term shrinks, the c n term stays)
-    q10k = synth.sample_queries(n, 10_000, 79)
-    sparse = run_form(vk, torch, w, ev, t0, T, A, mlp, "fp32", args.steps, args.warmup,
-                      queries=q10k)
-    ms_sparse = sparse["elapsed"] / args.steps * 1e3
+    sparse = None
+    if not args.no_sparse:
+        q10k = synth.sample_queries(n, 10_000, 79)
+        sparse = run_form(vk, torch, w, ev, t0, T, A, mlp, "fp32", args.steps, args.warmup,
+                          queries=q10k)
+        ms_sparse = sparse["elapsed"] / args.steps * 1e3
 
     def summary(r):
         ms = r["elapsed"] / args.steps * 1e3
@@ -675,7 +681,7 @@ def main():
                        peak=PEAK["fp16_TFLOPs"], kernel="k_encode<4"),
         # FP32-form perceptron: fp16 hi/lo operand pairs on the fp16 matrix cores
         "mlp": dict(ms=st32["mlp"], flops=mlp_flops_per_row(w.d, w.hidden) * rows,
-                    peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_split<"),
+                    peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_res<2"),
     }
     dom = max(cand, key=lambda k: cand[k]["ms"])
     c = cand[dom]
@@ -723,10 +729,11 @@ def main():
             "err_vs_oracle": {"flow_relL2_sampled": err16},
             "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
         },
-        "sparse_10k_queries": {"ms_per_call": round(ms_sparse, 4),
-                               "stages_ms": {k: (round(v[0] / v[1], 4) if v[1] else None)
-                                             for k, v in sparse["stages"].items()},
-                               "eqn18": eqn18_split(n, 10_000, ms_sparse, ms32)},
+        "sparse_10k_queries": None if sparse is None else {
+            "ms_per_call": round(ms_sparse, 4),
+            "stages_ms": {k: (round(v[0] / v[1], 4) if v[1] else None)
+                          for k, v in sparse["stages"].items()},
+            "eqn18": eqn18_split(n, 10_000, ms_sparse, ms32)},
         "rows": rows,
         "roofline": roofline,
         "serving": serving,
