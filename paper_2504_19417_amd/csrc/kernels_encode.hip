@@ -103,8 +103,8 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // Waves per block and the most 16-frequency tiles one wave holds.
 constexpr int kEncWaves = 16;
 constexpr int kEncMaxNtw = 4;
-// Fetch the next k-step's count words while the current step multiplies.
-constexpr bool kEncPrefetch = false;
+// With four slab buffers, take the k-steps in pairs: one barrier per pair.
+constexpr bool kEncPairSteps = true;
 
 template <int NA, int NT>
 struct EncShape {
@@ -183,6 +183,79 @@ struct CountWords {
 // accumulator of a lane holds 4 consecutive frequencies of one row (the
 // lane's row is lane & 15): the count of that row arrives in the same lane
 // and the row is written with 16-byte stores.
+// One k-step of the contraction for a wave with MTV valid row tiles: the
+// count pair sums of its rows (gathered from the box), the table slab `sb`
+// as A operand, and the exact neighbour count on the vector ALU.
+template <int NA, int NT, int MTV>
+__device__ inline void kstep_compute(int ks, const uint4* sb, const int32_t* runs_l,
+                                     const uint16_t* wts_l, const uint32_t* vol2,
+                                     const int (&rb)[EncShape<NA, NT>::MT],
+                                     floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                     floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
+                                     float (&cnt)[EncShape<NA, NT>::MT], int wn, int lane) {
+  using S = EncShape<NA, NT>;
+  constexpr int NTW = S::NTW;
+  const int g = lane >> 4;
+  CountWords<MTV> cw;
+  if constexpr (MTV > 0) {
+    cw.fetch(runs_l, vol2, rb, ks, g);
+    // pair sums and differences of counts at +o / -o: the -o run comes out
+    // of the pair layout descending and half-swapped
+    half8 cS[MTV], cD[MTV];
+#pragma unroll
+    for (int mt = 0; mt < MTV; ++mt) {
+      uint4 s4, d4;
+      s4.x = pk_sum_swapped(cw.P[mt][0], cw.Q[mt][0]);
+      s4.y = pk_sum_swapped(cw.P[mt][1], cw.Q[mt][1]);
+      s4.z = pk_sum_swapped(cw.P[mt][2], cw.Q[mt][2]);
+      s4.w = pk_sum_swapped(cw.P[mt][3], cw.Q[mt][3]);
+      d4.x = pk_diff_swapped(cw.P[mt][0], cw.Q[mt][0]);
+      d4.y = pk_diff_swapped(cw.P[mt][1], cw.Q[mt][1]);
+      d4.z = pk_diff_swapped(cw.P[mt][2], cw.Q[mt][2]);
+      d4.w = pk_diff_swapped(cw.P[mt][3], cw.Q[mt][3]);
+      cS[mt] = as_half8(s4);
+      cD[mt] = as_half8(d4);
+    }
+    const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) {
+      half8 tf[NA];
+#pragma unroll
+      for (int q = 0; q < NA; ++q) tf[q] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt) {
+        if constexpr (NA == 4) {
+          accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
+          accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[2], cD[mt], accI[mt][nt], 0, 0, 0);
+          accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cS[mt], accR[mt][nt], 0, 0, 0);
+          accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[3], cD[mt], accI[mt][nt], 0, 0, 0);
+        } else {
+          accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
+          accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cD[mt], accI[mt][nt], 0, 0, 0);
+        }
+      }
+    }
+    // neighbour count: the slot weights (1, 1/2 for the centre, 0 for
+    // padding) against the pair sums, exact in fp32; the lane covers its 8
+    // slots of the row, the 4 lanes of a row are added after the loop
+#pragma unroll
+    for (int mt = 0; mt < MTV; ++mt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        cnt[mt] = __builtin_amdgcn_fdot2(half2v{bw[2 * e], bw[2 * e + 1]},
+                                         half2v{cS[mt][2 * e], cS[mt][2 * e + 1]}, cnt[mt], false);
+  }
+}
+
+// The k-steps of one chunk for a wave that holds MTV valid 16-row tiles
+// (0 <= MTV <= MT; no per-tile branches inside).  Every wave runs it: a wave
+// without rows still moves its share of each slab and meets every barrier.
+// On entry the first slab is in LDS and the next NBUF - 2 are in flight.
+//
+// The table is the MFMA A operand and the counts the B operand, so that the
+// accumulator of a lane holds 4 consecutive frequencies of one row (the
+// lane's row is lane & 15): the count of that row arrives in the same lane
+// and the row is written with 16-byte stores.
 template <int NA, int NT, int NBUF, int MTV>
 __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
                                     const int32_t* runs_l, const uint16_t* wts_l,
@@ -192,73 +265,41 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
                                     float (&cnt)[EncShape<NA, NT>::MT], int wn, int wid,
                                     int lane) {
   using S = EncShape<NA, NT>;
-  constexpr int NW = S::NW, NTW = S::NTW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
-  constexpr int AHEAD = NBUF - 1;
-  const int g = lane >> 4;
-  CountWords<MTV> cw;
-  if constexpr (MTV > 0 && kEncPrefetch) cw.fetch(runs_l, vol2, rb, 0, g);
-  for (int ks = 0; ks < nsteps; ++ks) {
-    const int buf = ks % NBUF;
-    // start the slab AHEAD steps out now, so that it lands during this step:
-    // its buffer was last read in step ks - 1, before the last barrier
-    if (ks + AHEAD < nsteps)
-      issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
-                              slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
-    if constexpr (MTV > 0) {
-      if constexpr (!kEncPrefetch) cw.fetch(runs_l, vol2, rb, ks, g);
-      // pair sums and differences of counts at +o / -o: the -o run comes out
-      // of the pair layout descending and half-swapped
-      half8 cS[MTV], cD[MTV];
+  constexpr int NW = S::NW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
+  if constexpr (kEncPairSteps && NBUF == 4) {
+    // two k-steps per barrier: the slabs of the next pair go into the two
+    // buffers the previous pair used (free since the last barrier) and land
+    // while this pair multiplies; on entry slabs 0 and 1 are in LDS
+    for (int ks = 0; ks < nsteps; ks += 2) {
 #pragma unroll
-      for (int mt = 0; mt < MTV; ++mt) {
-        uint4 s4, d4;
-        s4.x = pk_sum_swapped(cw.P[mt][0], cw.Q[mt][0]);
-        s4.y = pk_sum_swapped(cw.P[mt][1], cw.Q[mt][1]);
-        s4.z = pk_sum_swapped(cw.P[mt][2], cw.Q[mt][2]);
-        s4.w = pk_sum_swapped(cw.P[mt][3], cw.Q[mt][3]);
-        d4.x = pk_diff_swapped(cw.P[mt][0], cw.Q[mt][0]);
-        d4.y = pk_diff_swapped(cw.P[mt][1], cw.Q[mt][1]);
-        d4.z = pk_diff_swapped(cw.P[mt][2], cw.Q[mt][2]);
-        d4.w = pk_diff_swapped(cw.P[mt][3], cw.Q[mt][3]);
-        cS[mt] = as_half8(s4);
-        cD[mt] = as_half8(d4);
-      }
-      const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
-      const uint4* sb = slab + buf * SLAB_U4;
-      if (kEncPrefetch && ks + 1 < nsteps) cw.fetch(runs_l, vol2, rb, ks + 1, g);
-#pragma unroll
-      for (int nt = 0; nt < NTW; ++nt) {
-        half8 tf[NA];
-#pragma unroll
-        for (int q = 0; q < NA; ++q) tf[q] = as_half8(sb[(q * NT + wn * NTW + nt) * 64 + lane]);
-#pragma unroll
-        for (int mt = 0; mt < MTV; ++mt) {
-          if constexpr (NA == 4) {
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[2], cD[mt], accI[mt][nt], 0, 0, 0);
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cS[mt], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[3], cD[mt], accI[mt][nt], 0, 0, 0);
-          } else {
-            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[0], cS[mt], accR[mt][nt], 0, 0, 0);
-            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tf[1], cD[mt], accI[mt][nt], 0, 0, 0);
-          }
-        }
-      }
-      // neighbour count: the slot weights (1, 1/2 for the centre, 0 for
-      // padding) against the pair sums, exact in fp32; the lane covers its 8
-      // slots of the row, the 4 lanes of a row are added after the loop
-#pragma unroll
-      for (int mt = 0; mt < MTV; ++mt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          cnt[mt] = __builtin_amdgcn_fdot2(half2v{bw[2 * e], bw[2 * e + 1]},
-                                           half2v{cS[mt][2 * e], cS[mt][2 * e + 1]}, cnt[mt], false);
+      for (int u = 2; u < 4; ++u)
+        if (ks + u < nsteps)
+          issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + u) * SLAB_U4,
+                                  slab + ((ks + u) % 4) * SLAB_U4, wid, lane);
+      kstep_compute<NA, NT, MTV>(ks, slab + (ks % 4) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
+                                 accI, cnt, wn, lane);
+      if (ks + 1 < nsteps)
+        kstep_compute<NA, NT, MTV>(ks + 1, slab + ((ks + 1) % 4) * SLAB_U4, runs_l, wts_l, vol2,
+                                   rb, accR, accI, cnt, wn, lane);
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));  // the next pair has landed
+      lds_barrier();
     }
-    // make sure the slab of step ks + 1 has landed (slabs ks + 2 .. ks +
-    // AHEAD may stay in flight)
-    const int last = ks + AHEAD < nsteps - 1 ? ks + AHEAD : nsteps - 1;  // newest slab issued
-    wait_slabs<PFW>(last - ks - 1 > 0 ? last - ks - 1 : 0);
-    lds_barrier();
+  } else {
+    constexpr int AHEAD = NBUF - 1;
+    for (int ks = 0; ks < nsteps; ++ks) {
+      // start the slab AHEAD steps out now, so that it lands during this
+      // step: its buffer was last read in step ks - 1, before the last barrier
+      if (ks + AHEAD < nsteps)
+        issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
+                                slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
+      kstep_compute<NA, NT, MTV>(ks, slab + (ks % NBUF) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
+                                 accI, cnt, wn, lane);
+      // make sure the slab of step ks + 1 has landed (slabs ks + 2 .. ks +
+      // AHEAD may stay in flight)
+      const int last = ks + AHEAD < nsteps - 1 ? ks + AHEAD : nsteps - 1;  // newest slab issued
+      wait_slabs<PFW>(last - ks - 1 > 0 ? last - ks - 1 : 0);
+      lds_barrier();
+    }
   }
 }
 
@@ -366,11 +407,20 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx + kRunPad);
       }
       // first slabs of the table
+      if constexpr (kEncPairSteps && NBUF == 4) {
+        // the first pair (and the box) has landed
 #pragma unroll
-      for (int u = 0; u < AHEAD; ++u)
-        if (u < a.nsteps)
-          issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
-      wait_slabs<PFW>((a.nsteps < AHEAD ? a.nsteps : AHEAD) - 1);  // slab 0 (and the box) landed
+        for (int u = 0; u < 2; ++u)
+          if (u < a.nsteps)
+            issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+      } else {
+#pragma unroll
+        for (int u = 0; u < AHEAD; ++u)
+          if (u < a.nsteps)
+            issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
+        wait_slabs<PFW>((a.nsteps < AHEAD ? a.nsteps : AHEAD) - 1);  // slab 0 (and the box) landed
+      }
       lds_barrier();
 
       // tiles are dealt round-robin over the row waves, so a short chunk
