@@ -533,6 +533,75 @@ def window_main(args):
     print(json.dumps(line), flush=True)
 
 
+def batch_main(args):
+    """The batched form: 64 slices (lognormal 10k-500k events, 346x260 and
+    640x480 sensors, 50 bins, D = 128, r = 5/3) in one launch sequence per
+    step, every event queried; FP16/BF16 form (the configuration's precision)
+    and FP32 form."""
+    import torch
+    import oracle
+    from paper_2504_19417_amd import synth, veckm as vk
+
+    w = synth.workloads()["batch64"]
+    parts = [synth.make_slice(s) for s in w.slices]
+    A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
+    mlp = synth.init_mlp(w.d, w.hidden)
+    specs = [(s.width, s.height, t0, T, len(e)) for s, (e, t0, T) in zip(w.slices, parts)]
+    ev = np.concatenate([p[0] for p in parts]).astype(np.int32)
+    n = len(ev)
+    evt = torch.from_numpy(ev).cuda()
+    res = {}
+    for form in ("fp16", "fp32"):
+        c = vk.Context(640, 480, w.rx, w.ry, w.rt, A, 50, n, form, max_slices=64)
+        c.set_mlp(*mlp)
+        out = torch.empty((n, 2), device="cuda")
+        for _ in range(args.warmup):
+            c.flow_batch(specs, evt, out=out)
+        torch.cuda.synchronize()
+        c.profile(True)
+        c.profile_read()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            c.flow_batch(specs, evt, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        st = {k: (round(v[0] / v[1], 4) if v[1] else None) for k, v in c.profile_read().items()}
+        status = c.status()
+        flows = out.cpu().numpy()
+        c.close()
+        if status != vk.VECKM_OK:
+            raise RuntimeError("input error reported by the device")
+        # 16 sampled events per slice against the oracle
+        got, ref, off = [], [], 0
+        for k, (e, t0, T) in enumerate(parts):
+            q = synth.sample_queries(len(e), 16, 600 + k)
+            emb, _ = oracle.encode(e, A, w.rx, w.ry, w.rt, queries=q)
+            ref.append(oracle.mlp(emb, *mlp))
+            got.append(flows[off + q])
+            off += len(e)
+        got, ref = np.concatenate(got).astype(np.float64), np.concatenate(ref)
+        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st,
+                         err=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    line = {
+        "metric": "normal flows/sec, 64-slice batch in one launch sequence (BF16 perceptron)",
+        "value": res["fp16"]["value"], "unit": "flows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["fp16"]["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
+        "data": "synthetic (seeded moving edges + 10% uniform noise, 64 slices)",
+        "config": {"workload": "batch64", "slices": 64, "events": n,
+                   "sensors": "346x260 / 640x480", "bins": 50, "d": w.d, "radius_xy": w.rx,
+                   "radius_t": w.rt, "hidden": w.hidden, "queries": "all events"},
+        "stages_ms": res["fp16"]["stages"],
+        "err_vs_oracle": {"flow_relL2_sampled": res["fp16"]["err"]},
+        "fp32": {"value": res["fp32"]["value"], "ms_per_step": round(res["fp32"]["ms"], 4),
+                 "stages_ms": res["fp32"]["stages"],
+                 "err_vs_oracle": {"flow_relL2_sampled": res["fp32"]["err"]}},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def train_main(args):
     """Training the perceptron on the 1M-event slice's edge events (about 0.9M
     rows of FP32 encodings, D = 128, hidden 256, their true normal flows):
@@ -591,7 +660,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="slice1m",
-                    choices=["slice1m", "paper_k8", "paper_k10", "window", "train"],
+                    choices=["slice1m", "paper_k8", "paper_k10", "window", "train", "batch64"],
                     help="slice1m: the bounded-window 1M-event slice (the headline line); "
                          "paper_k8 / paper_k10: the paper's own form at its recipes")
     ap.add_argument("--steps", type=int, default=20)
@@ -639,6 +708,9 @@ def main():
         return
     if args.workload == "train":
         train_main(args)
+        return
+    if args.workload == "batch64":
+        batch_main(args)
         return
     if args.workload != "slice1m":
         paper_main(args, args.workload)
