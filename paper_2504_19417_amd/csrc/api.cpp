@@ -129,7 +129,8 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   bytes += s.V * (4 + 4 + 1);                     // count, rank, qmark
   if (p->rt >= 0) bytes += s.P * 4;               // pair grid
   bytes += s.nb * s.bv * 4;                       // ulist
-  bytes += (3 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
+  bytes += (6 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
+  bytes += (scan_tiles(s.nb) + 1) * kScanNV * 4;  // brick-scan partials
   bytes += s.n * (4 + 4);                         // vox, qmap
   bytes += s.U * 2 * p->d * 4 + s.U * 8;          // rows (fp32 size), rowflow
   bytes += (int64_t)kp * p->d * na * 2 + kp * 3;  // phase table, run offsets, weights
@@ -178,6 +179,7 @@ int single_batch(const veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t
   bt->m = (int)m;
   bt->nvox = V;
   bt->npairs = P;
+  bt->max_rows = (int64_t)c->p.height * nbins;
   return VECKM_OK;
 }
 
@@ -188,7 +190,7 @@ int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_
   *slot = -1;
   if (!sl || count < 1 || count > c->max_slices) return VECKM_E_INVAL;
   std::vector<SliceDesc> tab((size_t)count);
-  int64_t evs = 0, vox = 0, prs = 0, bricks = 0;
+  int64_t evs = 0, vox = 0, prs = 0, bricks = 0, max_rows = 0;
   for (int k = 0; k < count; ++k) {
     const veckm_slice& s = sl[k];
     if (s.n < 0 || s.offset != evs) return VECKM_E_INVAL;
@@ -200,6 +202,7 @@ int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_
     evs += s.n;
     vox += (int64_t)s.width * s.height * s.nbins;
     prs += (int64_t)(s.width + 1) * s.height * s.nbins;
+    max_rows = std::max(max_rows, (int64_t)s.height * s.nbins);
     bricks += bricks_of(s.width, s.height, s.nbins, c->et.brick);
   }
   if (vox > c->w.vmax || prs > c->w.pmax || bricks > c->w.bmax) return VECKM_E_RANGE;
@@ -222,6 +225,7 @@ int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_
   bt->m = (int)evs;
   bt->nvox = vox;
   bt->npairs = prs;
+  bt->max_rows = max_rows;
   return VECKM_OK;
 }
 
@@ -430,7 +434,8 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
   rc = rc ? rc : dalloc(c->allocs, &w.brick_nq, (size_t)s.nb);
   rc = rc ? rc : dalloc(c->allocs, &w.brick_off, (size_t)s.nb + 1);
-  rc = rc ? rc : dalloc(c->allocs, &w.order, (size_t)s.nb);
+  rc = rc ? rc : dalloc(c->allocs, &w.order, (size_t)s.nb * 4);
+  rc = rc ? rc : dalloc(c->allocs, &w.scan_part, (size_t)((scan_tiles(s.nb) + 1) * kScanNV));
   rc = rc ? rc : dalloc(c->allocs, &w.vox, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &w.qmap, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &rows, (size_t)(s.U * 2 * params->d));
@@ -649,6 +654,7 @@ int window_batch(veckm_ctx* c, const veckm_event* queries, int64_t m, const void
   bt->m = (int)m;
   bt->nvox = (int64_t)c->p.width * c->p.height * T;
   bt->npairs = (int64_t)(c->p.width + 1) * c->p.height * T;
+  bt->max_rows = (int64_t)c->p.height * T;
   return VECKM_OK;
 }
 

@@ -46,9 +46,8 @@ struct EncArgs {
   int D;
   const int32_t* count;
   const int32_t* ulist;
-  const int32_t* brick_nq;
-  const int32_t* brick_off;
-  const int32_t* order;
+  const int4* order;  // work list: {brick, rows, first row, slice}
+  int lds_slices;     // slices whose descriptors are copied to LDS (0: read them from global)
   const uint4* frag;
   const int32_t* runs;
   const uint16_t* wts;
@@ -105,6 +104,9 @@ constexpr int kEncWaves = 16;
 constexpr int kEncMaxNtw = 4;
 // With four slab buffers, take the k-steps in pairs: one barrier per pair.
 constexpr bool kEncPairSteps = true;
+
+// LDS byte offset of the slice descriptors (after `bytes` of everything else).
+__host__ __device__ constexpr size_t slice_table_offset(size_t bytes) { return (bytes + 15) & ~size_t(15); }
 
 template <int NA, int NT>
 struct EncShape {
@@ -347,6 +349,9 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
   // is two aligned dword reads.  Box rows are kRunPad voxels wider than the
   // halo on each side, so runs (padding slots included) stay inside a row.
   uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4);
+  // the slice descriptors of a batch, when they fit
+  SliceDesc* stab = reinterpret_cast<SliceDesc*>(
+      smem + slice_table_offset(NBUF * SLAB_U4 * 16 + a.nsteps * 32 * 3 + CH * 4 + 16 + a.vol * 4));
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -356,23 +361,33 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
   const int D = a.D;
   for (int k = tid; k < KP / 4; k += NW * 64) runs_l[k] = a.runs[k];
   for (int k = tid; k < KP; k += NW * 64) wts_l[k] = a.wts[k];
+  for (int k = tid; k < a.lds_slices * (int)(sizeof(SliceDesc) / 4); k += NW * 64)
+    reinterpret_cast<int32_t*>(stab)[k] = reinterpret_cast<const int32_t*>(a.bt.table)[k];
 
+  // Work items come from a shared counter, in longest-first order, one
+  // brick at a time (taking the next brick ahead of time upsets the balance
+  // of long jobs and measured slower on sparse batches too).  An item's
+  // record holds all the brick needs; the slice descriptors are in LDS.
+  int4* item4 = reinterpret_cast<int4*>(item);
+  const int total = a.plan[2];
   for (;;) {
     if (tid == 0) {
       const int it = atomicAdd(&a.plan[1], 1);
-      item[0] = it < a.plan[2] ? a.order[it] : -1;
+      item4[0] = it < total ? a.order[it] : make_int4(-1, 0, 0, 0);
     }
     lds_barrier();
-    const int bid = item[0];
+    const int4 cur = item4[0];
+    const int bid = __builtin_amdgcn_readfirstlane(cur.x);
     if (bid < 0) break;
-    const int nq = a.brick_nq[bid];
-    const int row0 = a.brick_off[bid];
+    const int nq = __builtin_amdgcn_readfirstlane(cur.y);
+    const int row0 = __builtin_amdgcn_readfirstlane(cur.z);
+    const int si = __builtin_amdgcn_readfirstlane(cur.w);
 
     // ---- the brick's count box: one global->LDS copy per box row from the
     //      pair grid (lanes outside the slice read zeros); it has landed once
     //      the first chunk's prologue wait returns
     {
-      const SliceDesc sl = slice_by_brick(a.bt, bid);
+      const SliceDesc sl = a.bt.nslices == 1 ? a.bt.s0 : a.lds_slices ? stab[si] : a.bt.table[si];
       const int lb = bid - sl.brick_off;
       const int bxi = lb % sl.nbx, byi = (lb / sl.nbx) % sl.nby, bti = lb / (sl.nbx * sl.nby);
       const int x = bxi * a.b.bx - a.rx - kRunPad + lane;
@@ -544,8 +559,16 @@ size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol) {
 template <int NA, int NT, int NBUF>
 static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                     hipStream_t s) {
-  const size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
+  size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
+  // a batch's slice descriptors go to LDS when they fit beside the rest
+  EncArgs b = a;
+  b.lds_slices = 0;
+  const size_t with_tab = slice_table_offset(lds) + (size_t)a.bt.nslices * sizeof(SliceDesc);
+  if (a.bt.nslices > 1 && with_tab <= 160 * 1024) {
+    b.lds_slices = a.bt.nslices;
+    lds = with_tab;
+  }
   if (rows == kRowsHiLo16 && NA != 4) return VECKM_E_INVAL;  // hi/lo rows: the FP32 form only
   constexpr int HL = NA == 4 ? kRowsHiLo16 : kRowsF32;
   const void* fn =
@@ -556,14 +579,14 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_
     return VECKM_E_HIP;
   const int per_cu = (int)((160 * 1024) / lds);
   int grid = num_cus * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
-  if (grid > a.bt.nbricks) grid = a.bt.nbricks;
+  if (grid > b.bt.nbricks) grid = a.bt.nbricks;
   constexpr int threads = EncShape<NA, NT>::NW * 64;
   if (rows == kRowsBF16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, b);
   else if (rows == kRowsHiLo16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, HL>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, HL>), dim3(grid), dim3(threads), lds, s, b);
   else
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, b);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
@@ -611,9 +634,8 @@ int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, i
   a.D = et.d;
   a.count = w.count;
   a.ulist = w.ulist;
-  a.brick_nq = w.brick_nq;
-  a.brick_off = w.brick_off;
-  a.order = w.order;
+  a.order = reinterpret_cast<const int4*>(w.order);
+  a.lds_slices = 0;
   a.frag = reinterpret_cast<const uint4*>(et.frag);
   a.runs = et.runs;
   a.wts = et.wts;

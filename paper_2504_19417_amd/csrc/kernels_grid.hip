@@ -33,6 +33,34 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 
+// The slice of event i, for blocks whose threads take consecutive events
+// i = blockIdx.x * blockDim.x + threadIdx.x: two threads find the slices of
+// the block's first and last event, and the rest search only between them
+// (almost always one slice).  Every thread of the block must call it.
+__device__ inline SliceDesc slice_by_event_block(const Batch& bt, int i) {
+  if (bt.nslices == 1) return bt.s0;
+  __shared__ int ends[2];
+  const int first = blockIdx.x * blockDim.x;
+  const int last = min(first + (int)blockDim.x, bt.n) - 1;
+  if (threadIdx.x < 2) {
+    const int e = threadIdx.x ? last : first;
+    int lo = 0, hi = bt.nslices - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bt.table[mid].ev_off <= e) lo = mid; else hi = mid - 1;
+    }
+    ends[threadIdx.x] = lo;
+  }
+  __syncthreads();
+  int lo = ends[0], hi = ends[1];
+  const int e = min(i, bt.n - 1);
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bt.table[mid].ev_off <= e) lo = mid; else hi = mid - 1;
+  }
+  return bt.table[lo];
+}
+
 // One thread per event: validate against its slice, histogram (ADD), remember
 // the slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught by
 // k_pairs, which reads every count once.
@@ -40,8 +68,9 @@ template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= bt.n) return;  // (whole block; launches never do this)
+  const SliceDesc s = slice_by_event_block(bt, i);
   if (i >= bt.n) return;
-  const SliceDesc s = slice_by_event(bt, i);
   const int4 e = ev[i];
   const int64_t dt = (int64_t)e.z - (int64_t)s.t0;
   const bool ok = e.x >= 0 && e.x < s.W && e.y >= 0 && e.y < s.H && dt >= 0 && dt < s.T &&
@@ -79,32 +108,46 @@ __global__ void k_push(const int4* __restrict__ ev, int n, int W, int H, int T, 
 // (0 outside [0, W)), for x in [-1, W).  Any 4 consecutive voxels of a row
 // then sit in two aligned dwords, including a run that starts at x = -1.
 // Exact: counts are at most VECKM_MAX_VOXEL_EVENTS.
-__global__ void k_pairs(Batch bt, const int32_t* __restrict__ count, uint32_t* __restrict__ pairs,
-                        int32_t* __restrict__ err) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < bt.npairs; g += stride) {
-    int64_t poff = 0, voff = 0;
-    int W = bt.s0.W;
-    if (bt.nslices > 1) {
-      int lo = 0, hi = bt.nslices - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bt.table[mid].pair_off <= g) lo = mid; else hi = mid - 1;
+// One wavefront per x row; blockIdx.y picks the slice, the blocks of a
+// slice stride over its H T rows.
+__global__ __launch_bounds__(256) void k_pairs(Batch bt, const int32_t* __restrict__ count,
+                                               uint32_t* __restrict__ pairs,
+                                               int32_t* __restrict__ err) {
+  const SliceDesc s = bt.nslices > 1 ? bt.table[blockIdx.y] : bt.s0;
+  const int lane = threadIdx.x & 63;
+  const int W = s.W, nrows = s.H * s.T;
+  bool bad = false;
+  for (int row = blockIdx.x * 4 + (threadIdx.x >> 6); row < nrows; row += gridDim.x * 4) {
+    const int32_t* c = count + s.grid_off + (int64_t)row * W;
+    uint32_t* p = pairs + s.pair_off + (int64_t)row * (W + 1);
+    for (int e0 = 0; e0 <= W; e0 += 256) {
+      // entries e0 + 64 u + lane (entry e: voxels e - 1 and e).  The loads
+      // are unconditional (addresses clamped into the row, values masked
+      // afterwards), so all eight are in flight before the first wait.
+      int lo[4], hi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 64 * u + lane;
+        lo[u] = c[min(max(e - 1, 0), W - 1)];
+        hi[u] = c[min(e, W - 1)];
       }
-      poff = bt.table[lo].pair_off;
-      voff = bt.table[lo].grid_off;
-      W = bt.table[lo].W;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 64 * u + lane;
+        lo[u] = e >= 1 && e <= W ? lo[u] : 0;
+        hi[u] = e < W ? hi[u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 64 * u + lane;
+        bad |= hi[u] > VECKM_MAX_VOXEL_EVENTS;
+        if (e <= W)
+          p[e] = (uint32_t)__half_as_ushort(__float2half((float)lo[u])) |
+                 ((uint32_t)__half_as_ushort(__float2half((float)hi[u])) << 16);
+      }
     }
-    const int64_t p = g - poff;
-    const int64_t row = p / (W + 1);
-    const int x = (int)(p - row * (W + 1)) - 1;
-    const int32_t* c = count + voff + row * W;
-    const int cx = x >= 0 ? c[x] : 0;
-    if (cx > VECKM_MAX_VOXEL_EVENTS) atomicOr(err, kErrOverflow);
-    const uint32_t lo16 = __half_as_ushort(__float2half((float)cx));
-    const uint32_t hi16 = x + 1 < W ? __half_as_ushort(__float2half((float)c[x + 1])) : 0u;
-    pairs[g] = lo16 | (hi16 << 16);
   }
+  if (bad) atomicOr(err, kErrOverflow);
 }
 
 // Query subsets (one slice): mark the voxels that carry at least one query.
@@ -124,102 +167,285 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
 
 // One block per brick: number the brick's query voxels in (t, y, x) order.
 // rank[v] gets the brick-local number, ulist[brick][number] the brick-local
-// voxel index, brick_nq[brick] the total.
+// voxel index, brick_nq[brick] the total.  Wave w of the 4 takes the w-th
+// quarter of the brick in voxel order: a first pass keeps its ballots, one
+// barrier gives every wave its offset, a second pass writes the numbers.
+// Brick sides are powers of two and a brick holds at most kMaxBrickVoxels.
+constexpr int kMaxBrickVoxels = 4096;
+
 template <bool ALL>
 __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
                                               const uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
                                               int32_t* __restrict__ brick_nq) {
+  constexpr int kIt = kMaxBrickVoxels / 256;  // most iterations per wave
   __shared__ int wave_tot[4];
   const int gb = blockIdx.x;
   const SliceDesc s = slice_by_brick(bt, gb);
   const int lb = gb - s.brick_off;
   const int bxi = lb % s.nbx, byi = (lb / s.nbx) % s.nby, bti = lb / (s.nbx * s.nby);
   const int BV = b.bx * b.by * b.bt;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int base = 0;
-  for (int it = 0; it < BV; it += 256) {
-    const int li = it + threadIdx.x;
-    bool flag = false;
-    int64_t v = 0;
-    if (li < BV) {
-      const int lx = li % b.bx, ly = (li / b.bx) % b.by, lt = li / (b.bx * b.by);
-      const int x = bxi * b.bx + lx, y = byi * b.by + ly, t = bti * b.bt + lt;
-      if (x < s.W && y < s.H && t < s.T) {
-        v = s.grid_off + (t * s.H + y) * s.W + x;
-        flag = ALL ? (count[v] > 0) : (qmark[v] != 0);
-      }
-    }
-    const unsigned long long bal = __ballot(flag);
-    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wave_tot[wid] = __popcll(bal);
-    __syncthreads();
-    int woff = 0;
-    for (int w = 0; w < wid; ++w) woff += wave_tot[w];
-    const int tot = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
-    if (flag) {
-      const int r = base + woff + pre;
-      rank[v] = r;
-      ulist[(int64_t)gb * BV + r] = li;
-    }
-    base += tot;
-    __syncthreads();
+  const int sx = __builtin_ctz(b.bx), sy = __builtin_ctz(b.by);
+  const int per = (BV + 255) >> 8;  // iterations per wave
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x0 = bxi * b.bx, y0 = byi * b.by, t0 = bti * b.bt;
+  // voxel (grid index) of brick-local li, or -1 outside the slice (no
+  // branches, so that the loads below are not serialised)
+  auto voxel = [&](int li) -> int64_t {
+    const int x = x0 + (li & (b.bx - 1)), y = y0 + ((li >> sx) & (b.by - 1)),
+              t = t0 + (li >> (sx + sy));
+    const bool in = li < BV && x < s.W && y < s.H && t < s.T;
+    return in ? s.grid_off + ((int64_t)t * s.H + y) * s.W + x : (int64_t)-1;
+  };
+  // all loads first (unconditional: a voxel outside the slice reads the
+  // slice's first voxel and is masked), then the ballots
+  bool flag[kIt];
+#pragma unroll
+  for (int k = 0; k < kIt; ++k) {
+    const int64_t v = k < per ? voxel((wid * per + k) * 64 + lane) : (int64_t)-1;
+    const int64_t a = v >= 0 ? v : s.grid_off;
+    const bool f = ALL ? (count[a] > 0) : (qmark[a] != 0);
+    flag[k] = v >= 0 && f;
   }
-  if (threadIdx.x == 0) brick_nq[gb] = base;
+  unsigned long long bal[kIt];
+  int tot = 0;
+#pragma unroll
+  for (int k = 0; k < kIt; ++k) {
+    bal[k] = k < per ? __ballot(flag[k]) : 0ull;
+    tot += __popcll(bal[k]);
+  }
+  if (lane == 0) wave_tot[wid] = tot;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wid; ++w) base += wave_tot[w];
+  if (threadIdx.x == 0) brick_nq[gb] = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+  const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int k = 0; k < kIt; ++k) {
+    if (k < per) {
+      if ((bal[k] >> lane) & 1ull) {
+        const int li = (wid * per + k) * 64 + lane;
+        const int r = base + __popcll(bal[k] & below);
+        rank[voxel(li)] = r;
+        ulist[(int64_t)gb * BV + r] = li;
+      }
+      base += __popcll(bal[k]);
+    }
+  }
 }
 
-// One block: exclusive scan of the per-brick row counts; plan[0] = total
-// rows U, plan[1] = 0 (the encoder's work counter), plan[2] = number of
-// non-empty bricks, listed in order[] with the most encoder chunks first
-// (longest job first keeps the persistent encoder's tail short).
-constexpr int kMaxChunkBins = 64;
+// Exclusive scan of the per-brick row counts into off[] (off[nb] = total
+// rows U) and the list of non-empty bricks in order[] (one record per brick:
+// brick, rows, first row, slice), by size class (most encoder chunks
+// first: 64 or more, 32-63, 16-31, 12-15, 8-11, then 7, 6, ..., 1 exactly;
+// longest job first keeps the persistent encoder's tail short) and by brick
+// number within a class.  plan[0] = U, plan[1] = 0 (the encoder's work counter),
+// plan[2] = number of non-empty bricks.  Three launches: per-tile totals,
+// a scan of the tile totals, then each tile places its bricks.  Within a
+// tile thread t owns bricks [t kScanPer, (t + 1) kScanPer); nothing is
+// counted with atomics, so order[] is the same on every call.
+constexpr int kScanClasses = 12;  // kScanNV = class counts, then rows
+constexpr int kScanThreads = 1024, kScanPer = kScanTile / kScanThreads;
+static_assert(kScanNV == kScanClasses + 1 && kScanTile % kScanThreads == 0, "scan tiles");
 
-__global__ __launch_bounds__(1024) void k_brick_scan(const int32_t* __restrict__ nq, int nb,
-                                                     int ch, int32_t* __restrict__ off,
-                                                     int32_t* __restrict__ order,
-                                                     int32_t* __restrict__ plan) {
-  __shared__ int sums[1024];
-  __shared__ int hist[kMaxChunkBins + 1];
+__device__ inline int chunk_class(int nq, int ch) {
+  const int c = (nq + ch - 1) / ch;
+  return c >= 64 ? 0 : c >= 32 ? 1 : c >= 16 ? 2 : c >= 12 ? 3 : c >= 8 ? 4 : 12 - c;
+}
+
+// The tile's counts (coalesced through LDS), this thread's class counts and
+// rows in v[], their exclusive scan over the tile's threads in ex[], the
+// tile totals in tot[].
+__device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch, int tile,
+                                 int (&q)[kScanPer], int (&v)[kScanNV], int (&ex)[kScanNV],
+                                 int (&tot)[kScanNV]) {
+  __shared__ int tq[kScanTile];
+  __shared__ int sums[kScanNV][kScanThreads];
+  const int tid = threadIdx.x, base = tile * kScanTile;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int i = base + u * kScanThreads + tid;
+    tq[u * kScanThreads + tid] = i < nb ? nq[i] : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanNV; ++k) v[k] = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    q[u] = tq[tid * kScanPer + u];
+    v[kScanClasses] += q[u];
+    const int c = q[u] > 0 ? chunk_class(q[u], ch) : -1;
+#pragma unroll
+    for (int k = 0; k < kScanClasses; ++k) v[k] += c == k;
+  }
+#pragma unroll
+  for (int k = 0; k < kScanNV; ++k) sums[k][tid] = v[k];
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive scans, all at once
+    int add[kScanNV];
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) add[k] = tid >= d ? sums[k][tid - d] : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) sums[k][tid] += add[k];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kScanNV; ++k) {
+    ex[k] = sums[k][tid] - v[k];
+    tot[k] = sums[k][kScanThreads - 1];
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(const int32_t* __restrict__ nq,
+                                                              int nb, int ch,
+                                                              int32_t* __restrict__ part) {
+  int q[kScanPer], v[kScanNV], ex[kScanNV], tot[kScanNV];
+  scan_tile(nq, nb, ch, blockIdx.x, q, v, ex, tot);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) part[blockIdx.x * kScanNV + k] = tot[k];
+}
+
+// One block: turns the tile totals into each tile's starting positions
+// (class k of tile b starts at the class's start plus the class counts of
+// tiles before b; rows likewise).
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb,
+                                                             int32_t* __restrict__ part,
+                                                             int32_t* __restrict__ off,
+                                                             int32_t* __restrict__ plan) {
+  __shared__ int sums[kScanNV][kScanThreads];
   const int tid = threadIdx.x;
-  if (tid <= kMaxChunkBins) hist[tid] = 0;
-  const int per = (nb + 1023) / 1024;
-  const int s0 = min(tid * per, nb), s1 = min(s0 + per, nb);
-  int local = 0;
-  for (int i = s0; i < s1; ++i) local += nq[i];
-  sums[tid] = local;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int v = tid >= d ? sums[tid - d] : 0;
-    __syncthreads();
-    sums[tid] += v;
-    __syncthreads();
-  }
-  int run = tid ? sums[tid - 1] : 0;
-  for (int i = s0; i < s1; ++i) {
-    off[i] = run;
-    run += nq[i];
-    const int c = min((nq[i] + ch - 1) / ch, kMaxChunkBins);
-    if (c > 0) atomicAdd(&hist[kMaxChunkBins - c], 1);
+  const int per = (ntiles + kScanThreads - 1) / kScanThreads;
+  const int s0 = min(tid * per, ntiles), s1 = min(s0 + per, ntiles);
+  int v[kScanNV];
+#pragma unroll
+  for (int k = 0; k < kScanNV; ++k) {
+    v[k] = 0;
+    for (int i = s0; i < s1; ++i) v[k] += part[i * kScanNV + k];
+    sums[k][tid] = v[k];
   }
   __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int b = 0; b <= kMaxChunkBins; ++b) {
-      const int h = hist[b];
-      hist[b] = acc;
-      acc += h;
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    int add[kScanNV];
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) add[k] = tid >= d ? sums[k][tid - d] : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) sums[k][tid] += add[k];
+    __syncthreads();
+  }
+  int start[kScanNV];
+  int acc = 0;
+#pragma unroll
+  for (int k = 0; k < kScanClasses; ++k) {
+    start[k] = acc;
+    acc += sums[k][kScanThreads - 1];
+  }
+  start[kScanClasses] = 0;
+  int run[kScanNV];
+#pragma unroll
+  for (int k = 0; k < kScanNV; ++k) run[k] = start[k] + sums[k][tid] - v[k];
+  for (int i = s0; i < s1; ++i)
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) {
+      const int t = part[i * kScanNV + k];
+      part[i * kScanNV + k] = run[k];
+      run[k] += t;
     }
-    off[nb] = sums[1023];
-    plan[0] = sums[1023];
+  if (tid == 0) {
+    const int rows = sums[kScanClasses][kScanThreads - 1];
+    off[nb] = rows;
+    plan[0] = rows;
     plan[1] = 0;
     plan[2] = acc;
   }
-  __syncthreads();
-  for (int i = s0; i < s1; ++i) {
-    const int c = min((nq[i] + ch - 1) / ch, kMaxChunkBins);
-    if (c > 0) order[atomicAdd(&hist[kMaxChunkBins - c], 1)] = i;
+}
+
+// ONE = true: the bricks fit in one tile, and this single block does the
+// whole scan (part is not used; plan and off[nb] are written here).
+template <bool ONE>
+__global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
+                                                             const int32_t* __restrict__ nq,
+                                                             int nb, int ch,
+                                                             const int32_t* __restrict__ part,
+                                                             int32_t* __restrict__ off,
+                                                             int4* __restrict__ order,
+                                                             int32_t* __restrict__ plan) {
+  int q[kScanPer], v[kScanNV], ex[kScanNV], tot[kScanNV];
+  scan_tile(nq, nb, ch, blockIdx.x, q, v, ex, tot);
+  int pos[kScanNV];
+  if constexpr (ONE) {
+    int start = 0;
+#pragma unroll
+    for (int k = 0; k < kScanClasses; ++k) {
+      pos[k] = start + ex[k];
+      start += tot[k];
+    }
+    pos[kScanClasses] = ex[kScanClasses];
+    if (threadIdx.x == 0) {
+      off[nb] = tot[kScanClasses];
+      plan[0] = tot[kScanClasses];
+      plan[1] = 0;
+      plan[2] = start;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) pos[k] = part[blockIdx.x * kScanNV + k] + ex[k];
   }
+  const int i0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int i = i0 + u;
+    if (i >= nb) break;
+    off[i] = pos[kScanClasses];
+    pos[kScanClasses] += q[u];
+    if (q[u] > 0) {
+      const int c = chunk_class(q[u], ch);
+      int p = 0;
+#pragma unroll
+      for (int k = 0; k < kScanClasses; ++k)
+        if (c == k) p = pos[k]++;
+      int sl = 0;  // the brick's slice
+      if (bt.nslices > 1) {
+        int hi = bt.nslices - 1;
+        while (sl < hi) {
+          const int mid = (sl + hi + 1) >> 1;
+          if (bt.table[mid].brick_off <= i) sl = mid; else hi = mid - 1;
+        }
+      }
+      order[p] = make_int4(i, q[u], pos[kScanClasses] - q[u], sl);
+    }
+  }
+}
+
+// The three launches of the brick scan (part: kScanNV ints per tile).
+static void launch_brick_scan(const Batch& bt, const Workspace& w, int nb, int ch,
+                              hipStream_t s) {
+  const int ntiles = nb > 0 ? (int)scan_tiles(nb) : 1;
+  int4* order = reinterpret_cast<int4*>(w.order);
+  if (ntiles == 1) {
+    hipLaunchKernelGGL(k_scan_place<true>, dim3(1), dim3(kScanThreads), 0, s, bt, w.brick_nq, nb,
+                       ch, w.scan_part, w.brick_off, order, w.plan);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_totals, dim3(ntiles), dim3(kScanThreads), 0, s, w.brick_nq, nb, ch,
+                     w.scan_part);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, ntiles, nb, w.scan_part,
+                     w.brick_off, w.plan);
+  hipLaunchKernelGGL(k_scan_place<false>, dim3(ntiles), dim3(kScanThreads), 0, s, bt, w.brick_nq,
+                     nb, ch, w.scan_part, w.brick_off, order, w.plan);
+}
+
+// The row of slice-local voxel v (a query voxel of slice s).
+__device__ inline int qmap_row(const SliceDesc& s, const Brick& b, int v,
+                               const int32_t* __restrict__ rank,
+                               const int32_t* __restrict__ brick_off) {
+  const int x = v % s.W, y = (v / s.W) % s.H, t = v / (s.W * s.H);
+  const int lb = ((t / b.bt) * s.nby + y / b.by) * s.nbx + x / b.bx;
+  return brick_off[s.brick_off + lb] + rank[s.grid_off + v];
 }
 
 // One thread per query: the row of its voxel (or -1 for an invalid event).
@@ -228,8 +454,18 @@ __global__ void k_qmap(const int32_t* __restrict__ queries, Batch bt, Brick b,
                        const int32_t* __restrict__ brick_off, int32_t* __restrict__ qmap,
                        int32_t* __restrict__ rowvox) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!queries) {  // query i is event i: consecutive per block
+    if (blockIdx.x * blockDim.x >= bt.m) return;  // (whole block; launches never do this)
+    const SliceDesc s = slice_by_event_block(bt, i);
+    if (i >= bt.m) return;
+    const int v = vox[i];
+    const int r = v < 0 ? -1 : qmap_row(s, b, v, rank, brick_off);
+    qmap[i] = r;
+    if (rowvox && r >= 0) rowvox[r] = v;
+    return;
+  }
   if (i >= bt.m) return;
-  const int e = queries ? queries[i] : i;
+  const int e = queries[i];
   if (e < 0 || e >= bt.n) {
     qmap[i] = -1;
     return;
@@ -239,10 +475,7 @@ __global__ void k_qmap(const int32_t* __restrict__ queries, Batch bt, Brick b,
     qmap[i] = -1;
     return;
   }
-  const SliceDesc s = slice_by_event(bt, e);
-  const int x = v % s.W, y = (v / s.W) % s.H, t = v / (s.W * s.H);
-  const int lb = ((t / b.bt) * s.nby + y / b.by) * s.nbx + x / b.bx;
-  const int r = brick_off[s.brick_off + lb] + rank[s.grid_off + v];
+  const int r = qmap_row(slice_by_event(bt, e), b, v, rank, brick_off);
   qmap[i] = r;
   if (rowvox) rowvox[r] = v;  // every query of the voxel writes the same value
 }
@@ -276,6 +509,15 @@ static int fill_grid(int64_t n) {
   return (int)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
+// k_pairs over nslices slices of at most max_rows x rows each: about 4096
+// blocks in all (4 rows at a time per block).
+static dim3 pairs_grid(int nslices, int64_t max_rows) {
+  int64_t x = (4096 + nslices - 1) / nslices;
+  const int64_t need = (max_rows + 3) / 4;
+  x = x < need ? x : need;
+  return dim3((unsigned)(x < 1 ? 1 : x), (unsigned)nslices);
+}
+
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
@@ -286,8 +528,8 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
     hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
   if (pairs)
-    hipLaunchKernelGGL(k_pairs, dim3(fill_grid(bt.npairs)), dim3(256), 0, s, bt, w.count, w.pairs,
-                       w.err);
+    hipLaunchKernelGGL(k_pairs, pairs_grid(bt.nslices, bt.max_rows), dim3(256), 0, s, bt, w.count,
+                       w.pairs, w.err);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
@@ -297,8 +539,7 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   else
     hipLaunchKernelGGL(k_rank<true>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
                        w.qmark, w.rank, w.ulist, w.brick_nq);
-  hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, bt.nbricks,
-                     encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
                        et.brick, w.vox, w.rank, w.brick_off, w.qmap,
@@ -327,9 +568,11 @@ int launch_window_push(const Workspace& w, const veckm_event* ev, int64_t n, int
     if (sp[1] > 0) {
       Batch pb{};
       pb.s0.W = W;
+      pb.s0.H = H;
+      pb.s0.T = sp[1];
       pb.nslices = 1;
       pb.npairs = sp[1] * pplane;
-      hipLaunchKernelGGL(k_pairs, dim3(fill_grid(pb.npairs)), dim3(256), 0, s, pb,
+      hipLaunchKernelGGL(k_pairs, pairs_grid(1, (int64_t)H * sp[1]), dim3(256), 0, s, pb,
                          w.count + sp[0] * plane, w.pairs + sp[0] * pplane, w.err);
     }
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
@@ -347,8 +590,7 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
   }
   hipLaunchKernelGGL(k_rank<false>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
                      w.qmark, w.rank, w.ulist, w.brick_nq);
-  hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, s, w.brick_nq, bt.nbricks,
-                     encode_rows_per_chunk(et.d), w.brick_off, w.order, w.plan);
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt,
                        et.brick, w.vox, w.rank, w.brick_off, w.qmap, nullptr);

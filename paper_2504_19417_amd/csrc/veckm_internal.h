@@ -99,7 +99,14 @@ struct Batch {
   int m;                     // total queries
   int64_t nvox;              // total voxels
   int64_t npairs;            // total pair-grid entries (sum of (W + 1) H T)
+  int64_t max_rows;          // most x rows (H T) in one slice
 };
+
+// The brick scan works on tiles of kScanTile bricks and keeps kScanNV
+// partial sums per tile.
+constexpr int kScanTile = 8192;
+constexpr int kScanNV = 13;
+inline int64_t scan_tiles(int64_t nb) { return (nb + kScanTile - 1) / kScanTile; }
 
 struct Workspace {
   int32_t* count = nullptr;     // voxels: int32 event counts, slices back to back
@@ -111,7 +118,9 @@ struct Workspace {
   int32_t* ulist = nullptr;     // bricks * brick volume: brick-local voxel of each rank
   int32_t* brick_nq = nullptr;  // bricks
   int32_t* brick_off = nullptr; // bricks + 1 (exclusive scan)
-  int32_t* order = nullptr;     // bricks: non-empty bricks, most encoder chunks first
+  int32_t* order = nullptr;     // 4 x bricks: the encoder's work list, most chunks first;
+                                // per brick {brick, rows, first row, slice}
+  int32_t* scan_part = nullptr; // kScanNV ints per kScanTile bricks (brick-scan partials)
   int32_t* vox = nullptr;       // n: slice-local voxel of each event, -1 if invalid
   int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
   int32_t* rowvox = nullptr;    // U: voxel of each row (paper form only)
