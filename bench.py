@@ -554,6 +554,9 @@ def batch_main(args):
     for form in ("fp16", "fp32"):
         c = vk.Context(640, 480, w.rx, w.ry, w.rt, A, 50, n, form, max_slices=64)
         c.set_mlp(*mlp)
+        # the encoder tiling for this batch, picked by the library's tuner
+        # (set-up, outside the timed region)
+        tiling = c.tilings()[c.tune(specs, evt, reps=2)]
         out = torch.empty((n, 2), device="cuda")
         for _ in range(args.warmup):
             c.flow_batch(specs, evt, out=out)
@@ -580,7 +583,7 @@ def batch_main(args):
             got.append(flows[off + q])
             off += len(e)
         got, ref = np.concatenate(got).astype(np.float64), np.concatenate(ref)
-        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st,
+        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st, tiling=list(tiling),
                          err=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
     line = {
         "metric": "normal flows/sec, 64-slice batch in one launch sequence (BF16 perceptron)",
@@ -591,11 +594,12 @@ def batch_main(args):
         "data": "synthetic (seeded moving edges + 10% uniform noise, 64 slices)",
         "config": {"workload": "batch64", "slices": 64, "events": n,
                    "sensors": "346x260 / 640x480", "bins": 50, "d": w.d, "radius_xy": w.rx,
-                   "radius_t": w.rt, "hidden": w.hidden, "queries": "all events"},
+                   "radius_t": w.rt, "hidden": w.hidden, "queries": "all events",
+                   "tiling_brick_slabs": res["fp16"]["tiling"]},
         "stages_ms": res["fp16"]["stages"],
         "err_vs_oracle": {"flow_relL2_sampled": res["fp16"]["err"]},
         "fp32": {"value": res["fp32"]["value"], "ms_per_step": round(res["fp32"]["ms"], 4),
-                 "stages_ms": res["fp32"]["stages"],
+                 "stages_ms": res["fp32"]["stages"], "tiling_brick_slabs": res["fp32"]["tiling"],
                  "err_vs_oracle": {"flow_relL2_sampled": res["fp32"]["err"]}},
         "roofline": None, "cpu_baseline": None,
     }

@@ -186,6 +186,67 @@ int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
 int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                      const veckm_event* events, float* flow, void* stream);
 
+/* ---- launch graphs (batch forms) ---------------------------------------
+   A batch layout that repeats (the same slices, event buffer and output
+   buffer on every call, as in a serving loop) can be captured once as a HIP
+   graph and replayed with one launch, instead of a dozen kernel launches per
+   call (launch overhead dominates small slices).  veckm_graph_create
+   validates like veckm_flow_batch (flow != 0) or veckm_encode_batch
+   (flow == 0), copies the slice table into device memory the graph owns,
+   and captures the launch sequence for exactly these `slices`, `events` and
+   `out`.  veckm_graph_launch replays it on `stream`: it reads what `events`
+   holds at that time (the events may change between launches, the slice
+   layout may not: every event must still satisfy its slice's window and
+   sensor) and writes `out` as the batch call would, bit for bit.
+     ctx      the context whose workspaces the graph uses.  Replays and other
+              calls on the same context must not overlap on the device (issue
+              them on one stream, or synchronise); destroy a context's graphs
+              before the context.
+     out      device, total n x 2 (flow) or total n x 2D (encodings) float32.
+     *graph   receives the graph; release it with veckm_graph_destroy.
+   Returns the batch call's errors (VECKM_E_INVAL, VECKM_E_RANGE,
+   VECKM_E_STATE), VECKM_E_NOMEM, or VECKM_E_HIP if capture fails; no
+   kernel runs at creation.  Device-side input errors of a replay are
+   reported by veckm_status. */
+typedef struct veckm_graph veckm_graph;
+int veckm_graph_create(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                       const veckm_event* events, float* out, int32_t flow,
+                       veckm_graph** graph);
+int veckm_graph_launch(veckm_graph* graph, void* stream);
+void veckm_graph_destroy(veckm_graph* graph);
+
+/* ---- encoder tilings and the tuner --------------------------------------
+   The encoder cuts every slice into bricks of voxels and streams the phase
+   table through LDS a few slabs deep (the count box of a brick and the slabs
+   share the 160 KB of LDS).  A context offers a small set of tilings (brick
+   shape x buffered slabs): index 0 is the default (the largest brick that
+   fits beside two slabs, as many slabs as fit), the others larger bricks
+   with fewer slabs, which pay off where bricks hold few query voxels
+   (sparse slices).  Results do not depend on the tiling (bit-identical);
+   only the time does.
+     veckm_tiling_count     number of tilings (>= 1), or VECKM_E_INVAL
+     veckm_tiling_selected  index in use, or VECKM_E_INVAL
+     veckm_tiling_info      info[0..3] = brick x, y, t sides and slabs of
+                            tiling `index` (host int32[4])
+     veckm_tiling_select    use tiling `index` from the next call on
+     veckm_tune             times every tiling on the given batch (as for
+                            veckm_encode_batch: the front end and the encoder,
+                            one untimed and `reps` timed runs each, 1 <= reps
+                            <= 100, HIP events on `stream`), selects the
+                            fastest for the calls that follow and writes its
+                            index to *chosen (may be NULL).  Synchronises
+                            `stream`; writes no caller memory besides
+                            *chosen.  Errors as veckm_encode_batch; VECKM_E_INVAL
+                            for rt = -1 or sliding-window contexts (one
+                            tiling).  Must not overlap other calls on the
+                            context. */
+int veckm_tiling_count(const veckm_ctx* ctx);
+int veckm_tiling_selected(const veckm_ctx* ctx);
+int veckm_tiling_info(const veckm_ctx* ctx, int32_t index, int32_t* info);
+int veckm_tiling_select(veckm_ctx* ctx, int32_t index);
+int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+               const veckm_event* events, int32_t reps, void* stream, int32_t* chosen);
+
 /* Waits for `stream`, then reports (and clears) the device-side input error
    of the calls enqueued so far: VECKM_OK, VECKM_E_RANGE or
    VECKM_E_OVERFLOW. */

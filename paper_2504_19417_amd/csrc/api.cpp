@@ -26,7 +26,9 @@ struct veckm_ctx {
   std::vector<double> A;
   int device = 0;
   int num_cus = 0;
-  EncodeTables et;
+  EncodeTables et;                    // the tiling in use (one of `tilings`)
+  std::vector<EncodeTables> tilings;  // candidate encoder tilings (same tables, other bricks)
+  int tiling = 0;
   Workspace w;
   MlpWeights mw;
   bool paper = false;  // no temporal bound: the staged 2-D pooling encoder
@@ -103,22 +105,36 @@ int64_t pair_entries_of(const veckm_params* p) {
 }
 
 struct Sizes {
-  int64_t V, P, nb, bv, U, n;
+  int64_t V, P, nb, ulist, U, n;
 };
 
-Sizes sizes_for(const veckm_params* p, const Brick& b) {
+// Workspace sizes for every tiling a context may use: the most bricks and
+// the largest row list over the bricks.
+Sizes sizes_for(const veckm_params* p, const std::vector<Tiling>& tl) {
   Sizes s;
   s.V = voxels_of(p);
   s.P = pair_entries_of(p);
-  s.nb = slices_of(p) * bricks_of(p->width, p->height, p->max_bins, b);
-  s.bv = b.volume();
+  s.nb = 0;
+  s.ulist = 0;
+  for (const Tiling& t : tl) {
+    const int64_t nb = slices_of(p) * bricks_of(p->width, p->height, p->max_bins, t.brick);
+    s.nb = std::max(s.nb, nb);
+    s.ulist = std::max(s.ulist, nb * t.brick.volume());
+  }
   s.n = p->max_events;
   s.U = s.n < s.V ? s.n : s.V;
   return s;
 }
 
-int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
-  const Sizes s = sizes_for(p, b);
+// The tilings of a context made from p (the paper form numbers voxels with
+// one fixed brick and has no encoder tiling to choose).
+std::vector<Tiling> tilings_for(const veckm_params* p, int kp) {
+  if (p->rt < 0) return {Tiling{Brick{32, 16, 8}, 2}};
+  return tiling_candidates(p->rx, p->ry, p->rt, p->d, p->precision, kp);
+}
+
+int64_t bytes_for(const veckm_params* p, const std::vector<Tiling>& tl, int kp, int hidden) {
+  const Sizes s = sizes_for(p, tl);
   const int na = p->precision == VECKM_FP32 ? 4 : 2;
   int64_t bytes = 0;
   if (p->rt < 0) {  // paper form: G, S grids, pixel counts, phase tables
@@ -128,12 +144,13 @@ int64_t bytes_for(const veckm_params* p, const Brick& b, int kp, int hidden) {
   }
   bytes += s.V * (4 + 4 + 1);                     // count, rank, qmark
   if (p->rt >= 0) bytes += s.P * 4;               // pair grid
-  bytes += s.nb * s.bv * 4;                       // ulist
+  bytes += s.ulist * 4;                           // ulist
   bytes += (6 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
   bytes += (scan_tiles(s.nb) + 1) * kScanNV * 4;  // brick-scan partials
   bytes += s.n * (4 + 4);                         // vox, qmap
   bytes += s.U * 2 * p->d * 4 + s.U * 8;          // rows (fp32 size), rowflow
-  bytes += (int64_t)kp * p->d * na * 2 + kp * 3;  // phase table, run offsets, weights
+  bytes += (int64_t)kp * p->d * na * 2 + kp * 2;  // phase table, weights
+  bytes += (int64_t)tl.size() * kp;               // run offsets (one table per tiling)
   bytes += 64 * 4 + 4 + 64 * 4;                   // plan, err, zero page
   bytes += (int64_t)kRing * slices_of(p) * (int64_t)sizeof(SliceDesc);  // slice tables
   bytes += (int64_t)hidden * (2 * p->d) * 10 + hidden * 12 + 8;  // perceptron (fp32, bf16, fp16 hi/lo W1)
@@ -183,13 +200,11 @@ int single_batch(const veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t
   return VECKM_OK;
 }
 
-// A batch of slices: validate, describe, and upload the slice table through
-// the next ring slot (*slot, released by release_slot after the launches).
-int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
-                const void* out, void* stream, Batch* bt, int* slot) {
-  *slot = -1;
+// A batch of slices: validate and describe them (bt->table is left unset).
+int plan_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
+               const void* out, std::vector<SliceDesc>& tab, Batch* bt) {
   if (!sl || count < 1 || count > c->max_slices) return VECKM_E_INVAL;
-  std::vector<SliceDesc> tab((size_t)count);
+  tab.assign((size_t)count, SliceDesc{});
   int64_t evs = 0, vox = 0, prs = 0, bricks = 0, max_rows = 0;
   for (int k = 0; k < count; ++k) {
     const veckm_slice& s = sl[k];
@@ -205,8 +220,30 @@ int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_
     max_rows = std::max(max_rows, (int64_t)s.height * s.nbins);
     bricks += bricks_of(s.width, s.height, s.nbins, c->et.brick);
   }
-  if (vox > c->w.vmax || prs > c->w.pmax || bricks > c->w.bmax) return VECKM_E_RANGE;
+  if (vox > c->w.vmax || prs > c->w.pmax || bricks > c->w.bmax ||
+      bricks * c->et.brick.volume() > c->w.umax)
+    return VECKM_E_RANGE;
   if (evs > 0 && (!ev || !out)) return VECKM_E_INVAL;
+  bt->s0 = tab[0];
+  bt->table = nullptr;
+  bt->nslices = count;
+  bt->nbricks = (int)bricks;
+  bt->n = (int)evs;
+  bt->m = (int)evs;
+  bt->nvox = vox;
+  bt->npairs = prs;
+  bt->max_rows = max_rows;
+  return VECKM_OK;
+}
+
+// A batch of slices: validate, describe, and upload the slice table through
+// the next ring slot (*slot, released by release_slot after the launches).
+int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
+                const void* out, void* stream, Batch* bt, int* slot) {
+  *slot = -1;
+  std::vector<SliceDesc> tab;
+  const int rc = plan_batch(c, sl, count, ev, out, tab, bt);
+  if (rc) return rc;
   const int k = c->ring_next;
   if (c->ring_used[k] && hipEventSynchronize(c->ring_ev[k]) != hipSuccess) return VECKM_E_HIP;
   c->ring_next = (k + 1) % kRing;
@@ -217,15 +254,7 @@ int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_
                      (hipStream_t)stream) != hipSuccess)
     return VECKM_E_HIP;
   *slot = k;
-  bt->s0 = tab[0];
   bt->table = dev;
-  bt->nslices = count;
-  bt->nbricks = (int)bricks;
-  bt->n = (int)evs;
-  bt->m = (int)evs;
-  bt->nvox = vox;
-  bt->npairs = prs;
-  bt->max_rows = max_rows;
   return VECKM_OK;
 }
 
@@ -343,13 +372,9 @@ int64_t veckm_workspace_bytes(const veckm_params* params, int32_t hidden) {
   const int rc = veckm_params_check(params);
   if (rc) return rc;
   if (hidden < 0) return VECKM_E_INVAL;
-  Brick b;
-  int nbuf;
   const int rt_enc = params->rt < 0 ? 0 : params->rt;
   const SlotTable st = make_slots(params->rx, params->ry, rt_enc);
-  choose_layout(params->rx, params->ry, rt_enc, params->d, params->precision, st.KP, &b, &nbuf);
-  if (params->rt < 0) b = Brick{32, 16, 8};
-  return bytes_for(params, b, st.KP, hidden);
+  return bytes_for(params, tilings_for(params, st.KP), st.KP, hidden);
 }
 
 int veckm_offset_table(const veckm_params* params, int32_t* k_count, int32_t* offsets,
@@ -409,29 +434,26 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   et.ry = params->ry;
   et.rt = rt_enc;
   et.d = params->d;
-  choose_layout(params->rx, params->ry, rt_enc, params->d, params->precision, st.KP, &et.brick,
-                &et.nbuf);
-  if (c->paper) et.brick = Brick{32, 16, 8};
+  const std::vector<Tiling> tl = tilings_for(params, st.KP);
   const std::vector<uint16_t> frag = make_slot_fragments(st, c->A.data(), params->d, et.na);
-  const std::vector<int32_t> runs = make_run_offsets(st, et.brick, params->rx, params->ry);
   const std::vector<uint16_t> wts = make_slot_weights(st);
-  const Sizes s = sizes_for(params, et.brick);
+  const Sizes s = sizes_for(params, tl);
   Workspace& w = c->w;
   uint16_t* dfrag = nullptr;
-  int32_t* druns = nullptr;
+  std::vector<int32_t*> druns(tl.size(), nullptr);
   uint16_t* dwts = nullptr;
   uint32_t* dzeros = nullptr;
   float* rows = nullptr;
   rc = VECKM_OK;
   rc = rc ? rc : dalloc(c->allocs, &dfrag, frag.size());
-  rc = rc ? rc : dalloc(c->allocs, &druns, runs.size());
+  for (size_t i = 0; i < tl.size(); ++i) rc = rc ? rc : dalloc(c->allocs, &druns[i], st.KP / 4);
   rc = rc ? rc : dalloc(c->allocs, &dwts, wts.size());
   rc = rc ? rc : dalloc(c->allocs, &dzeros, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
   if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &w.pairs, (size_t)s.P);
   rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
-  rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)(s.nb * s.bv));
+  rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)s.ulist);
   rc = rc ? rc : dalloc(c->allocs, &w.brick_nq, (size_t)s.nb);
   rc = rc ? rc : dalloc(c->allocs, &w.brick_off, (size_t)s.nb + 1);
   rc = rc ? rc : dalloc(c->allocs, &w.order, (size_t)s.nb * 4);
@@ -482,8 +504,11 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     }
   if (!rc && hipMemcpy(dfrag, frag.data(), frag.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
-  if (!rc && hipMemcpy(druns, runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-    rc = VECKM_E_HIP;
+  for (size_t i = 0; !rc && i < tl.size(); ++i) {
+    const std::vector<int32_t> runs = make_run_offsets(st, tl[i].brick, params->rx, params->ry);
+    if (hipMemcpy(druns[i], runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      rc = VECKM_E_HIP;
+  }
   if (!rc && hipMemcpy(dwts, wts.data(), wts.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
   if (!rc && hipMemset(dzeros, 0, 64 * sizeof(uint32_t)) != hipSuccess) rc = VECKM_E_HIP;
@@ -500,9 +525,18 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   w.pmax = s.P;
   w.nmax = s.n;
   w.bmax = s.nb;
+  w.umax = s.ulist;
   et.frag = dfrag;
-  et.runs = druns;
   et.wts = dwts;
+  for (size_t i = 0; i < tl.size(); ++i) {
+    EncodeTables t = et;
+    t.brick = tl[i].brick;
+    t.nbuf = tl[i].nbuf;
+    t.runs = druns[i];
+    c->tilings.push_back(t);
+  }
+  c->et = c->tilings[0];
+  c->tiling = 0;
   *out = c;
   return VECKM_OK;
 }
@@ -700,6 +734,155 @@ int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
   rc = run(ctx, bt, events, nullptr, nullptr, flow, stream);
   const int rc2 = release_slot(ctx, slot, stream);
   return rc ? rc : rc2;
+}
+
+// ---- launch graphs
+
+struct veckm_graph {
+  veckm_ctx* ctx = nullptr;
+  SliceDesc* table = nullptr;  // device copy of the batch's slice table
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void veckm_graph_destroy(veckm_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->table) (void)hipFree(g->table);
+  delete g;
+}
+
+int veckm_graph_create(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+                       const veckm_event* events, float* out, int32_t flow, veckm_graph** g) {
+  if (!g) return VECKM_E_INVAL;
+  *g = nullptr;
+  if (!ctx || ctx->paper || ctx->window) return VECKM_E_INVAL;
+  if (flow && ctx->mw.hidden == 0) return VECKM_E_STATE;
+  std::vector<SliceDesc> tab;
+  Batch bt;
+  int rc = plan_batch(ctx, slices, count, events, out, tab, &bt);
+  if (rc) return rc;
+  veckm_graph* gr = new veckm_graph;
+  gr->ctx = ctx;
+  if (hipMalloc(&gr->table, tab.size() * sizeof(SliceDesc)) != hipSuccess) {
+    (void)hipGetLastError();
+    gr->table = nullptr;
+    veckm_graph_destroy(gr);
+    return VECKM_E_NOMEM;
+  }
+  if (hipMemcpy(gr->table, tab.data(), tab.size() * sizeof(SliceDesc), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    veckm_graph_destroy(gr);
+    return VECKM_E_HIP;
+  }
+  bt.table = gr->table;
+  // capture the launch sequence on a stream of our own (stage timing off:
+  // its events belong to eager calls)
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    veckm_graph_destroy(gr);
+    return VECKM_E_HIP;
+  }
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  rc = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+  if (!rc) {
+    rc = run(ctx, bt, events, nullptr, flow ? nullptr : out, flow ? out : nullptr, s);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(s, &graph) != hipSuccess && !rc) rc = VECKM_E_HIP;
+    gr->graph = graph;
+  }
+  ctx->prof = prof;
+  if (!rc && hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = VECKM_E_HIP;
+  (void)hipStreamDestroy(s);
+  if (rc) {
+    veckm_graph_destroy(gr);
+    return rc;
+  }
+  *g = gr;
+  return VECKM_OK;
+}
+
+int veckm_graph_launch(veckm_graph* g, void* stream) {
+  if (!g || !g->exec) return VECKM_E_INVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+// ---- encoder tilings and the tuner
+
+int veckm_tiling_count(const veckm_ctx* ctx) {
+  return ctx ? (int)ctx->tilings.size() : VECKM_E_INVAL;
+}
+
+int veckm_tiling_selected(const veckm_ctx* ctx) { return ctx ? ctx->tiling : VECKM_E_INVAL; }
+
+int veckm_tiling_info(const veckm_ctx* ctx, int32_t index, int32_t* info) {
+  if (!ctx || !info || index < 0 || index >= (int)ctx->tilings.size()) return VECKM_E_INVAL;
+  const EncodeTables& t = ctx->tilings[(size_t)index];
+  info[0] = t.brick.bx;
+  info[1] = t.brick.by;
+  info[2] = t.brick.bt;
+  info[3] = t.nbuf;
+  return VECKM_OK;
+}
+
+int veckm_tiling_select(veckm_ctx* ctx, int32_t index) {
+  if (!ctx || index < 0 || index >= (int)ctx->tilings.size()) return VECKM_E_INVAL;
+  ctx->et = ctx->tilings[(size_t)index];
+  ctx->tiling = index;
+  return VECKM_OK;
+}
+
+int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
+               const veckm_event* events, int32_t reps, void* stream, int32_t* chosen) {
+  if (!ctx || ctx->paper || ctx->window || reps < 1 || reps > 100) return VECKM_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return VECKM_E_HIP;
+  }
+  // the rows the flow path would write (the epilogue differs, the work not)
+  const int rows = ctx->p.precision == VECKM_FP16 ? kRowsBF16
+                   : ctx->mw.hidden > 0 && mlp_rows_split(ctx->p.d, ctx->mw.hidden)
+                       ? kRowsHiLo16
+                       : kRowsF32;
+  const int prev = ctx->tiling;
+  int best = -1, rc = VECKM_OK;
+  float best_ms = 0.f;
+  for (int i = 0; !rc && i < (int)ctx->tilings.size(); ++i) {
+    ctx->et = ctx->tilings[(size_t)i];
+    for (int r = 0; !rc && r <= reps; ++r) {  // one untimed run, then reps timed
+      if (r == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VECKM_E_HIP;
+      Batch bt;
+      int slot = -1;
+      // (the output argument is only checked for presence; nothing is written)
+      if (!rc) rc = multi_batch(ctx, slices, count, events, events, stream, &bt, &slot);
+      if (!rc && bt.m > 0) {
+        rc = launch_prepare(bt, ctx->w, events, nullptr, ctx->et, true, stream);
+        if (!rc) rc = launch_encode(bt, ctx->w, ctx->et, rows, ctx->num_cus, stream);
+      }
+      const int rc2 = release_slot(ctx, slot, stream);
+      rc = rc ? rc : rc2;
+    }
+    float ms = 0.f;
+    if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = VECKM_E_HIP;
+    if (!rc && (best < 0 || ms < best_ms)) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int pick = rc ? prev : best;
+  ctx->et = ctx->tilings[(size_t)pick];
+  ctx->tiling = pick;
+  if (!rc && chosen) *chosen = best;
+  return rc;
 }
 
 int veckm_profile_enable(veckm_ctx* ctx, int32_t enable) {

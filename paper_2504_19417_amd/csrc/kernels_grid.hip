@@ -170,16 +170,13 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
 // voxel index, brick_nq[brick] the total.  Wave w of the 4 takes the w-th
 // quarter of the brick in voxel order: a first pass keeps its ballots, one
 // barrier gives every wave its offset, a second pass writes the numbers.
-// Brick sides are powers of two and a brick holds at most kMaxBrickVoxels.
-constexpr int kMaxBrickVoxels = 4096;
-
-template <bool ALL>
+// Brick sides are powers of two and a brick holds at most 256 kIt voxels.
+template <bool ALL, int kIt>
 __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
                                               const uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
                                               int32_t* __restrict__ brick_nq) {
-  constexpr int kIt = kMaxBrickVoxels / 256;  // most iterations per wave
   __shared__ int wave_tot[4];
   const int gb = blockIdx.x;
   const SliceDesc s = slice_by_brick(bt, gb);
@@ -518,6 +515,21 @@ static dim3 pairs_grid(int nslices, int64_t max_rows) {
   return dim3((unsigned)(x < 1 ? 1 : x), (unsigned)nslices);
 }
 
+// k_rank for every voxel with events (all) or only the marked ones.
+static void launch_rank(const Batch& bt, const Workspace& w, const Brick& b, bool all,
+                        hipStream_t s) {
+  static_assert(kMaxBrickVoxels <= 8192, "k_rank holds at most 32 ballots per wave");
+  const bool big = b.volume() > 4096;
+  auto go = [&](auto fn) {
+    hipLaunchKernelGGL(fn, dim3(bt.nbricks), dim3(256), 0, s, bt, b, w.count, w.qmark, w.rank,
+                       w.ulist, w.brick_nq);
+  };
+  if (all)
+    big ? go(k_rank<true, 32>) : go(k_rank<true, 16>);
+  else
+    big ? go(k_rank<false, 32>) : go(k_rank<false, 16>);
+}
+
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
@@ -533,12 +545,7 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
-  if (queries)
-    hipLaunchKernelGGL(k_rank<false>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
-                       w.qmark, w.rank, w.ulist, w.brick_nq);
-  else
-    hipLaunchKernelGGL(k_rank<true>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
-                       w.qmark, w.rank, w.ulist, w.brick_nq);
+  launch_rank(bt, w, et.brick, queries == nullptr, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
@@ -588,8 +595,7 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt, w.vox,
                        w.qmark, w.err);
   }
-  hipLaunchKernelGGL(k_rank<false>, dim3(bt.nbricks), dim3(256), 0, s, bt, et.brick, w.count,
-                     w.qmark, w.rank, w.ulist, w.brick_nq);
+  launch_rank(bt, w, et.brick, false, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt,

@@ -240,4 +240,34 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
   *nbuf = 2;
 }
 
+// The encoder tilings a context offers: the default layout above first,
+// then each larger brick whose count box still fits beside two slabs (with
+// as many slabs as fit).  Larger bricks pay off where bricks hold few query
+// voxels (sparse slices: fewer passes over the table per row), the default
+// where they hold many (deeper slab buffering).
+std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp) {
+  std::vector<Tiling> out(1);
+  choose_layout(rx, ry, rt, d, precision, kp, &out[0].brick, &out[0].nbuf);
+  const Brick bigger[] = {{32, 32, 8}, {32, 16, 16}};
+  const int na = precision == VECKM_FP32 ? 4 : 2;
+  const bool even = (na * (d / 16) * 64) % (encode_waves() * 64) == 0;
+  for (const Brick& b : bigger) {
+    if (b.volume() <= out[0].brick.volume() || b.volume() > kMaxBrickVoxels ||
+        box_sx(b, rx) > 64)
+      continue;
+    auto fits = [&](int nb) {
+      return encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
+    };
+    if (!fits(2)) continue;
+    Tiling t{b, 2};
+    for (int nb = even ? kMaxSlabBuffers : 2; nb > 2; --nb)
+      if (fits(nb)) {
+        t.nbuf = nb;
+        break;
+      }
+    out.push_back(t);
+  }
+  return out;
+}
+
 }  // namespace veckm

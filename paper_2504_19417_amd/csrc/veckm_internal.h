@@ -58,6 +58,13 @@ OffsetTable make_offsets(int rx, int ry, int rt);
 // FP64 phases -> fp16 bit patterns [k][j][4] = (cos hi, cos lo, sin hi, sin lo).
 void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out);
 void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick, int* nbuf);
+// An encoder tiling: brick shape and table slabs buffered in LDS.
+struct Tiling {
+  Brick brick{32, 16, 8};
+  int nbuf = 2;
+};
+constexpr int kMaxBrickVoxels = 8192;  // largest brick (the ranking kernel's limit)
+std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp);
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol);
 int encode_rows_per_chunk(int d);
 int encode_waves();  // waves per encoder block
@@ -128,7 +135,7 @@ struct Workspace {
   float* rowflow = nullptr;     // U x 2
   int32_t* plan = nullptr;      // [0] = U, [1] = work counter, [2] = non-empty bricks
   int32_t* err = nullptr;       // error bits
-  int64_t vmax = 0, pmax = 0, nmax = 0, bmax = 0;
+  int64_t vmax = 0, pmax = 0, nmax = 0, bmax = 0, umax = 0;
   // paper form (no temporal bound) only
   float* G = nullptr;           // [D/8][H][W][8] complex: per-pixel temporal phase sums
   float* S = nullptr;           // [D/8][H][W][8] complex: window sums

@@ -98,6 +98,16 @@ _sig = {
     "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
+    "veckm_graph_create": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                                          ctypes.POINTER(_P)]),
+    "veckm_graph_launch": (ctypes.c_int, [_P, _P]),
+    "veckm_graph_destroy": (None, [_P]),
+    "veckm_tiling_count": (ctypes.c_int, [_P]),
+    "veckm_tiling_selected": (ctypes.c_int, [_P]),
+    "veckm_tiling_info": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "veckm_tiling_select": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "veckm_tune": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                                  ctypes.POINTER(ctypes.c_int32)]),
     "veckm_window_create": (ctypes.c_int, [ctypes.POINTER(veckm_params), ctypes.POINTER(_P)]),
     "veckm_window_push": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                          _P]),
@@ -369,6 +379,56 @@ class Context:
     def status(self, stream=None):
         return veckm_status(self.handle, self._stream(stream))
 
+    def tilings(self):
+        """[(bx, by, bt, slabs)] of the encoder tilings this context offers."""
+        n = _lib.veckm_tiling_count(self.handle)
+        out = []
+        for i in range(n):
+            info = (ctypes.c_int32 * 4)()
+            rc = _lib.veckm_tiling_info(self.handle, i, ctypes.cast(info, _P))
+            if rc:
+                raise VeckmError(rc, "veckm_tiling_info")
+            out.append(tuple(int(v) for v in info))
+        return out
+
+    def tiling(self):
+        return _lib.veckm_tiling_selected(self.handle)
+
+    def select_tiling(self, index):
+        rc = _lib.veckm_tiling_select(self.handle, int(index))
+        if rc:
+            raise VeckmError(rc, "veckm_tiling_select")
+
+    def tune(self, slices, events, reps=3, stream=None):
+        """Times every tiling on this batch and keeps the fastest; returns its index."""
+        self._check_inputs(events, None)
+        arr = make_slices(slices)
+        chosen = ctypes.c_int32(-1)
+        rc = _lib.veckm_tune(self.handle, ctypes.cast(arr, _P), len(slices), events.data_ptr(),
+                             int(reps), self._stream(stream), ctypes.byref(chosen))
+        if rc:
+            raise VeckmError(rc, "veckm_tune")
+        return chosen.value
+
+    def graph(self, slices, events, out, flow=True):
+        """A launch graph of flow_batch (flow=True) or encode_batch over
+        exactly these slices, event tensor and output tensor."""
+        self._check_inputs(events, None)
+        n = sum(int(s[4]) for s in slices)
+        width = 2 if flow else 2 * self.d
+        import torch
+        if n != events.shape[0] or tuple(out.shape) != (n, width) or not out.is_contiguous() \
+                or not out.is_cuda or out.dtype != torch.float32:
+            raise ValueError("events / out (contiguous float32 CUDA) do not match the slices")
+        arr = make_slices(slices)
+        h = _P()
+        rc = _lib.veckm_graph_create(self.handle, ctypes.cast(arr, _P), len(slices),
+                                     events.data_ptr(), out.data_ptr(), 1 if flow else 0,
+                                     ctypes.byref(h))
+        if rc:
+            raise VeckmError(rc, "veckm_graph_create")
+        return Graph(h, self, events, out)
+
     def profile(self, enable=True):
         veckm_profile_enable(self.handle, enable)
 
@@ -439,6 +499,30 @@ def veckm_server_stats(server, reset=False):
     if rc:
         raise VeckmError(rc, "veckm_server_stats")
     return {f: getattr(st, f) for f, _ in veckm_serving_stats._fields_}
+
+
+class Graph:
+    """A captured batch launch (holds its context, event and output tensors)."""
+
+    def __init__(self, handle, ctx, events, out):
+        self.handle, self.ctx, self.events, self.out = handle, ctx, events, out
+
+    def launch(self, stream=None):
+        rc = _lib.veckm_graph_launch(self.handle, self.ctx._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_graph_launch")
+        return self.out
+
+    def close(self):
+        if self.handle:
+            _lib.veckm_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Window(Context):

@@ -30,7 +30,9 @@ def test_header_declares_api():
                      "veckm_submit", "veckm_poll", "veckm_server_stats", "veckm_window_create",
                      "veckm_window_push", "veckm_window_encode", "veckm_window_flow",
                      "veckm_trainer_create", "veckm_trainer_step", "veckm_trainer_get",
-                     "veckm_trainer_destroy"]:
+                     "veckm_trainer_destroy", "veckm_graph_create", "veckm_graph_launch",
+                     "veckm_graph_destroy", "veckm_tiling_count", "veckm_tiling_selected",
+                     "veckm_tiling_info", "veckm_tiling_select", "veckm_tune"]:
         assert required in names
 
 
