@@ -277,6 +277,8 @@ def _find_csv(d, suffix):
 
 
 PROFILE_WORKLOADS = {
+    "batch64": "64-slice batch (lognormal 10k-500k events, 346x260 / 640x480, 50 bins, D=128, "
+               "r=5/3, perceptron 256-256-2), FP16/BF16 and FP32 forms, tuned tiling",
     "slice1m": "1M-event slice (346x260x50, D=128, r=5/3, perceptron 256-256-2), "
                "FP32 and FP16/BF16 forms",
     "paper_k8": "paper form, 640x480 recipe (0.5M events, 32 bins, D=64, delta 8, no temporal "
@@ -300,6 +302,14 @@ PROFILE_NOTES = {
                 "serve all three.",
 }
 PROFILE_NOTES["paper_k10"] = PROFILE_NOTES["paper_k8"]
+PROFILE_NOTES["batch64"] = (
+    "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end and "
+    "encoder), 1 warm-up and 3 timed steps.  FP16 form tilings: `k_encode<2, 8, 4, 1>` is the "
+    "default 32x16x8 brick (four slabs), `<2, 8, 2, 1>` the 32x32x8 brick (two slabs, the "
+    "tuner's pick: it also runs the timed steps), `<2, 8, 3, 1>` the 32x16x16 brick (three "
+    "slabs); `<4, 8, 2, 3>` is the FP32 form's encoder (one tiling fits).  `k_rank<true, 32>` "
+    "ranks the 8192-voxel bricks, `<true, 16>` the 4096-voxel ones.  The front-end kernels "
+    "serve both forms and the tuner runs.")
 
 
 def summarize_kernels(stats_dir, command, workload="slice1m"):
