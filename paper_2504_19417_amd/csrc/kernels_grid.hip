@@ -62,8 +62,9 @@ __device__ inline SliceDesc slice_by_event_block(const Batch& bt, int i) {
 }
 
 // One thread per event: validate against its slice, histogram (ADD), remember
-// the slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught by
-// k_pairs, which reads every count once.
+// the slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught
+// where the pair grid is built (k_rank, or k_pairs for a sliding window),
+// which reads every count once.
 template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err) {
@@ -108,8 +109,9 @@ __global__ void k_push(const int4* __restrict__ ev, int n, int W, int H, int T, 
 // (0 outside [0, W)), for x in [-1, W).  Any 4 consecutive voxels of a row
 // then sit in two aligned dwords, including a run that starts at x = -1.
 // Exact: counts are at most VECKM_MAX_VOXEL_EVENTS.
-// One wavefront per x row; blockIdx.y picks the slice, the blocks of a
-// slice stride over its H T rows.
+// The pair grid of a sliding window's new planes (slice calls build it in
+// k_rank).  One wavefront per x row; blockIdx.y picks the slice, the blocks
+// of a slice stride over its H T rows.
 __global__ __launch_bounds__(256) void k_pairs(Batch bt, const int32_t* __restrict__ count,
                                                uint32_t* __restrict__ pairs,
                                                int32_t* __restrict__ err) {
@@ -171,12 +173,18 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
 // quarter of the brick in voxel order: a first pass keeps its ballots, one
 // barrier gives every wave its offset, a second pass writes the numbers.
 // Brick sides are powers of two and a brick holds at most 256 kIt voxels.
-template <bool ALL, int kIt>
+// PAIRS: the block also writes the brick's entries of the pair grid (the
+// layout k_pairs writes: entry x of a row holds voxels x - 1 and x; the
+// voxel at x = W - 1 also writes entry W) and checks the voxel limit, so the
+// counts are read once for both.
+template <bool ALL, int kIt, bool PAIRS>
 __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
                                               const uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
-                                              int32_t* __restrict__ brick_nq) {
+                                              int32_t* __restrict__ brick_nq,
+                                              uint32_t* __restrict__ pairs,
+                                              int32_t* __restrict__ err) {
   __shared__ int wave_tot[4];
   const int gb = blockIdx.x;
   const SliceDesc s = slice_by_brick(bt, gb);
@@ -199,12 +207,41 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
   // all loads first (unconditional: a voxel outside the slice reads the
   // slice's first voxel and is masked), then the ballots
   bool flag[kIt];
+  int cv[PAIRS ? kIt : 1], pv[PAIRS ? kIt : 1];  // counts of the voxel and of x - 1
+  const int lx = lane & (b.bx - 1);  // the voxel's x within the brick (b.bx <= 64)
 #pragma unroll
   for (int k = 0; k < kIt; ++k) {
     const int64_t v = k < per ? voxel((wid * per + k) * 64 + lane) : (int64_t)-1;
     const int64_t a = v >= 0 ? v : s.grid_off;
-    const bool f = ALL ? (count[a] > 0) : (qmark[a] != 0);
+    if constexpr (PAIRS) {
+      cv[k] = count[a];
+      // the left neighbour of a brick's first column (x0 > 0) lies in the
+      // previous brick: read it; elsewhere it comes from the lane to the left
+      pv[k] = count[lx == 0 && x0 > 0 && v >= 0 ? a - 1 : a];
+    }
+    const bool f = ALL ? (PAIRS ? cv[k] > 0 : count[a] > 0) : (qmark[a] != 0);
     flag[k] = v >= 0 && f;
+  }
+  if constexpr (PAIRS) {
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+      if (k >= per) break;
+      const int li = (wid * per + k) * 64 + lane;
+      const int up = __shfl_up(cv[k], 1);
+      const int64_t v = voxel(li);
+      if (v >= 0) {
+        const int x = x0 + lx, y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+        const int lo = lx > 0 ? up : (x > 0 ? pv[k] : 0);
+        const int hi = cv[k];
+        bad |= hi > VECKM_MAX_VOXEL_EVENTS;
+        uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
+        row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
+                 ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
+        if (x == s.W - 1) row[s.W] = (uint32_t)__half_as_ushort(__float2half((float)hi));
+      }
+    }
+    if (bad) atomicOr(err, kErrOverflow);
   }
   unsigned long long bal[kIt];
   int tot = 0;
@@ -515,19 +552,27 @@ static dim3 pairs_grid(int nslices, int64_t max_rows) {
   return dim3((unsigned)(x < 1 ? 1 : x), (unsigned)nslices);
 }
 
-// k_rank for every voxel with events (all) or only the marked ones.
-static void launch_rank(const Batch& bt, const Workspace& w, const Brick& b, bool all,
+// k_rank for every voxel with events (all) or only the marked ones; with
+// `pairs` it also builds the pair grid.
+static void launch_rank(const Batch& bt, const Workspace& w, const Brick& b, bool all, bool pairs,
                         hipStream_t s) {
   static_assert(kMaxBrickVoxels <= 8192, "k_rank holds at most 32 ballots per wave");
   const bool big = b.volume() > 4096;
   auto go = [&](auto fn) {
     hipLaunchKernelGGL(fn, dim3(bt.nbricks), dim3(256), 0, s, bt, b, w.count, w.qmark, w.rank,
-                       w.ulist, w.brick_nq);
+                       w.ulist, w.brick_nq, w.pairs, w.err);
   };
-  if (all)
-    big ? go(k_rank<true, 32>) : go(k_rank<true, 16>);
-  else
-    big ? go(k_rank<false, 32>) : go(k_rank<false, 16>);
+  if (pairs) {
+    if (all)
+      big ? go(k_rank<true, 32, true>) : go(k_rank<true, 16, true>);
+    else
+      big ? go(k_rank<false, 32, true>) : go(k_rank<false, 16, true>);
+  } else {
+    if (all)
+      big ? go(k_rank<true, 32, false>) : go(k_rank<true, 16, false>);
+    else
+      big ? go(k_rank<false, 32, false>) : go(k_rank<false, 16, false>);
+  }
 }
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
@@ -539,13 +584,10 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   if (bt.n > 0)
     hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
-  if (pairs)
-    hipLaunchKernelGGL(k_pairs, pairs_grid(bt.nslices, bt.max_rows), dim3(256), 0, s, bt, w.count,
-                       w.pairs, w.err);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
-  launch_rank(bt, w, et.brick, queries == nullptr, s);
+  launch_rank(bt, w, et.brick, queries == nullptr, pairs, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
@@ -595,7 +637,7 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt, w.vox,
                        w.qmark, w.err);
   }
-  launch_rank(bt, w, et.brick, false, s);
+  launch_rank(bt, w, et.brick, false, false, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
   if (bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt,
