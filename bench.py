@@ -580,6 +580,7 @@ def batch_main(args):
         dt = (time.perf_counter() - t) / args.steps
         st = {k: (round(v[0] / v[1], 4) if v[1] else None) for k, v in c.profile_read().items()}
         status = c.status()
+        rows = c.last_rows()
         flows = out.cpu().numpy()
         c.close()
         if status != vk.VECKM_OK:
@@ -593,8 +594,16 @@ def batch_main(args):
             got.append(flows[off + q])
             off += len(e)
         got, ref = np.concatenate(got).astype(np.float64), np.concatenate(ref)
-        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st, tiling=list(tiling),
+        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st, tiling=list(tiling), rows=rows,
                          err=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    # the encoder (the dominant kernel) against the fp16 matrix-core peak
+    K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
+    r16 = res["fp16"]
+    achieved = encoder_flops_per_row(K, w.d) * r16["rows"] / (r16["stages"]["encode"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["fp16_TFLOPs"],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp16_TFLOPs"], 4),
+                "traffic": None, "kernel": "k_encode<2", "avg_launch_ms": r16["stages"]["encode"],
+                "rows_per_launch": r16["rows"], "flops_per_row": encoder_flops_per_row(K, w.d)}
     line = {
         "metric": "normal flows/sec, 64-slice batch in one launch sequence (BF16 perceptron)",
         "value": res["fp16"]["value"], "unit": "flows/s", "n_gpus": 1, "steps": args.steps,
@@ -611,7 +620,7 @@ def batch_main(args):
         "fp32": {"value": res["fp32"]["value"], "ms_per_step": round(res["fp32"]["ms"], 4),
                  "stages_ms": res["fp32"]["stages"], "tiling_brick_slabs": res["fp32"]["tiling"],
                  "err_vs_oracle": {"flow_relL2_sampled": res["fp32"]["err"]}},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roofline, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
