@@ -625,6 +625,62 @@ def batch_main(args):
     print(json.dumps(line), flush=True)
 
 
+def precision_main(args):
+    """The precision form: one 1280x720 slice of 5M events (64 moving edges
+    plus textured-blob noise), 100 bins, D = 128, r = 5/3, every event
+    queried; the FP16/BF16 form timed and compared with the FP32 form (whole
+    slice) and with the FP64 oracle (sampled events)."""
+    import torch
+    import oracle
+    from paper_2504_19417_amd import synth, veckm as vk
+
+    w = synth.workloads()["precision5m"]
+    ev, t0, T = synth.make_slice(w.slices[0])
+    A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
+    mlp = synth.init_mlp(w.d, w.hidden)
+    n = len(ev)
+    res = {f: run_form(vk, torch, w, ev, t0, T, A, mlp, f, args.steps, args.warmup)
+           for f in ("fp16", "fp32")}
+
+    def stages(r):
+        return {k: (round(v[0] / v[1], 4) if v[1] else None) for k, v in r["stages"].items()}
+
+    st16, st32 = stages(res["fp16"]), stages(res["fp32"])
+    err16 = sampled_error(oracle, w, ev, A, mlp, res["fp16"]["flows"])
+    err32 = sampled_error(oracle, w, ev, A, mlp, res["fp32"]["flows"])
+    f16 = res["fp16"]["flows"].astype(np.float64)
+    f32 = res["fp32"]["flows"].astype(np.float64)
+    vs32 = float(np.linalg.norm(f16 - f32) / np.linalg.norm(f32))
+    K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
+    rows = res["fp16"]["rows"]
+    achieved = encoder_flops_per_row(K, w.d) * rows / (st16["encode"] * 1e-3) / 1e12
+    line = {
+        "metric": "normal flows/sec, precision form (FP16 grid, BF16 perceptron) at 5M events",
+        "value": n * args.steps / res["fp16"]["elapsed"], "unit": "flows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["fp16"]["elapsed"] / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
+        "data": "synthetic (seeded moving edges + textured-blob noise)",
+        "config": {"workload": "precision5m", "sensor": "1280x720", "events": n, "bins": T,
+                   "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
+                   "queries": "all events"},
+        "stages_ms": st16, "rows": rows,
+        "err_vs_oracle": {"flow_relL2_sampled": err16},
+        "flow_relL2_vs_fp32_form": vs32,
+        "fp32": {"value": n * args.steps / res["fp32"]["elapsed"],
+                 "ms_per_step": round(res["fp32"]["elapsed"] / args.steps * 1e3, 4),
+                 "stages_ms": st32, "err_vs_oracle": {"flow_relL2_sampled": err32}},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
+                     "peak": PEAK["fp16_TFLOPs"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["fp16_TFLOPs"], 4), "traffic": None,
+                     "kernel": "k_encode<2", "avg_launch_ms": st16["encode"],
+                     "rows_per_launch": rows, "flops_per_row": encoder_flops_per_row(K, w.d)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def train_main(args):
     """Training the perceptron on the 1M-event slice's edge events (about 0.9M
     rows of FP32 encodings, D = 128, hidden 256, their true normal flows):
@@ -683,7 +739,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="slice1m",
-                    choices=["slice1m", "paper_k8", "paper_k10", "window", "train", "batch64"],
+                    choices=["slice1m", "paper_k8", "paper_k10", "window", "train", "batch64",
+                             "precision5m"],
                     help="slice1m: the bounded-window 1M-event slice (the headline line); "
                          "paper_k8 / paper_k10: the paper's own form at its recipes")
     ap.add_argument("--steps", type=int, default=20)
@@ -734,6 +791,9 @@ def main():
         return
     if args.workload == "batch64":
         batch_main(args)
+        return
+    if args.workload == "precision5m":
+        precision_main(args)
         return
     if args.workload != "slice1m":
         paper_main(args, args.workload)

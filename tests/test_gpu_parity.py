@@ -250,3 +250,50 @@ def test_slice1m_full_run_sampled_parity(vk, slice1m, precision):
     emb3, st = _run_encode(c, ev2, s["t0"] + (1 << 30), s["T"])
     assert st == vk.VECKM_OK and np.array_equal(emb, emb3)
     c.close()
+
+
+@pytest.fixture(scope="module")
+def precision5m():
+    w = synth.workloads()["precision5m"]
+    ev, t0, T = synth.make_slice(w.slices[0])
+    A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
+    mlp = synth.init_mlp(w.d, w.hidden)
+    q = synth.sample_queries(len(ev), 1024, 78)
+    emb, cnt = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q)
+    return dict(w=w, ev=ev, t0=t0, T=T, A=A, mlp=mlp, q=q, emb=emb,
+                flow=oracle.mlp(emb, *mlp))
+
+
+def test_precision5m_full_run_sampled_parity(vk, precision5m):
+    """The precision workload (1280x720, 5M events with textured-blob noise,
+    100 bins, D=128, r=5/3) at full size in the benchmark's launch
+    configuration, both forms: 1024 sampled rows against the oracle, and the
+    FP16/BF16 form's flows against the FP32 form's over the whole slice."""
+    s = precision5m
+    w = s["w"]
+    evt = torch.from_numpy(s["ev"]).cuda()
+    qt = torch.from_numpy(s["q"].astype(np.int64)).cuda()
+    flows = {}
+    for precision in ("fp32", "fp16"):
+        _say("case: precision5m %s full run" % precision)
+        c = _ctx(vk, 1280, 720, (w.rx, w.ry, w.rt), s["A"], s["T"], len(s["ev"]), precision,
+                 mlp=s["mlp"])
+        emb = c.encode(evt, s["t0"], s["T"])
+        emb_q = emb[qt].cpu().numpy()
+        del emb
+        flow = c.flow(evt, s["t0"], s["T"]).cpu().numpy()
+        torch.cuda.synchronize()
+        assert c.status() == vk.VECKM_OK
+        c.close()
+        e = rel_l2(emb_q, s["emb"])
+        f = rel_l2(flow[s["q"]], s["flow"])
+        _say("precision5m %s sampled emb relL2 %.3e flow relL2 %.3e" % (precision, e, f))
+        if precision == "fp32":
+            assert e <= 1e-4 and f <= 1e-3
+        else:
+            assert e <= 2e-3 and f <= 3e-2
+        assert np.isfinite(flow).all()
+        flows[precision] = flow
+    d = rel_l2(flows["fp16"], flows["fp32"].astype(np.float64))
+    _say("precision5m fp16 vs fp32 flow relL2 %.3e" % d)
+    assert d <= 3e-2
