@@ -778,7 +778,7 @@ def main():
                 f.write(summarize_kernels(args.summarize_kernels, args.command, wl))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(independent slices shard across GPUs with no exchange); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
