@@ -295,9 +295,12 @@ __device__ inline int chunk_class(int nq, int ch) {
 __device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch, int tile,
                                  int (&q)[kScanPer], int (&v)[kScanNV], int (&ex)[kScanNV],
                                  int (&tot)[kScanNV]) {
+  constexpr int NWV = kScanThreads / 64;  // waves
   __shared__ int tq[kScanTile];
-  __shared__ int sums[kScanNV][kScanThreads];
+  __shared__ int wsum[kScanNV][NWV];
+  __shared__ int ttot[kScanNV];
   const int tid = threadIdx.x, base = tile * kScanTile;
+  const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
   for (int u = 0; u < kScanPer; ++u) {
     const int i = base + u * kScanThreads + tid;
@@ -314,22 +317,41 @@ __device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch,
 #pragma unroll
     for (int k = 0; k < kScanClasses; ++k) v[k] += c == k;
   }
+  // inclusive scans within each wave (shuffles), then over the wave totals
+  int inc[kScanNV];
 #pragma unroll
-  for (int k = 0; k < kScanNV; ++k) sums[k][tid] = v[k];
+  for (int k = 0; k < kScanNV; ++k) inc[k] = v[k];
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) {
+      const int t = __shfl_up(inc[k], d);
+      if (lane >= d) inc[k] += t;
+    }
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < kScanNV; ++k) wsum[k][wid] = inc[k];
   __syncthreads();
-  for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive scans, all at once
-    int add[kScanNV];
+  if (wid == 0) {  // exclusive scan of the wave totals (lanes 0 .. NWV-1)
 #pragma unroll
-    for (int k = 0; k < kScanNV; ++k) add[k] = tid >= d ? sums[k][tid - d] : 0;
-    __syncthreads();
+    for (int k = 0; k < kScanNV; ++k) {
+      const int own = lane < NWV ? wsum[k][lane] : 0;
+      int s = own;
 #pragma unroll
-    for (int k = 0; k < kScanNV; ++k) sums[k][tid] += add[k];
-    __syncthreads();
+      for (int d = 1; d < NWV; d <<= 1) {
+        const int t = __shfl_up(s, d);
+        if (lane >= d) s += t;
+      }
+      const int total = __shfl(s, NWV - 1);
+      if (lane < NWV) wsum[k][lane] = s - own;
+      if (lane == 0) ttot[k] = total;
+    }
   }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < kScanNV; ++k) {
-    ex[k] = sums[k][tid] - v[k];
-    tot[k] = sums[k][kScanThreads - 1];
+    ex[k] = wsum[k][wid] + inc[k] - v[k];
+    tot[k] = ttot[k];
   }
 }
 
