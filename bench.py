@@ -277,6 +277,8 @@ def _find_csv(d, suffix):
 
 
 PROFILE_WORKLOADS = {
+    "precision5m": "precision form (1280x720x100, 5M events with textured-blob noise, D=128, "
+                   "r=5/3, perceptron 256-256-2), FP16/BF16 and FP32 forms",
     "batch64": "64-slice batch (lognormal 10k-500k events, 346x260 / 640x480, 50 bins, D=128, "
                "r=5/3, perceptron 256-256-2), FP16/BF16 and FP32 forms, tuned tiling",
     "slice1m": "1M-event slice (346x260x50, D=128, r=5/3, perceptron 256-256-2), "
@@ -302,6 +304,11 @@ PROFILE_NOTES = {
                 "serve all three.",
 }
 PROFILE_NOTES["paper_k10"] = PROFILE_NOTES["paper_k8"]
+PROFILE_NOTES["precision5m"] = (
+    "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `k_encode<2, ...>` and "
+    "`k_mlp_res<0, ...>` belong to the FP16/BF16 form, `k_encode<4, ...>` (writing fp16 hi/lo "
+    "rows) and `k_mlp_res<2, ...>` to the FP32 form; the front-end kernels serve both.  The "
+    "brick scan runs as three launches (23,400 bricks: three 8192-brick tiles).")
 PROFILE_NOTES["batch64"] = (
     "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end and "
     "encoder), 1 warm-up and 3 timed steps.  FP16 form tilings: `k_encode<2, 8, 4, 1>` is the "
@@ -774,8 +781,9 @@ def main():
                 f.write(traffic_markdown(rec, wl))
             print(json.dumps(rec["kernels"], indent=1))
         if args.summarize_kernels:
+            text = summarize_kernels(args.summarize_kernels, args.command, wl)
             with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % wl), "w") as f:
-                f.write(summarize_kernels(args.summarize_kernels, args.command, wl))
+                f.write(text)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
