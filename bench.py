@@ -66,11 +66,16 @@ def eqn18_split(n, m_small, ms_small, ms_all):
             "points": [[m_small, round(ms_small, 4)], [n, round(ms_all, 4)]]}
 
 
-def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=None):
+def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=None,
+             tune=False):
     ctx = vk.Context(w.slices[0].width, w.slices[0].height, w.rx, w.ry, w.rt, A, T, len(ev),
                      precision)
     ctx.set_mlp(*mlp)
     evt = torch.from_numpy(ev).cuda()
+    tiling = None
+    if tune:  # the library's tuner picks the encoder tiling (set-up, not timed)
+        W, H = w.slices[0].width, w.slices[0].height
+        tiling = list(ctx.tilings()[ctx.tune([(W, H, t0, T, len(ev))], evt, reps=3)])
     qt = None if queries is None else torch.from_numpy(np.asarray(queries, np.int32)).cuda()
     m = len(ev) if queries is None else len(queries)
     out = torch.empty((m, 2), dtype=torch.float32, device="cuda")
@@ -101,7 +106,7 @@ def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=
     ctx.close()
     if st != vk.VECKM_OK:
         raise RuntimeError("input error reported by the device")
-    return dict(elapsed=elapsed, lat=lat, stages=stages, rows=rows, flows=flows)
+    return dict(elapsed=elapsed, lat=lat, stages=stages, rows=rows, flows=flows, tiling=tiling)
 
 
 def cpu_baseline(oracle, w, ev, A, mlp, target_s):
@@ -646,7 +651,7 @@ def precision_main(args):
     A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
     mlp = synth.init_mlp(w.d, w.hidden)
     n = len(ev)
-    res = {f: run_form(vk, torch, w, ev, t0, T, A, mlp, f, args.steps, args.warmup)
+    res = {f: run_form(vk, torch, w, ev, t0, T, A, mlp, f, args.steps, args.warmup, tune=True)
            for f in ("fp16", "fp32")}
 
     def stages(r):
@@ -671,13 +676,14 @@ def precision_main(args):
         "data": "synthetic (seeded moving edges + textured-blob noise)",
         "config": {"workload": "precision5m", "sensor": "1280x720", "events": n, "bins": T,
                    "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
-                   "queries": "all events"},
+                   "queries": "all events", "tiling_brick_slabs": res["fp16"]["tiling"]},
         "stages_ms": st16, "rows": rows,
         "err_vs_oracle": {"flow_relL2_sampled": err16},
         "flow_relL2_vs_fp32_form": vs32,
         "fp32": {"value": n * args.steps / res["fp32"]["elapsed"],
                  "ms_per_step": round(res["fp32"]["elapsed"] / args.steps * 1e3, 4),
-                 "stages_ms": st32, "err_vs_oracle": {"flow_relL2_sampled": err32}},
+                 "stages_ms": st32, "tiling_brick_slabs": res["fp32"]["tiling"],
+                 "err_vs_oracle": {"flow_relL2_sampled": err32}},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                      "peak": PEAK["fp16_TFLOPs"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK["fp16_TFLOPs"], 4), "traffic": None,

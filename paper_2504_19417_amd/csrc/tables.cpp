@@ -242,18 +242,20 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
 
 // The encoder tilings a context offers: the default layout above first,
 // then each larger brick whose count box still fits beside two slabs (with
-// as many slabs as fit).  Larger bricks pay off where bricks hold few query
-// voxels (sparse slices: fewer passes over the table per row), the default
-// where they hold many (deeper slab buffering).
+// as many slabs as fit), then a smaller brick if it fits more slabs than the
+// default.  Larger bricks pay off where bricks hold few query voxels (sparse
+// slices: fewer passes over the table per row); deeper slab buffering where
+// they hold many.
 std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp) {
   std::vector<Tiling> out(1);
   choose_layout(rx, ry, rt, d, precision, kp, &out[0].brick, &out[0].nbuf);
-  const Brick bigger[] = {{32, 32, 8}, {32, 16, 16}};
+  const Tiling def = out[0];
+  const Brick cand[] = {{32, 32, 8}, {32, 16, 16}, {32, 16, 4}};
   const int na = precision == VECKM_FP32 ? 4 : 2;
   const bool even = (na * (d / 16) * 64) % (encode_waves() * 64) == 0;
-  for (const Brick& b : bigger) {
-    if (b.volume() <= out[0].brick.volume() || b.volume() > kMaxBrickVoxels ||
-        box_sx(b, rx) > 64)
+  for (const Brick& b : cand) {
+    const bool bigger = b.volume() > def.brick.volume();
+    if (b.volume() == def.brick.volume() || b.volume() > kMaxBrickVoxels || box_sx(b, rx) > 64)
       continue;
     auto fits = [&](int nb) {
       return encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
@@ -265,6 +267,7 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
         t.nbuf = nb;
         break;
       }
+    if (!bigger && t.nbuf <= def.nbuf) continue;  // smaller only for deeper buffering
     out.push_back(t);
   }
   return out;
