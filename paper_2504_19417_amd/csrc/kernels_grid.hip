@@ -226,19 +226,20 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < kIt; ++k) {
-      if (k >= per) break;
-      const int li = (wid * per + k) * 64 + lane;
-      const int up = __shfl_up(cv[k], 1);
-      const int64_t v = voxel(li);
-      if (v >= 0) {
-        const int x = x0 + lx, y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
-        const int lo = lx > 0 ? up : (x > 0 ? pv[k] : 0);
-        const int hi = cv[k];
-        bad |= hi > VECKM_MAX_VOXEL_EVENTS;
-        uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
-        row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
-                 ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
-        if (x == s.W - 1) row[s.W] = (uint32_t)__half_as_ushort(__float2half((float)hi));
+      const int up = __shfl_up(cv[k], 1);  // (all lanes; per is uniform)
+      if (k < per) {
+        const int li = (wid * per + k) * 64 + lane;
+        const int64_t v = voxel(li);
+        if (v >= 0) {
+          const int x = x0 + lx, y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+          const int lo = lx > 0 ? up : (x > 0 ? pv[k] : 0);
+          const int hi = cv[k];
+          bad |= hi > VECKM_MAX_VOXEL_EVENTS;
+          uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
+          row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
+                   ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
+          if (x == s.W - 1) row[s.W] = (uint32_t)__half_as_ushort(__float2half((float)hi));
+        }
       }
     }
     if (bad) atomicOr(err, kErrOverflow);
