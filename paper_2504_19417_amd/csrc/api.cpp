@@ -513,6 +513,7 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     rc = VECKM_E_HIP;
   if (!rc && hipMemset(dzeros, 0, 64 * sizeof(uint32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
+  if (!rc && hipMemset(w.qmark, 0, (size_t)s.V) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = VECKM_E_HIP;
   if (rc) {

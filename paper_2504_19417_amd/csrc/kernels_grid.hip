@@ -28,11 +28,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
-}
-
 // The slice of event i, for blocks whose threads take consecutive events
 // i = blockIdx.x * blockDim.x + threadIdx.x: two threads find the slices of
 // the block's first and last event, and the rest search only between them
@@ -62,12 +57,14 @@ __device__ inline SliceDesc slice_by_event_block(const Batch& bt, int i) {
 }
 
 // One thread per event: validate against its slice, histogram (ADD), remember
-// the slice-local voxel.  Voxels over VECKM_MAX_VOXEL_EVENTS are caught
+// the slice-local voxel, and mark it as a query voxel when qmark is given
+// (a sliding window's query events).  Voxels over VECKM_MAX_VOXEL_EVENTS are caught
 // where the pair grid is built (k_rank, or k_pairs for a sliding window),
 // which reads every count once.
 template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
-                          int32_t* __restrict__ vox, int32_t* __restrict__ err) {
+                          int32_t* __restrict__ vox, int32_t* __restrict__ err,
+                          uint8_t* __restrict__ qmark) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x * blockDim.x >= bt.n) return;  // (whole block; launches never do this)
   const SliceDesc s = slice_by_event_block(bt, i);
@@ -83,6 +80,7 @@ __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __rest
   }
   const int v = ((int)dt * s.H + e.y) * s.W + e.x;
   if (ADD) atomicAdd(&count[s.grid_off + v], 1);  // result unused: a no-return atomic
+  if (qmark) qmark[s.grid_off + v] = 1;
   vox[i] = v;
 }
 
@@ -179,7 +177,7 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
 // counts are read once for both.
 template <bool ALL, int kIt, bool PAIRS>
 __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
-                                              const uint8_t* __restrict__ qmark,
+                                              uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
                                               int32_t* __restrict__ brick_nq,
@@ -263,7 +261,9 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
       if ((bal[k] >> lane) & 1ull) {
         const int li = (wid * per + k) * 64 + lane;
         const int r = base + __popcll(bal[k] & below);
-        rank[voxel(li)] = r;
+        const int64_t v = voxel(li);
+        rank[v] = r;
+        if (!ALL) qmark[v] = 0;  // the marks are clear again for the next call
         ulist[(int64_t)gb * BV + r] = li;
       }
       base += __popcll(bal[k]);
@@ -602,11 +602,10 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
-  if (queries)
-    hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.qmark, bt.nvox);
   if (bt.n > 0)
     hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err);
+                       reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err,
+                       (uint8_t*)nullptr);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
@@ -653,12 +652,10 @@ int launch_window_push(const Workspace& w, const veckm_event* ev, int64_t n, int
 int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event* queries,
                           const EncodeTables& et, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.qmark, bt.nvox);
   if (bt.n > 0) {
+    // locate the query events and mark their voxels in one pass
     hipLaunchKernelGGL(k_scatter<false>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err);
-    hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt, w.vox,
-                       w.qmark, w.err);
+                       reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err, w.qmark);
   }
   launch_rank(bt, w, et.brick, false, false, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);

@@ -121,7 +121,8 @@ struct Workspace {
                                 // counts of voxels x and x + 1 of that row, x in [-1, W)
   const uint32_t* zeros = nullptr;  // 64 zero dwords (out-of-grid reads)
   int32_t* rank = nullptr;      // voxels: brick-local rank of query voxels
-  uint8_t* qmark = nullptr;     // voxels: query-voxel marks (query subsets)
+  uint8_t* qmark = nullptr;     // voxels: query-voxel marks (query subsets, windows); all zero
+                                // between calls (the ranking pass clears the marks it reads)
   int32_t* ulist = nullptr;     // bricks * brick volume: brick-local voxel of each rank
   int32_t* brick_nq = nullptr;  // bricks
   int32_t* brick_off = nullptr; // bricks + 1 (exclusive scan)
