@@ -318,8 +318,10 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
     if (rc) return rc;
   }
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
-  return flow ? launch_expand_flow(bt, c->w, flow, stream)
-              : launch_expand_emb(bt, c->w, c->p.d, emb, stream);
+  // (a window's queries are the query events themselves: index i is event i)
+  const int32_t* q = c->window ? nullptr : queries;
+  return flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, flow, stream)
+              : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, c->p.d, emb, stream);
 }
 
 }  // namespace

@@ -559,6 +559,52 @@ __global__ void k_expand_flow(const int32_t* __restrict__ qmap, int m,
   out[i] = r >= 0 ? rowflow[r] : make_float2(nan, nan);
 }
 
+// Output expansion without a query -> row map (all forms but the paper
+// form): each query finds its row from its event's voxel, the voxel's rank
+// in its brick and the brick's first row.  SUB: `queries` lists the query
+// events (one slice); else query i is event i.
+template <bool SUB>
+__device__ inline int query_row(const int32_t* __restrict__ queries, const Batch& bt,
+                                const SliceDesc& s, const Brick& b,
+                                const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
+                                const int32_t* __restrict__ brick_off, int i) {
+  const int e = SUB ? queries[i] : i;
+  if (e < 0 || e >= bt.n) return -1;  // (reported by k_mark)
+  const int v = vox[e];
+  return v < 0 ? -1 : qmap_row(s, b, v, rank, brick_off);
+}
+
+template <bool SUB>
+__global__ void k_expand_flow_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
+                                const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
+                                const int32_t* __restrict__ brick_off,
+                                const float2* __restrict__ rowflow, float2* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= bt.m) return;  // (whole block; launches never do this)
+  const SliceDesc s = SUB ? bt.s0 : slice_by_event_block(bt, i);
+  if (i >= bt.m) return;
+  const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, i);
+  const float nan = __builtin_nanf("");
+  out[i] = r >= 0 ? rowflow[r] : make_float2(nan, nan);
+}
+
+// One wavefront per query.
+template <bool SUB>
+__global__ void k_expand_emb_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
+                               const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
+                               const int32_t* __restrict__ brick_off,
+                               const float* __restrict__ rows, int d2, float* __restrict__ out) {
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (q >= bt.m) return;
+  const SliceDesc s = SUB ? bt.s0 : slice_by_event(bt, (int)q);
+  const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, (int)q);
+  const float4* src = reinterpret_cast<const float4*>(rows + (int64_t)(r < 0 ? 0 : r) * d2);
+  float4* dst = reinterpret_cast<float4*>(out + q * d2);
+  const float nan = __builtin_nanf("");
+  for (int c = lane; c < d2 / 4; c += 64) dst[c] = r >= 0 ? src[c] : make_float4(nan, nan, nan, nan);
+}
+
 static int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 static int fill_grid(int64_t n) {
@@ -611,10 +657,11 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                        w.qmark, w.err);
   launch_rank(bt, w, et.brick, queries == nullptr, pairs, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
-  if (bt.m > 0)
+  // the paper form needs each row's voxel (and its expansion reads the query
+  // -> row map); the other forms find rows as they expand
+  if (!pairs && bt.m > 0)
     hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt,
-                       et.brick, w.vox, w.rank, w.brick_off, w.qmap,
-                       pairs ? nullptr : w.rowvox);
+                       et.brick, w.vox, w.rank, w.brick_off, w.qmap, w.rowvox);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
@@ -659,9 +706,6 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
   }
   launch_rank(bt, w, et.brick, false, false, s);
   launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
-  if (bt.m > 0)
-    hipLaunchKernelGGL(k_qmap, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, nullptr, bt,
-                       et.brick, w.vox, w.rank, w.brick_off, w.qmap, nullptr);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
@@ -673,19 +717,38 @@ int launch_take_err(const Workspace& w, int32_t* host, void* stream) {
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream) {
+int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
+                      const Brick& b, bool use_qmap, int d, float* emb, void* stream) {
   if (bt.m <= 0) return VECKM_OK;
-  hipLaunchKernelGGL(k_expand_emb, dim3(blocks_for((int64_t)bt.m * 64, 256)), dim3(256), 0,
-                     (hipStream_t)stream, w.qmap, bt.m, static_cast<const float*>(w.rows), 2 * d,
-                     emb);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(blocks_for((int64_t)bt.m * 64, 256));
+  const float* rows = static_cast<const float*>(w.rows);
+  if (use_qmap)
+    hipLaunchKernelGGL(k_expand_emb, grid, dim3(256), 0, s, w.qmap, bt.m, rows, 2 * d, emb);
+  else if (queries)
+    hipLaunchKernelGGL(k_expand_emb_q<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox, w.rank,
+                       w.brick_off, rows, 2 * d, emb);
+  else
+    hipLaunchKernelGGL(k_expand_emb_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rows, 2 * d, emb);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream) {
+int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
+                       const Brick& b, bool use_qmap, float* flow, void* stream) {
   if (bt.m <= 0) return VECKM_OK;
-  hipLaunchKernelGGL(k_expand_flow, dim3(blocks_for(bt.m, 256)), dim3(256), 0,
-                     (hipStream_t)stream, w.qmap, bt.m,
-                     reinterpret_cast<const float2*>(w.rowflow), reinterpret_cast<float2*>(flow));
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(blocks_for(bt.m, 256));
+  const float2* rf = reinterpret_cast<const float2*>(w.rowflow);
+  float2* out = reinterpret_cast<float2*>(flow);
+  if (use_qmap)
+    hipLaunchKernelGGL(k_expand_flow, grid, dim3(256), 0, s, w.qmap, bt.m, rf, out);
+  else if (queries)
+    hipLaunchKernelGGL(k_expand_flow_q<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rf, out);
+  else
+    hipLaunchKernelGGL(k_expand_flow_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rf, out);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

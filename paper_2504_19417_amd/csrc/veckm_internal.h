@@ -199,13 +199,17 @@ void make_paper_tables(const double* A, int d, int width, int height, int max_bi
 constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
                   int num_cus, void* stream);
-int launch_expand_emb(const Batch& bt, const Workspace& w, int d, float* emb, void* stream);
+// Per-query outputs; use_qmap: rows from the query -> row map (paper form),
+// else found from each query's voxel (`queries` as in the call, or NULL).
+int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
+                      const Brick& b, bool use_qmap, int d, float* emb, void* stream);
 int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int num_cus,
                void* stream);
 // Whether the FP32-form perceptron runs on fp16 hi/lo operand pairs for
 // this shape (W1 fragments fit in registers); else on the fp32 matrix cores.
 bool mlp_rows_split(int d, int hidden);
-int launch_expand_flow(const Batch& bt, const Workspace& w, float* flow, void* stream);
+int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
+                       const Brick& b, bool use_qmap, float* flow, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
 int launch_take_err(const Workspace& w, int32_t* host, void* stream);
 // Sliding window: the bins [clear_b0, clear_b0 + clear_nb) enter the ring of
