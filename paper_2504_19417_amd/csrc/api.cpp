@@ -298,11 +298,19 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
                    : !mlp_rows_split(c->p.d, c->mw.hidden) ? kRowsF32
                    : c->paper                          ? kRowsSplit16
                                                       : kRowsHiLo16;
+  // slice calls (not the paper form; a window's counts are resident) find
+  // the count grid zero and leave it zero: with every event queried the
+  // output expansion clears every counted voxel, a query subset clears the
+  // grid after its expansion, and so does a call whose launches fail
+  const bool clear = !c->paper && !c->window;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
     const int rc = c->window ? launch_window_prepare(bt, c->w, ev, c->et, stream)
                              : launch_prepare(bt, c->w, ev, queries, c->et, !c->paper, stream);
-    if (rc) return rc;
+    if (rc) {
+      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      return rc;
+    }
   }
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
@@ -310,18 +318,31 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
     const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 ? rows : kRowsF32;
     const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, c->num_cus, stream)
                             : launch_encode(bt, c->w, c->et, erows, c->num_cus, stream);
-    if (rc) return rc;
+    if (rc) {
+      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      return rc;
+    }
   }
   if (flow) {
     StageTimer t(c, VECKM_STAGE_MLP, stream);
     const int rc = launch_mlp(c->w, c->mw, c->p.d, rows, c->num_cus, stream);
-    if (rc) return rc;
+    if (rc) {
+      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      return rc;
+    }
   }
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
   // (a window's queries are the query events themselves: index i is event i)
   const int32_t* q = c->window ? nullptr : queries;
-  return flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, flow, stream)
-              : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, c->p.d, emb, stream);
+  const bool in_expand = clear && !q;
+  int rc = flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, in_expand, flow, stream)
+                : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, in_expand, c->p.d, emb,
+                                    stream);
+  if (clear && (q || rc)) {
+    const int rc2 = launch_clear_counts(bt, c->w, stream);
+    rc = rc ? rc : rc2;
+  }
+  return rc;
 }
 
 }  // namespace
@@ -516,6 +537,7 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   if (!rc && hipMemset(dzeros, 0, 64 * sizeof(uint32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.qmark, 0, (size_t)s.V) != hipSuccess) rc = VECKM_E_HIP;
+  if (!rc && hipMemset(w.count, 0, (size_t)s.V * 4) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = VECKM_E_HIP;
   if (rc) {
@@ -866,6 +888,9 @@ int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
       if (!rc && bt.m > 0) {
         rc = launch_prepare(bt, ctx->w, events, nullptr, ctx->et, true, stream);
         if (!rc) rc = launch_encode(bt, ctx->w, ctx->et, rows, ctx->num_cus, stream);
+        // no output expansion here: return the counts to zero
+        const int rc3 = launch_clear_counts(bt, ctx->w, stream);
+        rc = rc ? rc : rc3;
       }
       const int rc2 = release_slot(ctx, slot, stream);
       rc = rc ? rc : rc2;
