@@ -300,8 +300,9 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
                                                       : kRowsHiLo16;
   // slice calls (not the paper form; a window's counts are resident) find
   // the count grid zero and leave it zero: with every event queried the
-  // output expansion clears every counted voxel, a query subset clears the
-  // grid after its expansion, and so does a call whose launches fail
+  // encoder clears its rows' voxels (exactly the counted ones), a query
+  // subset clears the grid after its expansion, and so does a call whose
+  // launches fail
   const bool clear = !c->paper && !c->window;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
@@ -317,7 +318,8 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
     // the encoder writes fp32 rows unless the perceptron takes bf16 or hi/lo rows
     const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 ? rows : kRowsF32;
     const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, c->num_cus, stream)
-                            : launch_encode(bt, c->w, c->et, erows, c->num_cus, stream);
+                            : launch_encode(bt, c->w, c->et, erows, clear && !queries,
+                                            c->num_cus, stream);
     if (rc) {
       if (clear) (void)launch_clear_counts(bt, c->w, stream);
       return rc;
@@ -334,10 +336,8 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
   // (a window's queries are the query events themselves: index i is event i)
   const int32_t* q = c->window ? nullptr : queries;
-  const bool in_expand = clear && !q;
-  int rc = flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, in_expand, flow, stream)
-                : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, in_expand, c->p.d, emb,
-                                    stream);
+  int rc = flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, flow, stream)
+                : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, c->p.d, emb, stream);
   if (clear && (q || rc)) {
     const int rc2 = launch_clear_counts(bt, c->w, stream);
     rc = rc ? rc : rc2;
@@ -886,11 +886,10 @@ int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
       // (the output argument is only checked for presence; nothing is written)
       if (!rc) rc = multi_batch(ctx, slices, count, events, events, stream, &bt, &slot);
       if (!rc && bt.m > 0) {
+        // (the encoder returns the counts to zero, as in a batch call)
         rc = launch_prepare(bt, ctx->w, events, nullptr, ctx->et, true, stream);
-        if (!rc) rc = launch_encode(bt, ctx->w, ctx->et, rows, ctx->num_cus, stream);
-        // no output expansion here: return the counts to zero
-        const int rc3 = launch_clear_counts(bt, ctx->w, stream);
-        rc = rc ? rc : rc3;
+        if (!rc) rc = launch_encode(bt, ctx->w, ctx->et, rows, true, ctx->num_cus, stream);
+        if (rc) (void)launch_clear_counts(bt, ctx->w, stream);
       }
       const int rc2 = release_slot(ctx, slot, stream);
       rc = rc ? rc : rc2;

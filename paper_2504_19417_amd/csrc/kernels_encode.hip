@@ -44,7 +44,8 @@ struct EncArgs {
   int K, nsteps;
   int SX, SY, ST, vol;
   int D;
-  const int32_t* count;
+  int32_t* count;      // the count grid: the rows' voxels are returned to zero when clear
+  int clear;
   const int32_t* ulist;
   const int4* order;  // work list: {brick, rows, first row, slice}
   int lds_slices;     // slices whose descriptors are copied to LDS (0: read them from global)
@@ -383,6 +384,9 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
     const int row0 = __builtin_amdgcn_readfirstlane(cur.z);
     const int si = __builtin_amdgcn_readfirstlane(cur.w);
 
+    // the brick's first voxel in the count grid and the grid's strides (for
+    // returning the rows' counts to zero: nothing reads them after ranking)
+    int vlo = 0, vhi = 0, vW = 0, vH = 0;
     // ---- the brick's count box: one global->LDS copy per box row from the
     //      pair grid (lanes outside the slice read zeros); it has landed once
     //      the first chunk's prologue wait returns
@@ -390,6 +394,14 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
       const SliceDesc sl = a.bt.nslices == 1 ? a.bt.s0 : a.lds_slices ? stab[si] : a.bt.table[si];
       const int lb = bid - sl.brick_off;
       const int bxi = lb % sl.nbx, byi = (lb / sl.nbx) % sl.nby, bti = lb / (sl.nbx * sl.nby);
+      if (a.clear) {
+        const int64_t vorg = sl.grid_off +
+                             ((int64_t)(bti * a.b.bt) * sl.H + byi * a.b.by) * sl.W + bxi * a.b.bx;
+        vlo = __builtin_amdgcn_readfirstlane((int)(uint32_t)vorg);
+        vhi = __builtin_amdgcn_readfirstlane((int)(vorg >> 32));
+        vW = __builtin_amdgcn_readfirstlane(sl.W);
+        vH = __builtin_amdgcn_readfirstlane(sl.H);
+      }
       const int x = bxi * a.b.bx - a.rx - kRunPad + lane;
       const int y0 = byi * a.b.by - a.ry, tb = bti * a.b.bt - a.rt;
       const bool xin = x >= -1 && x < sl.W;  // the pair grid has a column for x = -1
@@ -420,6 +432,10 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
         const int li = a.ulist[(int64_t)bid * BV + rr];
         const int lx = li % a.b.bx, ly = (li / a.b.bx) % a.b.by, lt = li / (a.b.bx * a.b.by);
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx + kRunPad);
+        if (a.clear && r < nr) {
+          const int64_t vorg = ((int64_t)(uint32_t)vhi << 32) | (uint32_t)vlo;
+          a.count[vorg + ((int64_t)lt * vH + ly) * vW + lx] = 0;
+        }
       }
       // first slabs of the table
       if constexpr (kEncPairSteps && NBUF == 4) {
@@ -618,7 +634,7 @@ int encode_rows_per_chunk(int d) { return chunk_rows(d / 16); }
 int encode_waves() { return kEncWaves; }
 
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  int num_cus, void* stream) {
+                  bool clear, int num_cus, void* stream) {
   EncArgs a;
   a.bt = bt;
   a.b = et.brick;
@@ -633,6 +649,7 @@ int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, i
   a.vol = a.SX * a.SY * a.ST;
   a.D = et.d;
   a.count = w.count;
+  a.clear = clear ? 1 : 0;
   a.ulist = w.ulist;
   a.order = reinterpret_cast<const int4*>(w.order);
   a.lds_slices = 0;

@@ -574,29 +574,15 @@ __device__ inline int query_row(const int32_t* __restrict__ queries, const Batch
   return v < 0 ? -1 : qmap_row(s, b, v, rank, brick_off);
 }
 
-// With every event queried (!SUB) and `count` given, each query also
-// returns its voxel's count to zero: every counted voxel holds a query, and
-// nothing reads the counts after ranking, so the grid is all zero for the
-// next call without a fill.
-template <bool SUB>
-__device__ inline void clear_count(int32_t* __restrict__ count, const SliceDesc& s,
-                                   const int32_t* __restrict__ vox, int i) {
-  if (SUB || !count) return;
-  const int v = vox[i];
-  if (v >= 0) count[s.grid_off + v] = 0;
-}
-
 template <bool SUB>
 __global__ void k_expand_flow_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
                                 const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
                                 const int32_t* __restrict__ brick_off,
-                                const float2* __restrict__ rowflow, float2* __restrict__ out,
-                                int32_t* __restrict__ count) {
+                                const float2* __restrict__ rowflow, float2* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x * blockDim.x >= bt.m) return;  // (whole block; launches never do this)
   const SliceDesc s = SUB ? bt.s0 : slice_by_event_block(bt, i);
   if (i >= bt.m) return;
-  clear_count<SUB>(count, s, vox, i);
   const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, i);
   const float nan = __builtin_nanf("");
   out[i] = r >= 0 ? rowflow[r] : make_float2(nan, nan);
@@ -607,13 +593,11 @@ template <bool SUB>
 __global__ void k_expand_emb_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
                                const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
                                const int32_t* __restrict__ brick_off,
-                               const float* __restrict__ rows, int d2, float* __restrict__ out,
-                               int32_t* __restrict__ count) {
+                               const float* __restrict__ rows, int d2, float* __restrict__ out) {
   const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (q >= bt.m) return;
   const SliceDesc s = SUB ? bt.s0 : slice_by_event(bt, (int)q);
-  if (lane == 0) clear_count<SUB>(count, s, vox, (int)q);
   const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, (int)q);
   const float4* src = reinterpret_cast<const float4*>(rows + (int64_t)(r < 0 ? 0 : r) * d2);
   float4* dst = reinterpret_cast<float4*>(out + q * d2);
@@ -665,7 +649,8 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
   hipStream_t s = (hipStream_t)stream;
   // slice calls (not the paper form) find the count grid zero: every such
   // call returns its counts to zero after use (zeroed once at context
-  // creation); the paper form clears it here
+  // creation; the encoder clears them when every event is queried); the
+  // paper form clears it here
   if (!pairs)
     hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
   if (bt.n > 0)
@@ -744,8 +729,7 @@ int launch_take_err(const Workspace& w, int32_t* host, void* stream) {
 }
 
 int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
-                      const Brick& b, bool use_qmap, bool clear, int d, float* emb,
-                      void* stream) {
+                      const Brick& b, bool use_qmap, int d, float* emb, void* stream) {
   if (bt.m <= 0) return VECKM_OK;
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(blocks_for((int64_t)bt.m * 64, 256));
@@ -754,15 +738,15 @@ int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* querie
     hipLaunchKernelGGL(k_expand_emb, grid, dim3(256), 0, s, w.qmap, bt.m, rows, 2 * d, emb);
   else if (queries)
     hipLaunchKernelGGL(k_expand_emb_q<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox, w.rank,
-                       w.brick_off, rows, 2 * d, emb, (int32_t*)nullptr);
+                       w.brick_off, rows, 2 * d, emb);
   else
     hipLaunchKernelGGL(k_expand_emb_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
-                       w.rank, w.brick_off, rows, 2 * d, emb, clear ? w.count : nullptr);
+                       w.rank, w.brick_off, rows, 2 * d, emb);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
 int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
-                       const Brick& b, bool use_qmap, bool clear, float* flow, void* stream) {
+                       const Brick& b, bool use_qmap, float* flow, void* stream) {
   if (bt.m <= 0) return VECKM_OK;
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid(blocks_for(bt.m, 256));
@@ -772,10 +756,10 @@ int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queri
     hipLaunchKernelGGL(k_expand_flow, grid, dim3(256), 0, s, w.qmap, bt.m, rf, out);
   else if (queries)
     hipLaunchKernelGGL(k_expand_flow_q<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
-                       w.rank, w.brick_off, rf, out, (int32_t*)nullptr);
+                       w.rank, w.brick_off, rf, out);
   else
     hipLaunchKernelGGL(k_expand_flow_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
-                       w.rank, w.brick_off, rf, out, clear ? w.count : nullptr);
+                       w.rank, w.brick_off, rf, out);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

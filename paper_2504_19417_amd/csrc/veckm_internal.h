@@ -117,8 +117,9 @@ inline int64_t scan_tiles(int64_t nb) { return (nb + kScanTile - 1) / kScanTile;
 
 struct Workspace {
   int32_t* count = nullptr;     // voxels: int32 event counts, slices back to back; all zero
-                                // between calls (cleared by the output expansion of calls
-                                // that query every event, else filled before the scatter)
+                                // between slice calls (the encoder clears the rows' voxels of
+                                // calls that query every event; a query subset fills it after
+                                // use; the paper form fills it before its scatter)
   uint32_t* pairs = nullptr;    // (W + 1) H T per slice: entry x + 1 of a row holds the fp16
                                 // counts of voxels x and x + 1 of that row, x in [-1, W)
   const uint32_t* zeros = nullptr;  // 64 zero dwords (out-of-grid reads)
@@ -199,21 +200,21 @@ int launch_paper_encode(const Batch& bt, const Workspace& w, const PaperTables& 
 void make_paper_tables(const double* A, int d, int width, int height, int max_bins,
                        std::vector<float>* ttab, std::vector<float>* xtab, std::vector<float>* ytab);
 constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
+// clear: also return every row's voxel count to zero (calls that query every
+// event: their rows are exactly the counted voxels).
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  int num_cus, void* stream);
+                  bool clear, int num_cus, void* stream);
 // Per-query outputs; use_qmap: rows from the query -> row map (paper form),
 // else found from each query's voxel (`queries` as in the call, or NULL).
-// clear: also return the counted voxels' counts to zero (every event queried).
 int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
-                      const Brick& b, bool use_qmap, bool clear, int d, float* emb,
-                      void* stream);
+                      const Brick& b, bool use_qmap, int d, float* emb, void* stream);
 int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int num_cus,
                void* stream);
 // Whether the FP32-form perceptron runs on fp16 hi/lo operand pairs for
 // this shape (W1 fragments fit in registers); else on the fp32 matrix cores.
 bool mlp_rows_split(int d, int hidden);
 int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
-                       const Brick& b, bool use_qmap, bool clear, float* flow, void* stream);
+                       const Brick& b, bool use_qmap, float* flow, void* stream);
 // The count grid of a batch back to zero (after a run that skipped the expansion).
 int launch_clear_counts(const Batch& bt, const Workspace& w, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
