@@ -109,49 +109,121 @@ def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=
     return dict(elapsed=elapsed, lat=lat, stages=stages, rows=rows, flows=flows, tiling=tiling)
 
 
+def host_cpu():
+    """The host's processor model and logical CPU count (lscpu, else /proc)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except Exception:
+            pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def _timed(fn):
+    t = time.perf_counter()
+    fn()
+    return time.perf_counter() - t
+
+
 def cpu_baseline(oracle, w, ev, A, mlp, target_s):
-    """The FP64 oracle (bucketed neighbour search, OpenMP over queries) on a
-    seeded sample of the same slice's queries, sized to ~target_s seconds."""
+    """The FP64 oracle, as it stands, on the host's cores.
+
+    Headline (value): a seeded sample of the same slice's queries, bucketed
+    neighbour search, OpenMP over queries on every available thread, sized to
+    about 0.6 target_s.  Further legs: the same search on one thread; the
+    20k-event workload (346x260x25, D = 64, r = 3/2, perceptron 128-128-2) in
+    full with the bucketed and with the literal quadratic search; and the
+    literal quadratic scan on 1024 queries of this slice."""
     from paper_2504_19417_amd import synth
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    q0 = synth.sample_queries(len(ev), 512, 901)
-    t = time.perf_counter()
-    e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q0, threads=threads)
-    oracle.mlp(e, *mlp, threads=threads)
-    t0 = time.perf_counter() - t
-    m = int(min(len(ev), max(512, 512 * target_s / max(t0, 1e-3))))
-    q = synth.sample_queries(len(ev), m, 902)
-    t = time.perf_counter()
-    e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q, threads=threads)
-    oracle.mlp(e, *mlp, threads=threads)
-    dt = time.perf_counter() - t
+
+    def rate(queries, nthreads, search="bucket", events=ev, A_=A, wl=w, mlp_=mlp):
+        def go():
+            e, _ = oracle.encode(events, A_, wl.rx, wl.ry, wl.rt, queries=queries,
+                                 search=search, threads=nthreads)
+            oracle.mlp(e, *mlp_, threads=nthreads)
+        dt = _timed(go)
+        m = len(events) if queries is None else len(queries)
+        return m, dt
+
+    def sized(nthreads, budget, seed):
+        m0, t0 = rate(synth.sample_queries(len(ev), 512, seed), nthreads)
+        m = int(min(len(ev), max(512, 512 * budget / max(t0, 1e-3))))
+        return rate(synth.sample_queries(len(ev), m, seed + 1), nthreads)
+
+    m, dt = sized(threads, 0.6 * target_s, 901)
+    m1, dt1 = sized(1, 0.15 * target_s, 911)
+    tw = synth.workloads()["tiny"]
+    tev, _, _ = synth.make_slice(tw.slices[0])
+    tA = synth.draw_frequencies(tw.d, tw.rx, tw.ry, tw.rt)
+    tmlp = synth.init_mlp(tw.d, tw.hidden)
+    tb = rate(None, threads, "bucket", tev, tA, tw, tmlp)
+    tq = rate(None, threads, "scan", tev, tA, tw, tmlp)
+    q1k = rate(synth.sample_queries(len(ev), 1024, 921), threads, "scan")
     return {"value": m / dt, "unit": "flows/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the slice's %d queries (seeded), FP64 quadratic adjacency-row "
-                      "encoding with bucketed neighbour search + FP64 perceptron, %.1f s"
-                      % (m, len(ev), dt)}
+                      "encoding with bucketed neighbour search + FP64 perceptron, %d threads, "
+                      "%.1f s" % (m, len(ev), threads, dt),
+            "host": host_cpu(),
+            "legs": {
+                "one_thread_bucketed": {"flows_per_s": m1 / dt1, "queries": m1,
+                                        "seconds": round(dt1, 2), "threads": 1},
+                "tiny_full_bucketed": {"flows_per_s": tb[0] / tb[1], "queries": tb[0],
+                                       "seconds": round(tb[1], 3), "threads": threads},
+                "tiny_full_quadratic": {"flows_per_s": tq[0] / tq[1], "queries": tq[0],
+                                        "seconds": round(tq[1], 3), "threads": threads},
+                "slice_quadratic_1024": {"flows_per_s": q1k[0] / q1k[1], "queries": q1k[0],
+                                         "seconds": round(q1k[1], 2), "threads": threads,
+                                         "extrapolated_full_slice_s":
+                                             round(q1k[1] * len(ev) / q1k[0], 1)}}}
 
 
 def sampled_error(oracle, w, ev, A, mlp, flows, seed=903, count=2048):
+    """Flow error against the FP64 oracle on `count` seeded events: relative
+    L2 over the sample, the largest absolute error, and the 99.9th percentile
+    of the per-event relative error."""
     from paper_2504_19417_amd import synth
     q = synth.sample_queries(len(ev), count, seed)
     e, _ = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q)
     ref = oracle.mlp(e, *mlp)
     got = flows[q].astype(np.float64)
-    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    d = np.linalg.norm(got - ref, axis=1)
+    return {"flow_relL2_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "flow_maxabs_sampled": float(np.abs(got - ref).max()),
+            "flow_row_rel_p999": float(np.percentile(d / np.maximum(np.linalg.norm(ref, axis=1),
+                                                                    1e-300), 99.9)),
+            "sampled_events": int(count)}
 
 
-def serving_run(vk, seconds, pool=3):
+def serving_run(vk, seconds, pool=3, scale=1.0):
     """The serving workload: 32 streams (346x260 or 1280x720, Poisson event
-    rates 0.5-10 Mev/s, slice windows 1-20 ms, D = 128, r = 5/3, BF16
-    perceptron 256-256-2) replayed in real time for `seconds`: each stream's
-    thread submits a slice every window (cycling over `pool` pre-generated
-    slices) and polls its previous one.  Latency is measured by the server
-    from submit to completion; flows/s is completed flows over the span from
-    the first submit to the last completion."""
+    rates 0.5-10 Mev/s times `scale`, slice windows 1-20 ms, D = 128,
+    r = 5/3, BF16 perceptron 256-256-2) replayed in real time for `seconds`:
+    each stream's thread submits a slice every window (cycling over `pool`
+    pre-generated slices) and polls its previous one.  Latency is measured by
+    the server from submit to completion, overall and per sensor class;
+    flows/s is completed flows over the span from the first submit to the
+    last completion."""
+    import dataclasses
     import threading
     from paper_2504_19417_amd import synth
     w = synth.workloads()["slice1m"]
-    specs = synth.serving_streams()
+    specs = [dataclasses.replace(sp, rate_mev_s=sp.rate_mev_s * scale)
+             for sp in synth.serving_streams()]
     slices = [synth.stream_slices(sp, pool) for sp in specs]
     A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
     mlp = synth.init_mlp(w.d, w.hidden)
@@ -201,19 +273,39 @@ def serving_run(vk, seconds, pool=3):
         t.start()
     for t in th:
         t.join()
+    classes = {}
+    for W, H in sorted({(sp.width, sp.height) for sp in specs}):
+        c = srv.stats_sensor(W, H)
+        classes["%dx%d" % (W, H)] = {
+            "streams": sum(1 for sp in specs if (sp.width, sp.height) == (W, H)),
+            "slices": c["slices"], "p50_ms": round(c["p50_ms"], 3),
+            "p99_ms": round(c["p99_ms"], 3), "max_ms": round(c["max_ms"], 3)}
     st = srv.stats()
     for sid in sids:
         srv.close_stream(sid)
     srv.close()
     if errors:
         raise RuntimeError("serving errors: %s" % sorted(set(errors)))
-    return {"streams": len(specs), "offered_mev_s": round(sum(sp.rate_mev_s for sp in specs), 1),
+    # offered event rate of the replayed slices (Mev/s)
+    offered = sum(np.mean([len(e) for e, _, _ in sl]) / (sp.window_ms * 1e-3)
+                  for sp, sl in zip(specs, slices)) / 1e6
+    return {"streams": len(specs), "rate_scale": scale,
+            "offered_mev_s": round(float(offered), 1),
             "seconds": seconds, "slices": st["slices"], "batches": st["batches"],
             "flows_per_s": st["flows"] / st["busy_s"] if st["busy_s"] > 0 else None,
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-            "max_ms": round(st["max_ms"], 3),
+            "max_ms": round(st["max_ms"], 3), "per_sensor": classes}
+
+
+def serving_sweep(vk, seconds, scales=(0.5, 1.0, 2.0)):
+    """The serving replay at x0.5, x1 and x2 of the stream rates: where the
+    served rate stops tracking the offered rate the server is saturated."""
+    pts = [serving_run(vk, seconds, scale=f) for f in scales]
+    return {"points": pts,
             "latency": "submit to completion (host copies and device work included)",
-            "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation"}
+            "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
+            "served_over_offered": [round(p["flows_per_s"] / (p["offered_mev_s"] * 1e6), 3)
+                                    if p["flows_per_s"] else None for p in pts]}
 
 
 KERNEL_SOURCES = {  # kernel name prefix (template form) -> source file it is built from
@@ -324,10 +416,40 @@ PROFILE_NOTES["batch64"] = (
     "serve both forms and the tuner runs.")
 
 
+KERNELS_JSON = os.path.join(ROOT, "profiles", "kernels.json")
+
+
+def record_kernel_times(rows, workload):
+    """Keeps the rocprofv3 average duration of the hot kernels of `workload`
+    (with the hash of their source) in profiles/kernels.json."""
+    rec = json.load(open(KERNELS_JSON)) if os.path.exists(KERNELS_JSON) else {}
+    out = {}
+    for r in rows:
+        for short, src in KERNEL_SOURCES.items():
+            if ("veckm::%s" % short) in r["Name"] and short not in out:
+                out[short] = {"kernel": r["Name"], "calls": int(r["Calls"]),
+                              "avg_us": round(float(r["AverageNs"]) / 1e3, 2),
+                              "source": src, "source_sha": source_sha(src)}
+    rec[workload] = out
+    with open(KERNELS_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+
+
+def profiled_ms(workload, kernel):
+    """The committed rocprofv3 average of `kernel` (ms) on `workload`, if it
+    was taken on the current source; else None."""
+    try:
+        r = json.load(open(KERNELS_JSON))[workload][kernel]
+        return r["avg_us"] / 1e3 if source_sha(r["source"]) == r["source_sha"] else None
+    except Exception:
+        return None
+
+
 def summarize_kernels(stats_dir, command, workload="slice1m"):
     """Markdown summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
     rows = list(csv.DictReader(open(_find_csv(stats_dir, "kernel_stats.csv"))))
+    record_kernel_times(rows, workload)
     out = ["# Kernel times: " + PROFILE_WORKLOADS[workload], "",
            "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
     out += ["    " + c for c in command.split(" ; ")]
@@ -448,10 +570,10 @@ def paper_main(args, name):
                    "d": w.d, "radius_xy": w.rx, "radius_t": "none (whole slice)",
                    "delta_t_bins": T / 2, "hidden": w.hidden, "queries": "all events"},
         "stages_ms": st32,
-        "err_vs_oracle": {"flow_relL2_sampled": err32},
+        "err_vs_oracle": err32,
         "fp16_bf16": {"value": n * args.steps / res["fp16"]["elapsed"],
                       "ms_per_step": round(res["fp16"]["elapsed"] / args.steps * 1e3, 4),
-                      "stages_ms": st16, "err_vs_oracle": {"flow_relL2_sampled": err16},
+                      "stages_ms": st16, "err_vs_oracle": err16,
                       "dtype": "fp32 encoder, bf16 perceptron"},
         "worked_example_10k_flows": {"ms_per_call": round(ms_sparse, 4),
                                      "stages_ms": stages(sparse),
@@ -678,12 +800,12 @@ def precision_main(args):
                    "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
                    "queries": "all events", "tiling_brick_slabs": res["fp16"]["tiling"]},
         "stages_ms": st16, "rows": rows,
-        "err_vs_oracle": {"flow_relL2_sampled": err16},
+        "err_vs_oracle": err16,
         "flow_relL2_vs_fp32_form": vs32,
         "fp32": {"value": n * args.steps / res["fp32"]["elapsed"],
                  "ms_per_step": round(res["fp32"]["elapsed"] / args.steps * 1e3, 4),
                  "stages_ms": st32, "tiling_brick_slabs": res["fp32"]["tiling"],
-                 "err_vs_oracle": {"flow_relL2_sampled": err32}},
+                 "err_vs_oracle": err32},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                      "peak": PEAK["fp16_TFLOPs"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK["fp16_TFLOPs"], 4), "traffic": None,
@@ -859,11 +981,17 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / c["peak"], 4),
                 "traffic": load_traffic(c["kernel"]), "kernel": c["kernel"],
                 "avg_launch_ms": round(c["ms"], 4), "rows_per_launch": rows,
-                "flops_per_row": c["flops"] // rows}
+                "flops_per_row": c["flops"] // rows,
+                "clock": "HIP events around the kernel's launch on its stream"}
+    # the same figure from the committed rocprofv3 kernel trace of this source
+    pms = profiled_ms("slice1m", c["kernel"])
+    if pms:
+        roofline["rocprof_avg_ms"] = round(pms, 4)
+        roofline["rocprof_frac"] = round(c["flops"] / (pms * 1e-3) / 1e12 / c["peak"], 4)
 
     err32 = sampled_error(oracle, w, ev, A, mlp, res["fp32"]["flows"])
     err16 = sampled_error(oracle, w, ev, A, mlp, res["fp16"]["flows"])
-    serving = serving_run(vk, args.serving_seconds) if args.serving_seconds > 0 else None
+    serving = serving_sweep(vk, args.serving_seconds) if args.serving_seconds > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, w, ev, A, mlp, args.cpu_seconds)
 
     def lat(r):
@@ -888,14 +1016,14 @@ def main():
                    "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
                    "queries": "all events"},
         "latency_ms": lat(res["fp32"]),
-        "err_vs_oracle": {"flow_relL2_sampled": err32},
+        "err_vs_oracle": err32,
         "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st32.items()},
         "fp16_bf16": {
             "value": n * args.steps / res["fp16"]["elapsed"],
             "ms_per_step": round(ms16, 4),
             "latency_ms": lat(res["fp16"]),
             "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st16.items()},
-            "err_vs_oracle": {"flow_relL2_sampled": err16},
+            "err_vs_oracle": err16,
             "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
         },
         "sparse_10k_queries": None if sparse is None else {

@@ -173,6 +173,18 @@ int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
                int32_t nbins, const int32_t* queries, int64_t m, float* flow,
                void* stream);
 
+/* The neighbour count of each queried event, as the encoder computes it for
+   its normalisation (Eqn. 17; Algorithm 1 final step): the number of events
+   k of the slice with |x_k - x_q| <= rx, |y_k - y_q| <= ry and
+   |t_k - t_q| <= rt, the query itself included.  Same arguments, limits and
+   errors as veckm_encode; counts is device m x int32 (-1 for a query whose
+   event broke the conventions, reported by veckm_status).  The count is
+   exact (integer pair sums summed exactly in fp32).  Returns VECKM_E_INVAL
+   for a window or rt = -1 context. */
+int veckm_count(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                int32_t nbins, const int32_t* queries, int64_t m, int32_t* counts,
+                void* stream);
+
 /* Batch forms: one launch sequence for `count` slices (1 <= count <=
    max_slices).  Every event of every slice is queried; outputs follow the
    event order (emb: device, total n x 2D float32; flow: device, total n x 2
@@ -219,15 +231,18 @@ void veckm_graph_destroy(veckm_graph* graph);
    The encoder cuts every slice into bricks of voxels and streams the phase
    table through LDS a few slabs deep (the count box of a brick and the slabs
    share the 160 KB of LDS).  A context offers a small set of tilings (brick
-   shape x buffered slabs): index 0 is the default (the largest brick that
-   fits beside two slabs, as many slabs as fit), the others larger bricks
-   with fewer slabs, which pay off where bricks hold few query voxels
-   (sparse slices).  Results do not depend on the tiling (bit-identical);
+   shape x buffered slabs x wave layout): index 0 is the default (the largest
+   brick that fits beside two slabs, as many slabs as fit), the others larger
+   bricks with fewer slabs, which pay off where bricks hold few query voxels
+   (sparse slices), and each of those with fewer, wider waves.  Results do not depend on the tiling (bit-identical);
    only the time does.
      veckm_tiling_count     number of tilings (>= 1), or VECKM_E_INVAL
      veckm_tiling_selected  index in use, or VECKM_E_INVAL
-     veckm_tiling_info      info[0..3] = brick x, y, t sides and slabs of
-                            tiling `index` (host int32[4])
+     veckm_tiling_info      info[0..4] = brick x, y, t sides, slabs and wave
+                            layout (0: 16 waves of 2 row tiles; 1: 8 waves
+                            of 4 row tiles, each table fragment feeding
+                            twice the products) of tiling `index` (host
+                            int32[5])
      veckm_tiling_select    use tiling `index` from the next call on
      veckm_tune             times every tiling on the given batch (as for
                             veckm_encode_batch: the front end and the encoder,
@@ -354,26 +369,33 @@ int veckm_last_rows(veckm_ctx* ctx, void* stream, int64_t* rows);
 /* ---- serving: asynchronous event streams, continuously batched -------------
 
    A server owns one context (sized by `params`: the largest sensor, bins and
-   batch it will run), a HIP stream of its own, and two native threads: a
-   launcher that packs every waiting slice that fits into one batch call
-   (veckm_flow_batch) as soon as fewer than two batches are on the device, and
-   a completer that waits for each batch, stamps its slices' completion time
-   and wakes the pollers.  Slices that arrive while a batch runs go into the
-   next one, so work from different streams overlaps on the device; a slice's
-   result does not depend on which other slices share its batch (bit-identical
-   to veckm_flow on that slice alone).
+   batch it will run), three HIP streams of its own (events in, kernels,
+   flows out) and two native threads: a launcher that packs waiting slices,
+   at most one per stream, into one batch call (veckm_flow_batch) whenever
+   one of two device lanes is free, and a completer that waits for each
+   batch, stamps its slices' completion time and wakes the pollers.  Each
+   lane has its own device event and flow buffers, so the host-to-device copy
+   of one batch overlaps the kernels of the other.  Slices that arrive while
+   a batch runs go into the next one, so work from different streams
+   overlaps on the device; a slice's result does not depend on which other
+   slices share its batch (bit-identical to veckm_flow on that slice alone).
 
-   Admission by HBM budget: the server's device memory (context workspaces,
-   phase table, perceptron, batch input/output buffers) must fit in
-   hbm_budget_bytes at create time, and every open stream reserves its share
-   of one batch (W*H*max_bins voxels and max_events events): veckm_stream_open
-   returns VECKM_E_BUDGET when the open streams' shares would exceed the batch
-   capacity, so one waiting slice of every admitted stream always fits into a
-   batch.  Batches take waiting slices in submission order while they fit.
-   Closing a stream releases its share.
+   Resident grids and admission by HBM budget: every open stream keeps its
+   own count and pair grids (W*H*max_bins voxels, 8-9 bytes each) resident on
+   the device for as long as it is open; each of its slices is counted into
+   that region and leaves it clean for the next.  The regions come from a
+   grid arena of params->max_voxels voxels (0: room for max_streams streams
+   at the largest sensor and bins).  The server's device memory (the arena,
+   the batch workspaces, phase table, perceptron, two lanes of event and flow
+   buffers) must fit in hbm_budget_bytes at create time, and
+   veckm_stream_open returns VECKM_E_BUDGET when the stream's grids do not
+   fit in what is left of the arena, or when the open streams' events would
+   exceed one batch (so one waiting slice of every admitted stream always
+   fits into a batch).  Batches take waiting slices in submission order
+   while they fit.  Closing a stream returns its grids to the arena.
 
    Threading: veckm_submit, veckm_poll, veckm_stream_open/close and
-   veckm_server_stats may be called from any threads concurrently.
+   veckm_server_stats(_sensor) may be called from any threads concurrently.
    veckm_server_destroy must not race with other calls on the server. */
 typedef struct veckm_server veckm_server;
 
@@ -437,6 +459,13 @@ typedef struct veckm_serving_stats {
 } veckm_serving_stats;
 
 int veckm_server_stats(veckm_server* server, veckm_serving_stats* out, int32_t reset);
+
+/* As veckm_server_stats (without a reset), with slices, p50, p99 and max
+   over the slices of streams whose sensor is width x height only (a sensor
+   class); flows, batches and busy_s are the server's totals.
+   VECKM_E_INVAL for a non-positive size. */
+int veckm_server_stats_sensor(veckm_server* server, int32_t width, int32_t height,
+                              veckm_serving_stats* out);
 
 #ifdef __cplusplus
 }

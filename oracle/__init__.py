@@ -8,15 +8,17 @@ Contents
     quadratic adjacency-row encoding (Eqn. 10 over the neighbourhood of
     Eqn. 1, normalised by the count of Eqn. 17) and the two-layer perceptron
     (Eqns. 5-6), in FP64.
-  * ``alg1_paper_form`` -- Algorithm 1 as the paper states it: a 2-D
-    PixelEmbed/PixelCount grid filled with temporal phases (Eqns. 14-15),
-    pooled over the spatial window with the precomputed spatial offset
-    phases (Eqn. 16, count of Eqn. 17), then multiplied by the conjugate
-    temporal phase of the query and divided by the count.  No temporal
-    bound, as in Eqn. 1.
+  * ``alg1_paper_form`` -- the staged 2-D form of Sec. 2.2.2 (Eqns.
+    14-17): a per-pixel grid of summed temporal phases and event counts,
+    pooled over the spatial window with the spatial offset phases, then
+    turned back by the conjugate temporal phase of the query and divided by
+    the count.  No temporal bound, as in Eqn. 1.
   * ``pooling_form_3d`` -- the same pooling idea generalised to a temporal
     radius: a 3-D (x, y, t) count grid pooled with (dx, dy, dt) offset
     phases.
+  * ``box_count`` -- the windowed neighbour count of Eqn. 17 alone, exact
+    in integers, from a summed-volume table of the event histogram (cheap
+    enough for every event of the largest slices).
 
 These two numpy routines are independent routes to the same numbers and
 are used to pin the C oracle (they share no code with it).
@@ -140,43 +142,73 @@ def flow(events, A, rx, ry, rt, W1, b1, W2, b2, queries=None, search="bucket", t
 
 
 def alg1_paper_form(events, A, rx, ry, queries=None):
-    """Algorithm 1 in numpy (no temporal bound), FP64.
+    """The staged 2-D form of Sec. 2.2.2 (no temporal bound), FP64.
 
-    Per pixel: PixelEmbed[x, y, :] = sum of exp(i * A_t * t_k) over its
-    events, PixelCount[x, y] = number of events (Eqns. 14-15).  Per query:
-    pool PixelEmbed over the window with the precomputed spatial offset
-    phases exp(i (A_x dx + A_y dy)), pool the counts (Eqns. 16-17), then
-    multiply by exp(-i A_t t_q) and divide by the count.  Time is measured
-    from the earliest event, a constant shift that cancels between the
-    scattered and the conjugate temporal phase."""
+    Eqns. 14-15: a per-pixel grid holding, for each pixel p, the sum of the
+    temporal phases exp(i A_t t_k) of its events (PixelEmbed) and their
+    number (PixelCount).  Eqns. 16-17: for a query at pixel q, the window sum
+    over spatial offsets o of PixelEmbed(q + o) times the spatial offset
+    phase exp(i (A_x o_x + A_y o_y)), and the window count.  The query's own
+    temporal phase is then removed (conjugate factor) and the sum divided by
+    the count.  Time is measured from the earliest event: a constant shift
+    that cancels between the two temporal phases.  Evaluated offset by
+    offset over all queries at once (grid padded by the radii)."""
     ev = np.asarray(events, dtype=np.int64)
     A = np.asarray(A, dtype=np.float64)
-    x, y, t = ev[:, 0], ev[:, 1], ev[:, 2] - ev[:, 2].min()
-    x0, y0 = x.min() - rx, y.min() - ry
-    gx, gy = x - x0, y - y0
-    Wg, Hg = gx.max() + rx + 1, gy.max() + ry + 1
     D = A.shape[0]
-    embed = np.zeros((Wg, Hg, D), dtype=np.complex128)
-    count = np.zeros((Wg, Hg), dtype=np.int64)
-    temporal = np.exp(1j * np.outer(t.astype(np.float64), A[:, 2]))      # [n, D]
-    for k in range(len(ev)):                                              # scatter
-        embed[gx[k], gy[k]] += temporal[k]
-        count[gx[k], gy[k]] += 1
-    offs = [(dx, dy) for dx in range(-rx, rx + 1) for dy in range(-ry, ry + 1)]
-    table = {o: np.exp(1j * (A[:, 0] * o[0] + A[:, 1] * o[1])) for o in offs}  # precomputed
-    qs = np.arange(len(ev)) if queries is None else np.asarray(queries)
-    out = np.zeros((len(qs), 2 * D))
+    qs = np.arange(len(ev)) if queries is None else np.asarray(queries, dtype=np.int64)
+    # pixel coordinates inside a grid padded by the window radii
+    px = ev[:, 0] - ev[:, 0].min() + rx
+    py = ev[:, 1] - ev[:, 1].min() + ry
+    tt = (ev[:, 2] - ev[:, 2].min()).astype(np.float64)
+    GW, GH = int(px.max()) + rx + 1, int(py.max()) + ry + 1
+    flat = py * GW + px
+    tphase = np.exp(1j * tt[:, None] * A[None, :, 2])                 # [n, D]
+    pix_embed = np.zeros((GH * GW, D), dtype=np.complex128)
+    np.add.at(pix_embed, flat, tphase)                               # Eqn. 14
+    pix_count = np.bincount(flat, minlength=GH * GW)                 # Eqn. 15
+    dxs = np.arange(-rx, rx + 1)
+    dys = np.arange(-ry, ry + 1)
+    # spatial offset phases, [2ry+1, 2rx+1, D]
+    ophase = np.exp(1j * (dys[:, None, None] * A[None, None, :, 1] +
+                          dxs[None, :, None] * A[None, None, :, 0]))
+    qflat = flat[qs]
+    acc = np.zeros((len(qs), D), dtype=np.complex128)
     cnt = np.zeros(len(qs), dtype=np.int64)
-    for i, q in enumerate(qs):
-        e = np.zeros(D, dtype=np.complex128)
-        c = 0
-        for (dx, dy) in offs:
-            c += count[gx[q] + dx, gy[q] + dy]
-            e += embed[gx[q] + dx, gy[q] + dy] * table[(dx, dy)]
-        e = e * np.exp(-1j * t[q] * A[:, 2]) / c
-        out[i, :D], out[i, D:] = e.real, e.imag
-        cnt[i] = c
-    return out, cnt
+    for iy, dy in enumerate(dys):                                    # Eqns. 16-17
+        for ix, dx in enumerate(dxs):
+            nb = qflat + dy * GW + dx
+            acc += pix_embed[nb] * ophase[iy, ix][None, :]
+            cnt += pix_count[nb]
+    emb = acc * np.conj(tphase[qs]) / cnt[:, None]
+    return np.concatenate([emb.real, emb.imag], axis=1), cnt
+
+
+def box_count(events, rx, ry, rt, queries=None):
+    """Windowed neighbour count of Eqn. 17 for every queried event, exact.
+
+    N(q) = number of events k with |x_k - x_q| <= rx, |y_k - y_q| <= ry and
+    |t_k - t_q| <= rt (rt < 0: no temporal bound, Eqn. 1 as written), the
+    query included.  Computed as a box sum of the integer event histogram
+    over (t, y, x) voxels, read off a summed-volume table (inclusion-exclusion
+    over the 8 corners of the clipped box).  int64[m]."""
+    ev = np.asarray(events, dtype=np.int64)
+    if len(ev) == 0:
+        return np.zeros(0, dtype=np.int64)
+    x, y, t = ev[:, 0] - ev[:, 0].min(), ev[:, 1] - ev[:, 1].min(), ev[:, 2] - ev[:, 2].min()
+    W, H, T = int(x.max()) + 1, int(y.max()) + 1, int(t.max()) + 1
+    if rt < 0:
+        rt = T
+    hist = np.zeros((T, H, W), dtype=np.int64)
+    np.add.at(hist, (t, y, x), 1)
+    sv = np.zeros((T + 1, H + 1, W + 1), dtype=np.int64)   # sv[a, b, c] = hist[:a, :b, :c].sum()
+    sv[1:, 1:, 1:] = hist.cumsum(0).cumsum(1).cumsum(2)
+    qs = np.arange(len(ev)) if queries is None else np.asarray(queries, dtype=np.int64)
+    t0, t1 = np.maximum(t[qs] - rt, 0), np.minimum(t[qs] + rt + 1, T)
+    y0, y1 = np.maximum(y[qs] - ry, 0), np.minimum(y[qs] + ry + 1, H)
+    x0, x1 = np.maximum(x[qs] - rx, 0), np.minimum(x[qs] + rx + 1, W)
+    return (sv[t1, y1, x1] - sv[t0, y1, x1] - sv[t1, y0, x1] - sv[t1, y1, x0]
+            + sv[t0, y0, x1] + sv[t0, y1, x0] + sv[t1, y0, x0] - sv[t0, y0, x0])
 
 
 def pooling_form_3d(events, A, rx, ry, rt, queries=None):

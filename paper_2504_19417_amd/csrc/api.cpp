@@ -201,11 +201,16 @@ int single_batch(const veckm_ctx* c, const veckm_event* ev, int64_t n, int32_t t
 }
 
 // A batch of slices: validate and describe them (bt->table is left unset).
+// Grids lie back to back, or, when `at` is given, slice k's count grid starts
+// at voxel at[2k] and its pair grid at entry at[2k + 1] (regions a server
+// keeps for its streams; they must not overlap).
 int plan_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
-               const void* out, std::vector<SliceDesc>& tab, Batch* bt) {
+               const void* out, std::vector<SliceDesc>& tab, Batch* bt,
+               const int64_t* at = nullptr) {
   if (!sl || count < 1 || count > c->max_slices) return VECKM_E_INVAL;
   tab.assign((size_t)count, SliceDesc{});
-  int64_t evs = 0, vox = 0, prs = 0, bricks = 0, max_rows = 0;
+  int64_t evs = 0, vox = 0, prs = 0, bricks = 0, max_rows = 0, vend = 0, pend = 0;
+  std::vector<std::pair<int64_t, int64_t>> vreg, preg;
   for (int k = 0; k < count; ++k) {
     const veckm_slice& s = sl[k];
     if (s.n < 0 || s.offset != evs) return VECKM_E_INVAL;
@@ -213,16 +218,33 @@ int plan_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_e
     if (s.width < 1 || s.height < 1 || s.width > c->p.width || s.height > c->p.height)
       return VECKM_E_RANGE;
     if (s.nbins < 1 || s.nbins > c->p.max_bins) return VECKM_E_RANGE;
-    tab[k] = describe(c, s.width, s.height, s.nbins, s.t0, bricks, vox, prs, evs, s.n);
+    const int64_t V = (int64_t)s.width * s.height * s.nbins;
+    const int64_t P = (int64_t)(s.width + 1) * s.height * s.nbins;
+    const int64_t go = at ? at[2 * k] : vox, po = at ? at[2 * k + 1] : prs;
+    if (go < 0 || po < 0) return VECKM_E_INVAL;
+    tab[k] = describe(c, s.width, s.height, s.nbins, s.t0, bricks, go, po, evs, s.n);
     evs += s.n;
-    vox += (int64_t)s.width * s.height * s.nbins;
-    prs += (int64_t)(s.width + 1) * s.height * s.nbins;
+    vox += V;
+    prs += P;
+    vend = std::max(vend, go + V);
+    pend = std::max(pend, po + P);
+    if (at) {
+      vreg.push_back({go, go + V});
+      preg.push_back({po, po + P});
+    }
     max_rows = std::max(max_rows, (int64_t)s.height * s.nbins);
     bricks += bricks_of(s.width, s.height, s.nbins, c->et.brick);
   }
-  if (vox > c->w.vmax || prs > c->w.pmax || bricks > c->w.bmax ||
+  for (auto* reg : {&vreg, &preg}) {
+    std::sort(reg->begin(), reg->end());
+    for (size_t i = 1; i < reg->size(); ++i)
+      if ((*reg)[i].first < (*reg)[i - 1].second) return VECKM_E_INVAL;
+  }
+  if (vend > c->w.vmax || pend > c->w.pmax || bricks > c->w.bmax ||
       bricks * c->et.brick.volume() > c->w.umax)
     return VECKM_E_RANGE;
+  vox = vend;  // the extent the batch's grids span (cleared on failed runs)
+  prs = pend;
   if (evs > 0 && (!ev || !out)) return VECKM_E_INVAL;
   bt->s0 = tab[0];
   bt->table = nullptr;
@@ -239,10 +261,10 @@ int plan_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_e
 // A batch of slices: validate, describe, and upload the slice table through
 // the next ring slot (*slot, released by release_slot after the launches).
 int multi_batch(veckm_ctx* c, const veckm_slice* sl, int32_t count, const veckm_event* ev,
-                const void* out, void* stream, Batch* bt, int* slot) {
+                const void* out, void* stream, Batch* bt, int* slot, const int64_t* at = nullptr) {
   *slot = -1;
   std::vector<SliceDesc> tab;
-  const int rc = plan_batch(c, sl, count, ev, out, tab, bt);
+  const int rc = plan_batch(c, sl, count, ev, out, tab, bt, at);
   if (rc) return rc;
   const int k = c->ring_next;
   if (c->ring_used[k] && hipEventSynchronize(c->ring_ev[k]) != hipSuccess) return VECKM_E_HIP;
@@ -287,9 +309,12 @@ struct StageTimer {
 };
 
 // The launch sequence of one call: `emb` for encode calls, `flow` for flow
-// calls (exactly one is non-NULL).
-int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* queries, float* emb,
-        float* flow, void* stream) {
+// calls, `counts` for count calls (exactly one is non-NULL), on the
+// workspaces `w` (the context's own, or the allocation-free entry point's
+// static ones).
+int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev,
+        const int32_t* queries, float* emb, float* flow, void* stream,
+        int32_t* counts = nullptr) {
   // a window's encode: ev holds the query events, the counts are resident
   if (bt.m == 0) return VECKM_OK;
   // rows the encoder hands to the perceptron (encodings handed out are fp32)
@@ -306,10 +331,10 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
   const bool clear = !c->paper && !c->window;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
-    const int rc = c->window ? launch_window_prepare(bt, c->w, ev, c->et, stream)
-                             : launch_prepare(bt, c->w, ev, queries, c->et, !c->paper, stream);
+    const int rc = c->window ? launch_window_prepare(bt, w, ev, c->et, stream)
+                             : launch_prepare(bt, w, ev, queries, c->et, !c->paper, stream);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      if (clear) (void)launch_clear_counts(bt, w, stream);
       return rc;
     }
   }
@@ -317,29 +342,32 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
     // the encoder writes fp32 rows unless the perceptron takes bf16 or hi/lo rows
     const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 ? rows : kRowsF32;
-    const int rc = c->paper ? launch_paper_encode(bt, c->w, c->pt, c->et.brick, erows, c->num_cus, stream)
-                            : launch_encode(bt, c->w, c->et, erows, clear && !queries,
-                                            c->num_cus, stream);
+    const int rc = c->paper ? launch_paper_encode(bt, w, c->pt, c->et.brick, erows, c->num_cus, stream)
+                            : launch_encode(bt, w, c->et, erows, clear && !queries,
+                                            c->num_cus, stream,
+                                            counts ? reinterpret_cast<int32_t*>(w.rowflow)
+                                                   : nullptr);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      if (clear) (void)launch_clear_counts(bt, w, stream);
       return rc;
     }
   }
   if (flow) {
     StageTimer t(c, VECKM_STAGE_MLP, stream);
-    const int rc = launch_mlp(c->w, c->mw, c->p.d, rows, c->num_cus, stream);
+    const int rc = launch_mlp(w, c->mw, c->p.d, rows, c->num_cus, stream);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, c->w, stream);
+      if (clear) (void)launch_clear_counts(bt, w, stream);
       return rc;
     }
   }
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
   // (a window's queries are the query events themselves: index i is event i)
   const int32_t* q = c->window ? nullptr : queries;
-  int rc = flow ? launch_expand_flow(bt, c->w, q, c->et.brick, c->paper, flow, stream)
-                : launch_expand_emb(bt, c->w, q, c->et.brick, c->paper, c->p.d, emb, stream);
+  int rc = flow     ? launch_expand_flow(bt, w, q, c->et.brick, c->paper, flow, stream)
+           : counts ? launch_expand_count(bt, w, q, c->et.brick, counts, stream)
+                    : launch_expand_emb(bt, w, q, c->et.brick, c->paper, c->p.d, emb, stream);
   if (clear && (q || rc)) {
-    const int rc2 = launch_clear_counts(bt, c->w, stream);
+    const int rc2 = launch_clear_counts(bt, w, stream);
     rc = rc ? rc : rc2;
   }
   return rc;
@@ -348,6 +376,19 @@ int run(veckm_ctx* c, const Batch& bt, const veckm_event* ev, const int32_t* que
 }  // namespace
 
 namespace veckm {
+
+int flow_batch_at(veckm_ctx* c, const veckm_slice* slices, int32_t count, const int64_t* at,
+                  const veckm_event* events, float* flow, void* stream) {
+  if (!c || c->paper || c->window || !at) return VECKM_E_INVAL;
+  if (c->mw.hidden == 0) return VECKM_E_STATE;
+  Batch bt;
+  int slot;
+  int rc = multi_batch(c, slices, count, events, flow, stream, &bt, &slot, at);
+  if (rc) return rc;
+  rc = run(c, c->w, bt, events, nullptr, nullptr, flow, stream);
+  const int rc2 = release_slot(c, slot, stream);
+  return rc ? rc : rc2;
+}
 
 Capacity ctx_capacity(const veckm_ctx* c) {
   Capacity k;
@@ -557,6 +598,7 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     EncodeTables t = et;
     t.brick = tl[i].brick;
     t.nbuf = tl[i].nbuf;
+    t.layout = tl[i].layout;
     t.runs = druns[i];
     c->tilings.push_back(t);
   }
@@ -638,7 +680,7 @@ int veckm_encode(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t
   Batch bt;
   const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, emb, &bt);
   if (rc) return rc;
-  return run(ctx, bt, events, queries, emb, nullptr, stream);
+  return run(ctx, ctx->w, bt, events, queries, emb, nullptr, stream);
 }
 
 int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
@@ -648,7 +690,17 @@ int veckm_flow(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
   const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, flow, &bt);
   if (rc) return rc;
   if (ctx->mw.hidden == 0) return VECKM_E_STATE;
-  return run(ctx, bt, events, queries, nullptr, flow, stream);
+  return run(ctx, ctx->w, bt, events, queries, nullptr, flow, stream);
+}
+
+int veckm_count(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                int32_t nbins, const int32_t* queries, int64_t m, int32_t* counts,
+                void* stream) {
+  if (!ctx || ctx->window || ctx->paper) return VECKM_E_INVAL;
+  Batch bt;
+  const int rc = single_batch(ctx, events, n, t0, nbins, queries, m, counts, &bt);
+  if (rc) return rc;
+  return run(ctx, ctx->w, bt, events, queries, nullptr, nullptr, stream, counts);
 }
 
 // ---- sliding window ------------------------------------------------------
@@ -724,7 +776,7 @@ int veckm_window_encode(veckm_ctx* ctx, const veckm_event* queries, int64_t m, f
   Batch bt;
   const int rc = window_batch(ctx, queries, m, emb, &bt);
   if (rc) return rc;
-  return run(ctx, bt, queries, nullptr, emb, nullptr, stream);
+  return run(ctx, ctx->w, bt, queries, nullptr, emb, nullptr, stream);
 }
 
 int veckm_window_flow(veckm_ctx* ctx, const veckm_event* queries, int64_t m, float* flow,
@@ -733,7 +785,7 @@ int veckm_window_flow(veckm_ctx* ctx, const veckm_event* queries, int64_t m, flo
   const int rc = window_batch(ctx, queries, m, flow, &bt);
   if (rc) return rc;
   if (ctx->mw.hidden == 0) return VECKM_E_STATE;
-  return run(ctx, bt, queries, nullptr, nullptr, flow, stream);
+  return run(ctx, ctx->w, bt, queries, nullptr, nullptr, flow, stream);
 }
 
 int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
@@ -743,7 +795,7 @@ int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
   int slot;
   int rc = multi_batch(ctx, slices, count, events, emb, stream, &bt, &slot);
   if (rc) return rc;
-  rc = run(ctx, bt, events, nullptr, emb, nullptr, stream);
+  rc = run(ctx, ctx->w, bt, events, nullptr, emb, nullptr, stream);
   const int rc2 = release_slot(ctx, slot, stream);
   return rc ? rc : rc2;
 }
@@ -756,7 +808,7 @@ int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
   int slot;
   int rc = multi_batch(ctx, slices, count, events, flow, stream, &bt, &slot);
   if (rc) return rc;
-  rc = run(ctx, bt, events, nullptr, nullptr, flow, stream);
+  rc = run(ctx, ctx->w, bt, events, nullptr, nullptr, flow, stream);
   const int rc2 = release_slot(ctx, slot, stream);
   return rc ? rc : rc2;
 }
@@ -813,7 +865,7 @@ int veckm_graph_create(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
   ctx->prof = false;
   rc = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess ? VECKM_OK : VECKM_E_HIP;
   if (!rc) {
-    rc = run(ctx, bt, events, nullptr, flow ? nullptr : out, flow ? out : nullptr, s);
+    rc = run(ctx, ctx->w, bt, events, nullptr, flow ? nullptr : out, flow ? out : nullptr, s);
     hipGraph_t graph = nullptr;
     if (hipStreamEndCapture(s, &graph) != hipSuccess && !rc) rc = VECKM_E_HIP;
     gr->graph = graph;
@@ -850,6 +902,7 @@ int veckm_tiling_info(const veckm_ctx* ctx, int32_t index, int32_t* info) {
   info[1] = t.brick.by;
   info[2] = t.brick.bt;
   info[3] = t.nbuf;
+  info[4] = t.layout;
   return VECKM_OK;
 }
 

@@ -56,6 +56,7 @@ struct EncArgs {
   const uint32_t* zeros;
   void* rows;
   int32_t* plan;
+  int32_t* rowcnt;  // per-row neighbour counts, or NULL
 };
 
 __device__ inline half8 as_half8(uint4 u) {
@@ -103,19 +104,28 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // Waves per block and the most 16-frequency tiles one wave holds.
 constexpr int kEncWaves = 16;
 constexpr int kEncMaxNtw = 4;
+// 16-row tiles each wave holds per chunk.
+constexpr int kEncMt = 2;
 // With four slab buffers, take the k-steps in pairs: one barrier per pair.
 constexpr bool kEncPairSteps = true;
 
 // LDS byte offset of the slice descriptors (after `bytes` of everything else).
 __host__ __device__ constexpr size_t slice_table_offset(size_t bytes) { return (bytes + 15) & ~size_t(15); }
 
-template <int NA, int NT>
+// Wave layouts of the encoder block: 0 = 16 waves (4 per SIMD) of kEncMt
+// row tiles each; 1 = 8 waves (2 per SIMD) of 2 kEncMt row tiles each
+// (every table fragment read from LDS feeds twice the products; half the
+// waves to hide latency).
+constexpr int enc_waves(int L) { return L == 0 ? kEncWaves : kEncWaves / 2; }
+constexpr int enc_mt(int L) { return L == 0 ? kEncMt : 2 * kEncMt; }
+
+template <int NA, int NT, int L>
 struct EncShape {
-  static constexpr int NW = kEncWaves;          // waves per block
+  static constexpr int NW = enc_waves(L);       // waves per block
   static constexpr int NTW = NT < kEncMaxNtw ? NT : kEncMaxNtw;  // frequency tiles per wave
-  static constexpr int WN = NT / NTW;           // waves across frequencies (1, or 2 at D = 256)
+  static constexpr int WN = NT / NTW;           // waves across frequencies (2 at D = 128, 4 at D = 256)
   static constexpr int WM = NW / WN;            // waves across rows
-  static constexpr int MT = 2;                  // 16-row tiles per wave
+  static constexpr int MT = enc_mt(L);          // 16-row tiles per wave
   static constexpr int CH = WM * MT * 16;       // rows per chunk
   static constexpr int SLAB_U4 = NA * NT * 64;  // uint4 per 32-slot slab
   static constexpr int PFW = SLAB_U4 / (NW * 64);  // copies per wave per slab
@@ -189,14 +199,14 @@ struct CountWords {
 // One k-step of the contraction for a wave with MTV valid row tiles: the
 // count pair sums of its rows (gathered from the box), the table slab `sb`
 // as A operand, and the exact neighbour count on the vector ALU.
-template <int NA, int NT, int MTV>
+template <int NA, int NT, int L, int MTV>
 __device__ inline void kstep_compute(int ks, const uint4* sb, const int32_t* runs_l,
                                      const uint16_t* wts_l, const uint32_t* vol2,
-                                     const int (&rb)[EncShape<NA, NT>::MT],
-                                     floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                     floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                     float (&cnt)[EncShape<NA, NT>::MT], int wn, int lane) {
-  using S = EncShape<NA, NT>;
+                                     const int (&rb)[EncShape<NA, NT, L>::MT],
+                                     floatx4 (&accR)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                     floatx4 (&accI)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                     float (&cnt)[EncShape<NA, NT, L>::MT], int wn, int lane) {
+  using S = EncShape<NA, NT, L>;
   constexpr int NTW = S::NTW;
   const int g = lane >> 4;
   CountWords<MTV> cw;
@@ -259,15 +269,15 @@ __device__ inline void kstep_compute(int ks, const uint4* sb, const int32_t* run
 // accumulator of a lane holds 4 consecutive frequencies of one row (the
 // lane's row is lane & 15): the count of that row arrives in the same lane
 // and the row is written with 16-byte stores.
-template <int NA, int NT, int NBUF, int MTV>
+template <int NA, int NT, int L, int NBUF, int MTV>
 __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
                                     const int32_t* runs_l, const uint16_t* wts_l,
-                                    const uint32_t* vol2, const int (&rb)[EncShape<NA, NT>::MT],
-                                    floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                    floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                    float (&cnt)[EncShape<NA, NT>::MT], int wn, int wid,
+                                    const uint32_t* vol2, const int (&rb)[EncShape<NA, NT, L>::MT],
+                                    floatx4 (&accR)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                    floatx4 (&accI)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                    float (&cnt)[EncShape<NA, NT, L>::MT], int wn, int wid,
                                     int lane) {
-  using S = EncShape<NA, NT>;
+  using S = EncShape<NA, NT, L>;
   constexpr int NW = S::NW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
   if constexpr (kEncPairSteps && NBUF == 4) {
     // two k-steps per barrier: the slabs of the next pair go into the two
@@ -279,10 +289,10 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
         if (ks + u < nsteps)
           issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + u) * SLAB_U4,
                                   slab + ((ks + u) % 4) * SLAB_U4, wid, lane);
-      kstep_compute<NA, NT, MTV>(ks, slab + (ks % 4) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
+      kstep_compute<NA, NT, L, MTV>(ks, slab + (ks % 4) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
                                  accI, cnt, wn, lane);
       if (ks + 1 < nsteps)
-        kstep_compute<NA, NT, MTV>(ks + 1, slab + ((ks + 1) % 4) * SLAB_U4, runs_l, wts_l, vol2,
+        kstep_compute<NA, NT, L, MTV>(ks + 1, slab + ((ks + 1) % 4) * SLAB_U4, runs_l, wts_l, vol2,
                                    rb, accR, accI, cnt, wn, lane);
       __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));  // the next pair has landed
       lds_barrier();
@@ -295,7 +305,7 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
       if (ks + AHEAD < nsteps)
         issue_slab<SLAB_U4, NW>(frag + (size_t)(ks + AHEAD) * SLAB_U4,
                                 slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
-      kstep_compute<NA, NT, MTV>(ks, slab + (ks % NBUF) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
+      kstep_compute<NA, NT, L, MTV>(ks, slab + (ks % NBUF) * SLAB_U4, runs_l, wts_l, vol2, rb, accR,
                                  accI, cnt, wn, lane);
       // make sure the slab of step ks + 1 has landed (slabs ks + 2 .. ks +
       // AHEAD may stay in flight)
@@ -307,23 +317,23 @@ __device__ inline void chunk_ksteps(int nsteps, const uint4* frag, uint4* slab,
 }
 
 // Dispatches on the wave's number of valid row tiles (wave-uniform).
-template <int NA, int NT, int NBUF, int M>
+template <int NA, int NT, int L, int NBUF, int M>
 __device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, uint4* slab,
                                       const int32_t* runs_l, const uint16_t* wts_l,
-                                      const uint32_t* vol2, const int (&rb)[EncShape<NA, NT>::MT],
-                                      floatx4 (&accR)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                      floatx4 (&accI)[EncShape<NA, NT>::MT][EncShape<NA, NT>::NTW],
-                                      float (&cnt)[EncShape<NA, NT>::MT], int wn, int wid,
+                                      const uint32_t* vol2, const int (&rb)[EncShape<NA, NT, L>::MT],
+                                      floatx4 (&accR)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                      floatx4 (&accI)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                      float (&cnt)[EncShape<NA, NT, L>::MT], int wn, int wid,
                                       int lane) {
   if constexpr (M == 0) {
-    chunk_ksteps<NA, NT, NBUF, 0>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
+    chunk_ksteps<NA, NT, L, NBUF, 0>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
                                   wn, wid, lane);
   } else {
     if (mtv == M)
-      chunk_ksteps<NA, NT, NBUF, M>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
+      chunk_ksteps<NA, NT, L, NBUF, M>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI, cnt,
                                     wn, wid, lane);
     else
-      chunk_ksteps_n<NA, NT, NBUF, M - 1>(mtv, nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR,
+      chunk_ksteps_n<NA, NT, L, NBUF, M - 1>(mtv, nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR,
                                           accI, cnt, wn, wid, lane);
   }
 }
@@ -331,9 +341,9 @@ __device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, ui
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 
-template <int NA, int NT, int NBUF, int ROWS>
-__global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
-  using S = EncShape<NA, NT>;
+template <int NA, int NT, int L, int NBUF, int ROWS>
+__global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
+  using S = EncShape<NA, NT, L>;
   constexpr int NW = S::NW, NTW = S::NTW, WN = S::WN, WM = S::WM, MT = S::MT, CH = S::CH,
                 SLAB_U4 = S::SLAB_U4, PFW = S::PFW;
   static_assert(NBUF == 2 || ((NBUF == 3 || NBUF == 4) && S::EVEN),
@@ -477,7 +487,7 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
           accI[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
       }
-      chunk_ksteps_n<NA, NT, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb, accR,
+      chunk_ksteps_n<NA, NT, L, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb, accR,
                                        accI, cnt, wn, wid, lane);
 
       // ---- normalise by the neighbour count and write the rows: the lane
@@ -491,6 +501,7 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
         n += __shfl_xor(n, 16);
         n += __shfl_xor(n, 32);
         if (r >= nr) continue;
+        if (a.rowcnt && wn == 0 && lane < 16) a.rowcnt[row0 + c0 + r] = (int)n;
         const float rc = __builtin_amdgcn_rcpf(n);
         // x / n: reciprocal estimate plus one residual correction (exact for
         // x = n, so an all-ones feature still gives exactly 1).  A query of a
@@ -553,29 +564,31 @@ __global__ __launch_bounds__(kEncWaves * 64) void k_encode(EncArgs a) {
   }
 }
 
-template <int NA, int NT, int NBUF>
+template <int NA, int NT, int L, int NBUF>
 static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
-  using S = EncShape<NA, NT>;
+  using S = EncShape<NA, NT, L>;
   return (size_t)NBUF * S::SLAB_U4 * 16 + (size_t)et.KP + (size_t)et.KP * 2 +
          (size_t)S::CH * 4 + 16 + (size_t)vol * 4;
 }
 
-// Rows per chunk and LDS bytes of the encoder for a given D (mirrors EncShape).
-static int chunk_rows(int nt) {
-  const int ntw = nt < kEncMaxNtw ? nt : kEncMaxNtw, wn = nt / ntw, wm = kEncWaves / wn;
-  return wm * 4 * 16;
+// Rows per chunk and LDS bytes of the encoder for a given D and wave layout
+// (the host-side mirror of EncShape::CH).
+static int chunk_rows(int nt, int layout) {
+  const int ntw = nt < kEncMaxNtw ? nt : kEncMaxNtw, wn = nt / ntw;
+  const int wm = enc_waves(layout) / wn;
+  return wm * enc_mt(layout) * 16;
 }
 
-size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol) {
+size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol, int layout) {
   const int na = precision == VECKM_FP32 ? 4 : 2, nt = d / 16;
-  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)chunk_rows(nt) * 4 + 16 +
-         (size_t)vol * 4;
+  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)chunk_rows(nt, layout) * 4 +
+         16 + (size_t)vol * 4;
 }
 
-template <int NA, int NT, int NBUF>
+template <int NA, int NT, int L, int NBUF>
 static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                     hipStream_t s) {
-  size_t lds = encode_lds_bytes<NA, NT, NBUF>(et, a.vol);
+  size_t lds = encode_lds_bytes<NA, NT, L, NBUF>(et, a.vol);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
   // a batch's slice descriptors go to LDS when they fit beside the rest
   EncArgs b = a;
@@ -588,54 +601,70 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_
   if (rows == kRowsHiLo16 && NA != 4) return VECKM_E_INVAL;  // hi/lo rows: the FP32 form only
   constexpr int HL = NA == 4 ? kRowsHiLo16 : kRowsF32;
   const void* fn =
-      rows == kRowsBF16     ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsBF16>)
-      : rows == kRowsHiLo16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, HL>)
-                            : reinterpret_cast<const void*>(&k_encode<NA, NT, NBUF, kRowsF32>);
+      rows == kRowsBF16     ? reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, kRowsBF16>)
+      : rows == kRowsHiLo16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, HL>)
+                            : reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, kRowsF32>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
   const int per_cu = (int)((160 * 1024) / lds);
   int grid = num_cus * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
   if (grid > b.bt.nbricks) grid = a.bt.nbricks;
-  constexpr int threads = EncShape<NA, NT>::NW * 64;
+  constexpr int threads = EncShape<NA, NT, L>::NW * 64;
   if (rows == kRowsBF16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, b);
+    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, b);
   else if (rows == kRowsHiLo16)
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, HL>), dim3(grid), dim3(threads), lds, s, b);
+    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, HL>), dim3(grid), dim3(threads), lds, s, b);
   else
-    hipLaunchKernelGGL((k_encode<NA, NT, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, b);
+    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, b);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
-template <int NA, int NT>
+static_assert(EncShape<4, 8, 0>::CH == 8 * kEncMt * 16 && EncShape<2, 16, 0>::CH == 4 * kEncMt * 16 &&
+                  EncShape<4, 1, 0>::CH == 16 * kEncMt * 16 &&
+                  EncShape<4, 8, 1>::CH == 4 * 2 * kEncMt * 16,
+              "chunk_rows mirrors EncShape");
+
+template <int NA, int NT, int L>
 static int launch_nb(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                      hipStream_t s) {
-  if constexpr (EncShape<NA, NT>::EVEN) {
-    if (et.nbuf == 4) return launch_t<NA, NT, 4>(a, et, rows, num_cus, s);
-    if (et.nbuf == 3) return launch_t<NA, NT, 3>(a, et, rows, num_cus, s);
+  if constexpr (EncShape<NA, NT, L>::EVEN) {
+    if (et.nbuf == 4) return launch_t<NA, NT, L, 4>(a, et, rows, num_cus, s);
+    if (et.nbuf == 3) return launch_t<NA, NT, L, 3>(a, et, rows, num_cus, s);
   }
-  return launch_t<NA, NT, 2>(a, et, rows, num_cus, s);
+  return launch_t<NA, NT, L, 2>(a, et, rows, num_cus, s);
+}
+
+template <int NA, int NT>
+static int launch_layout(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
+                         hipStream_t s) {
+  // the 8-wave layout only where a wave holds several frequency tiles
+  if constexpr (NT >= 4) {
+    if (et.layout == 1) return launch_nb<NA, NT, 1>(a, et, rows, num_cus, s);
+  }
+  return launch_nb<NA, NT, 0>(a, et, rows, num_cus, s);
 }
 
 template <int NA>
 static int dispatch_nt(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                        hipStream_t s) {
   switch (a.D / 16) {
-    case 1: return launch_nb<NA, 1>(a, et, rows, num_cus, s);
-    case 2: return launch_nb<NA, 2>(a, et, rows, num_cus, s);
-    case 3: return launch_nb<NA, 3>(a, et, rows, num_cus, s);
-    case 4: return launch_nb<NA, 4>(a, et, rows, num_cus, s);
-    case 8: return launch_nb<NA, 8>(a, et, rows, num_cus, s);
-    case 16: return launch_nb<NA, 16>(a, et, rows, num_cus, s);
+    case 1: return launch_layout<NA, 1>(a, et, rows, num_cus, s);
+    case 2: return launch_layout<NA, 2>(a, et, rows, num_cus, s);
+    case 3: return launch_layout<NA, 3>(a, et, rows, num_cus, s);
+    case 4: return launch_layout<NA, 4>(a, et, rows, num_cus, s);
+    case 8: return launch_layout<NA, 8>(a, et, rows, num_cus, s);
+    case 16: return launch_layout<NA, 16>(a, et, rows, num_cus, s);
     default: return VECKM_E_INVAL;
   }
 }
 
-int encode_rows_per_chunk(int d) { return chunk_rows(d / 16); }
-int encode_waves() { return kEncWaves; }
+int encode_rows_per_chunk(int d, int layout) { return chunk_rows(d / 16, layout); }
+int encode_waves(int layout) { return enc_waves(layout); }
 
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream) {
+                  bool clear, int num_cus, void* stream, int32_t* rowcnt) {
   EncArgs a;
+  a.rowcnt = rowcnt;
   a.bt = bt;
   a.b = et.brick;
   a.rx = et.rx;

@@ -588,6 +588,19 @@ __global__ void k_expand_flow_q(const int32_t* __restrict__ queries, Batch bt, B
   out[i] = r >= 0 ? rowflow[r] : make_float2(nan, nan);
 }
 
+template <bool SUB>
+__global__ void k_expand_count_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
+                                 const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
+                                 const int32_t* __restrict__ brick_off,
+                                 const int32_t* __restrict__ rowcnt, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= bt.m) return;  // (whole block; launches never do this)
+  const SliceDesc s = SUB ? bt.s0 : slice_by_event_block(bt, i);
+  if (i >= bt.m) return;
+  const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, i);
+  out[i] = r >= 0 ? rowcnt[r] : -1;
+}
+
 // One wavefront per query.
 template <bool SUB>
 __global__ void k_expand_emb_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
@@ -661,7 +674,7 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
   launch_rank(bt, w, et.brick, queries == nullptr, pairs, s);
-  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), s);
   // the paper form needs each row's voxel (and its expansion reads the query
   // -> row map); the other forms find rows as they expand
   if (!pairs && bt.m > 0)
@@ -710,7 +723,7 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
                        reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err, w.qmark);
   }
   launch_rank(bt, w, et.brick, false, false, s);
-  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d), s);
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), s);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
@@ -760,6 +773,21 @@ int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queri
   else
     hipLaunchKernelGGL(k_expand_flow_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
                        w.rank, w.brick_off, rf, out);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int launch_expand_count(const Batch& bt, const Workspace& w, const int32_t* queries,
+                        const Brick& b, int32_t* counts, void* stream) {
+  if (bt.m <= 0) return VECKM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid(blocks_for(bt.m, 256));
+  const int32_t* rc = reinterpret_cast<const int32_t*>(w.rowflow);
+  if (queries)
+    hipLaunchKernelGGL(k_expand_count_q<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rc, counts);
+  else
+    hipLaunchKernelGGL(k_expand_count_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rc, counts);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

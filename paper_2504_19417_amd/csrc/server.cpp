@@ -2,12 +2,19 @@
 //
 // Slices are independent (every neighbourhood lies inside its slice,
 // Sec. 2.1), so slices of different streams and sensors can share one batch
-// call and the result of each is the same as alone.  A launcher thread packs
-// the waiting slices into batches while fewer than kMaxInflight batches are
-// on the device; a completer thread waits for each batch in order, checks its
-// device error bits and hands the flows to the pollers.  A batch that reports
-// an input error has its slices run again one by one, so only the offending
-// slice gets the error.
+// call and the result of each is the same as alone.  Every open stream keeps
+// its count and pair grids resident on the device: a region of the server's
+// grid arena, taken at veckm_stream_open (admission: the region must fit in
+// the arena the HBM budget pays for) and reused by each of its slices (the
+// encoder returns the counted voxels to zero, so the region is clean for the
+// next slice).  A launcher thread packs waiting slices, at most one per
+// stream, into batches while a device lane is free; each lane has its own
+// event and flow buffers, so the host-to-device copy of one batch (on a copy
+// stream) overlaps the kernels of the other (on the compute stream), and the
+// copy of its flows back runs on a third stream.  A completer thread waits
+// for each batch in order, checks its device error bits and hands the flows
+// to the pollers.  A batch that reports an input error has its slices run
+// again one by one, so only the offending slice gets the error.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +36,7 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr int kMaxInflight = 2;  // batches on the device at once: one running, one queued
+constexpr int kLanes = 2;  // batches on the device at once, each with its own buffers
 constexpr int kMaxDepth = 16;
 
 struct Slot {  // pinned host staging of one submitted slice
@@ -43,9 +50,35 @@ struct Stream {
   int W = 0, H = 0, T = 0;
   int64_t max_events = 0;
   Capacity share;
+  int64_t grid_at = 0, pair_at = 0;  // its resident count / pair grid region
   std::vector<Slot> slots;
   int outstanding = 0;  // submitted and not complete
   int copying = 0;      // results being copied out by veckm_poll
+};
+
+// First-fit allocator of [offset, offset + length) regions in an arena.
+struct Arena {
+  int64_t size = 0;
+  std::vector<std::pair<int64_t, int64_t>> used;  // sorted by offset
+  bool take(int64_t len, int64_t* at) {
+    int64_t pos = 0;
+    size_t i = 0;
+    for (; i < used.size(); ++i) {
+      if (used[i].first - pos >= len) break;
+      pos = used[i].first + used[i].second;
+    }
+    if (i == used.size() && size - pos < len) return false;
+    used.insert(used.begin() + (long)i, {pos, len});
+    *at = pos;
+    return true;
+  }
+  void give(int64_t at) {
+    for (size_t i = 0; i < used.size(); ++i)
+      if (used[i].first == at) {
+        used.erase(used.begin() + (long)i);
+        return;
+      }
+  }
 };
 
 struct Ticket {
@@ -61,13 +94,15 @@ struct Ticket {
 
 struct InFlight {
   std::vector<Ticket*> tickets;
-  hipEvent_t done = nullptr;
+  int lane = -1;
+  hipEvent_t copied = nullptr, computed = nullptr, done = nullptr;
   int32_t* err = nullptr;  // pinned: the batch's device error bits
 };
 
+// What one batch can take (the grids are resident, so only the per-call
+// workspaces count).
 bool fits(const Capacity& used, const Capacity& need, const Capacity& cap) {
-  return used.events + need.events <= cap.events && used.voxels + need.voxels <= cap.voxels &&
-         used.pairs + need.pairs <= cap.pairs && used.bricks + need.bricks <= cap.bricks &&
+  return used.events + need.events <= cap.events && used.bricks + need.bricks <= cap.bricks &&
          used.slices + need.slices <= cap.slices;
 }
 
@@ -85,11 +120,15 @@ struct veckm_server {
   veckm_ctx* ctx = nullptr;
   veckm_params p{};
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // kernels
+  hipStream_t h2d = nullptr;     // events in
+  hipStream_t d2h = nullptr;     // flows out
   int depth = 1;
   Capacity cap, reserved;
-  veckm_event* ev_dev = nullptr;
-  float* flow_dev = nullptr;
+  Arena grid_arena, pair_arena;  // resident stream grids (voxels, pair entries)
+  veckm_event* ev_dev[kLanes] = {};
+  float* flow_dev[kLanes] = {};
+  bool lane_busy[kLanes] = {};
   std::vector<Stream> streams;
   // `mu` guards everything below and the stream table
   std::mutex mu;
@@ -104,6 +143,7 @@ struct veckm_server {
   std::mutex ctx_mu;  // calls on the context (which is not thread-safe)
   std::thread launcher, completer;
   std::vector<double> lat_ms;
+  std::vector<int64_t> lat_sensor;  // W << 32 | H of each latency sample
   int64_t done_slices = 0, done_flows = 0, batches = 0;
   bool have_first = false;
   Clock::time_point first_submit, last_done;
@@ -119,13 +159,24 @@ int take_flight(veckm_server* s, InFlight* f) {
     return VECKM_OK;
   }
   InFlight g;
-  if (hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) return VECKM_E_HIP;
+  for (hipEvent_t* e : {&g.copied, &g.computed, &g.done})
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      for (hipEvent_t x : {g.copied, g.computed, g.done})
+        if (x) (void)hipEventDestroy(x);
+      return VECKM_E_HIP;
+    }
   if (hipHostMalloc(reinterpret_cast<void**>(&g.err), sizeof(int32_t)) != hipSuccess) {
-    (void)hipEventDestroy(g.done);
+    for (hipEvent_t x : {g.copied, g.computed, g.done}) (void)hipEventDestroy(x);
     return VECKM_E_NOMEM;
   }
   *f = g;
   return VECKM_OK;
+}
+
+void drop_flight(InFlight& f) {
+  for (hipEvent_t x : {f.copied, f.computed, f.done})
+    if (x) (void)hipEventDestroy(x);
+  if (f.err) (void)hipHostFree(f.err);
 }
 
 // Completes a ticket (caller holds mu).
@@ -133,18 +184,24 @@ void finish(veckm_server* s, Ticket* t, int status, Clock::time_point now) {
   t->done = true;
   t->status = status;
   t->completed = now;
+  const Stream& st = s->streams[t->sid];
   s->streams[t->sid].outstanding -= 1;
   s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - t->submitted).count());
+  s->lat_sensor.push_back((int64_t)st.W << 32 | st.H);
   s->done_slices += 1;
   s->done_flows += t->n;
   s->last_done = now;
 }
 
-// Copies the batch's events in, runs it, copies the flows out and records
-// its completion event; all on the server's stream.
+// Enqueues one batch on lane f.lane: its events in on the copy stream, the
+// kernels on the compute stream once they have landed, its flows out on the
+// second copy stream once the kernels are done; f.done marks the end.
 int enqueue(veckm_server* s, const std::vector<Ticket*>& take, InFlight& f) {
   std::lock_guard<std::mutex> g(s->ctx_mu);
   std::vector<veckm_slice> sl(take.size());
+  std::vector<int64_t> at(2 * take.size());
+  veckm_event* ev_dev = s->ev_dev[f.lane];
+  float* flow_dev = s->flow_dev[f.lane];
   int64_t off = 0;
   for (size_t k = 0; k < take.size(); ++k) {
     const Ticket* t = take[k];
@@ -155,27 +212,41 @@ int enqueue(veckm_server* s, const std::vector<Ticket*>& take, InFlight& f) {
     sl[k].nbins = t->nbins;
     sl[k].offset = off;
     sl[k].n = t->n;
-    if (t->n > 0 && hipMemcpyAsync(s->ev_dev + off, st.slots[t->slot].ev,
+    at[2 * k] = st.grid_at;
+    at[2 * k + 1] = st.pair_at;
+    if (t->n > 0 && hipMemcpyAsync(ev_dev + off, st.slots[t->slot].ev,
                                    (size_t)t->n * sizeof(veckm_event), hipMemcpyHostToDevice,
-                                   s->stream) != hipSuccess)
+                                   s->h2d) != hipSuccess)
       return VECKM_E_HIP;
     off += t->n;
   }
-  int rc = veckm_flow_batch(s->ctx, sl.data(), (int32_t)sl.size(), s->ev_dev, s->flow_dev,
-                            s->stream);
+  if (hipEventRecord(f.copied, s->h2d) != hipSuccess ||
+      hipStreamWaitEvent(s->stream, f.copied, 0) != hipSuccess)
+    return VECKM_E_HIP;
+  int rc = flow_batch_at(s->ctx, sl.data(), (int32_t)sl.size(), at.data(), ev_dev, flow_dev,
+                         s->stream);
   if (rc) return rc;
   rc = ctx_take_err(s->ctx, f.err, s->stream);
   if (rc) return rc;
+  if (hipEventRecord(f.computed, s->stream) != hipSuccess ||
+      hipStreamWaitEvent(s->d2h, f.computed, 0) != hipSuccess)
+    return VECKM_E_HIP;
   off = 0;
   for (const Ticket* t : take) {
     const Stream& st = s->streams[t->sid];
-    if (t->n > 0 && hipMemcpyAsync(st.slots[t->slot].flow, s->flow_dev + 2 * off,
+    if (t->n > 0 && hipMemcpyAsync(st.slots[t->slot].flow, flow_dev + 2 * off,
                                    (size_t)t->n * 2 * sizeof(float), hipMemcpyDeviceToHost,
-                                   s->stream) != hipSuccess)
+                                   s->d2h) != hipSuccess)
       return VECKM_E_HIP;
     off += t->n;
   }
-  return hipEventRecord(f.done, s->stream) == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+  return hipEventRecord(f.done, s->d2h) == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int free_lane(const veckm_server* s) {
+  for (int l = 0; l < kLanes; ++l)
+    if (!s->lane_busy[l]) return l;
+  return -1;
 }
 
 void launcher_main(veckm_server* s) {
@@ -183,10 +254,11 @@ void launcher_main(veckm_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     s->cv_launch.wait(lk, [s] {
-      return s->stop || (!s->pending.empty() && (int)s->inflight.size() < kMaxInflight);
+      return s->stop || (!s->pending.empty() && free_lane(s) >= 0);
     });
     if (s->stop) return;
-    // waiting slices in submission order while they fit; a slice marked
+    // waiting slices in submission order while they fit, at most one per
+    // stream (a stream's slices share its resident grid); a slice marked
     // solo runs alone
     std::vector<Ticket*> take;
     Capacity used;
@@ -194,14 +266,21 @@ void launcher_main(veckm_server* s) {
       take.push_back(s->pending.front());
       s->pending.pop_front();
     } else {
-      while (!s->pending.empty() && !s->pending.front()->solo) {
-        Ticket* t = s->pending.front();
+      std::vector<char> in_batch(s->streams.size(), 0);
+      for (auto it = s->pending.begin(); it != s->pending.end();) {
+        Ticket* t = *it;
+        if (t->solo) break;
+        if (in_batch[(size_t)t->sid]) {  // its stream's next slice: next batch
+          ++it;
+          continue;
+        }
         const Stream& st = s->streams[t->sid];
         const Capacity need = slice_need(s->ctx, st.W, st.H, t->nbins, t->n);
         if (!fits(used, need, s->cap)) break;
         add(used, need, 1);
+        in_batch[(size_t)t->sid] = 1;
         take.push_back(t);
-        s->pending.pop_front();
+        it = s->pending.erase(it);
       }
     }
     if (take.empty()) {  // cannot happen for admitted streams; never spin on it
@@ -213,12 +292,19 @@ void launcher_main(veckm_server* s) {
     }
     InFlight f;
     int rc = take_flight(s, &f);
+    f.lane = free_lane(s);
+    s->lane_busy[f.lane] = true;
     lk.unlock();
     if (!rc) rc = enqueue(s, take, f);
     lk.lock();
     if (rc) {
+      // whatever was enqueued must finish before the lane is reused
+      (void)hipStreamSynchronize(s->h2d);
+      (void)hipStreamSynchronize(s->stream);
+      (void)hipStreamSynchronize(s->d2h);
       const Clock::time_point now = Clock::now();
       for (Ticket* t : take) finish(s, t, rc, now);
+      s->lane_busy[f.lane] = false;
       if (f.done) s->spare.push_back(f);
       s->cv_done.notify_all();
       continue;
@@ -253,6 +339,7 @@ void completer_main(veckm_server* s) {
       for (Ticket* t : f.tickets) finish(s, t, code, now);
     }
     f.tickets.clear();
+    s->lane_busy[f.lane] = false;
     s->spare.push_back(f);
     s->cv_launch.notify_one();
     s->cv_done.notify_all();
@@ -279,12 +366,16 @@ int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, in
     return VECKM_E_INVAL;
   veckm_params p = *params;
   if (p.max_slices < max_streams) p.max_slices = max_streams;
+  // the resident grid arena: by default room for every stream at the
+  // largest sensor and slice length
+  if (p.max_voxels == 0) p.max_voxels = (int64_t)p.width * p.height * p.max_bins * max_streams;
   int rc = veckm_params_check(&p);
   if (rc) return rc;
   if (p.rt < 0) return VECKM_E_INVAL;  // batches need the temporally bounded encoder
   const int64_t ws = veckm_workspace_bytes(&p, 512);
   if (ws < 0) return (int)ws;
-  const int64_t bytes = ws + p.max_events * (int64_t)(sizeof(veckm_event) + 2 * sizeof(float));
+  const int64_t bytes =
+      ws + kLanes * p.max_events * (int64_t)(sizeof(veckm_event) + 2 * sizeof(float));
   if (bytes > hbm_budget_bytes) return VECKM_E_BUDGET;
   veckm_server* s = new (std::nothrow) veckm_server();
   if (!s) return VECKM_E_NOMEM;
@@ -292,23 +383,30 @@ int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, in
   s->depth = depth;
   rc = veckm_create(&p, &s->ctx);
   if (!rc && hipGetDevice(&s->device) != hipSuccess) rc = VECKM_E_HIP;
-  if (!rc && hipMalloc(reinterpret_cast<void**>(&s->ev_dev),
-                       (size_t)std::max<int64_t>(p.max_events, 1) * sizeof(veckm_event)) != hipSuccess)
-    rc = VECKM_E_NOMEM;
-  if (!rc && hipMalloc(reinterpret_cast<void**>(&s->flow_dev),
-                       (size_t)std::max<int64_t>(p.max_events, 1) * 2 * sizeof(float)) != hipSuccess)
-    rc = VECKM_E_NOMEM;
-  if (!rc && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-    rc = VECKM_E_HIP;
+  const size_t nev = (size_t)std::max<int64_t>(p.max_events, 1);
+  for (int l = 0; !rc && l < kLanes; ++l) {
+    if (hipMalloc(reinterpret_cast<void**>(&s->ev_dev[l]), nev * sizeof(veckm_event)) !=
+            hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s->flow_dev[l]), nev * 2 * sizeof(float)) != hipSuccess)
+      rc = VECKM_E_NOMEM;
+  }
+  for (hipStream_t* st : {&s->stream, &s->h2d, &s->d2h})
+    if (!rc && hipStreamCreateWithFlags(st, hipStreamNonBlocking) != hipSuccess) rc = VECKM_E_HIP;
   if (rc) {
     (void)hipGetLastError();
-    if (s->ev_dev) (void)hipFree(s->ev_dev);
-    if (s->flow_dev) (void)hipFree(s->flow_dev);
+    for (int l = 0; l < kLanes; ++l) {
+      if (s->ev_dev[l]) (void)hipFree(s->ev_dev[l]);
+      if (s->flow_dev[l]) (void)hipFree(s->flow_dev[l]);
+    }
+    for (hipStream_t st : {s->stream, s->h2d, s->d2h})
+      if (st) (void)hipStreamDestroy(st);
     if (s->ctx) veckm_destroy(s->ctx);
     delete s;
     return rc;
   }
   s->cap = ctx_capacity(s->ctx);
+  s->grid_arena.size = s->cap.voxels;
+  s->pair_arena.size = s->cap.pairs;
   s->streams.resize((size_t)max_streams);
   s->launcher = std::thread(launcher_main, s);
   s->completer = std::thread(completer_main, s);
@@ -327,17 +425,16 @@ void veckm_server_destroy(veckm_server* s) {
   s->launcher.join();  // no batch is launched after this
   s->cv_complete.notify_all();
   s->completer.join();
-  (void)hipStreamSynchronize(s->stream);
+  for (hipStream_t st : {s->h2d, s->stream, s->d2h}) (void)hipStreamSynchronize(st);
   for (InFlight& f : s->inflight) s->spare.push_back(f);
   for (auto& kv : s->tickets) delete kv.second;
-  for (InFlight& f : s->spare) {
-    (void)hipEventDestroy(f.done);
-    (void)hipHostFree(f.err);
-  }
+  for (InFlight& f : s->spare) drop_flight(f);
   for (Stream& st : s->streams) free_slots(st);
-  (void)hipStreamDestroy(s->stream);
-  (void)hipFree(s->ev_dev);
-  (void)hipFree(s->flow_dev);
+  for (hipStream_t st : {s->stream, s->h2d, s->d2h}) (void)hipStreamDestroy(st);
+  for (int l = 0; l < kLanes; ++l) {
+    (void)hipFree(s->ev_dev[l]);
+    (void)hipFree(s->flow_dev[l]);
+  }
   veckm_destroy(s->ctx);
   delete s;
 }
@@ -347,6 +444,7 @@ int veckm_server_set_mlp(veckm_server* s, int32_t hidden, const float* W1, const
   if (!s) return VECKM_E_INVAL;
   std::lock_guard<std::mutex> g(s->ctx_mu);
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->d2h);
   const int rc = veckm_set_mlp(s->ctx, hidden, W1, b1, W2, b2);
   if (!rc) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -392,6 +490,12 @@ int veckm_stream_open(veckm_server* s, int32_t width, int32_t height, int32_t ma
   if (s->stop) rc = VECKM_E_STATE;
   else if (k < 0) rc = VECKM_E_AGAIN;
   else if (!fits(s->reserved, fresh.share, s->cap)) rc = VECKM_E_BUDGET;
+  // the stream's resident grids
+  else if (!s->grid_arena.take(fresh.share.voxels, &fresh.grid_at)) rc = VECKM_E_BUDGET;
+  else if (!s->pair_arena.take(fresh.share.pairs, &fresh.pair_at)) {
+    s->grid_arena.give(fresh.grid_at);
+    rc = VECKM_E_BUDGET;
+  }
   if (rc) {
     lk.unlock();
     free_slots(fresh);
@@ -419,6 +523,8 @@ int veckm_stream_close(veckm_server* s, int32_t sid) {
     }
   }
   add(s->reserved, st.share, -1);
+  s->grid_arena.give(st.grid_at);
+  s->pair_arena.give(st.pair_at);
   Stream gone = std::move(st);
   s->streams[(size_t)sid] = Stream();
   lk.unlock();
@@ -509,13 +615,19 @@ int veckm_poll(veckm_server* s, uint64_t ticket, float* flows, int32_t timeout_u
   return status;
 }
 
-int veckm_server_stats(veckm_server* s, veckm_serving_stats* out, int32_t reset) {
+namespace {
+
+int stats_of(veckm_server* s, veckm_serving_stats* out, int32_t reset, int32_t width,
+             int32_t height) {
   if (!s || !out) return VECKM_E_INVAL;
   std::vector<double> lat;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    lat = s->lat_ms;
-    out->slices = s->done_slices;
+    const bool all = width == 0 && height == 0;
+    const int64_t key = (int64_t)width << 32 | height;
+    for (size_t i = 0; i < s->lat_ms.size(); ++i)
+      if (all || s->lat_sensor[i] == key) lat.push_back(s->lat_ms[i]);
+    out->slices = all ? s->done_slices : (int64_t)lat.size();
     out->flows = s->done_flows;
     out->batches = s->batches;
     out->busy_s = s->have_first && s->done_slices > 0
@@ -523,6 +635,7 @@ int veckm_server_stats(veckm_server* s, veckm_serving_stats* out, int32_t reset)
                       : 0.0;
     if (reset) {
       s->lat_ms.clear();
+      s->lat_sensor.clear();
       s->done_slices = s->done_flows = s->batches = 0;
       s->have_first = false;
     }
@@ -538,6 +651,18 @@ int veckm_server_stats(veckm_server* s, veckm_serving_stats* out, int32_t reset)
   out->p99_ms = pct(0.99);
   out->max_ms = lat.empty() ? 0.0 : lat.back();
   return VECKM_OK;
+}
+
+}  // namespace
+
+int veckm_server_stats(veckm_server* s, veckm_serving_stats* out, int32_t reset) {
+  return stats_of(s, out, reset, 0, 0);
+}
+
+int veckm_server_stats_sensor(veckm_server* s, int32_t width, int32_t height,
+                              veckm_serving_stats* out) {
+  if (width < 1 || height < 1) return VECKM_E_INVAL;
+  return stats_of(s, out, 0, width, height);
 }
 
 }  // extern "C"

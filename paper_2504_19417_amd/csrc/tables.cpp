@@ -37,6 +37,15 @@ int check_params(const veckm_params* p) {
   if (V > (int64_t)std::numeric_limits<int32_t>::max() / 2) return VECKM_E_INVAL;
   for (int i = 0; i < 3 * p->d; ++i)
     if (!std::isfinite(p->A[i])) return VECKM_E_INVAL;
+  if (p->rt >= 0) {
+    // the encoder needs a brick whose count box fits in LDS beside two
+    // table slabs (large D with the largest windows does not)
+    const SlotTable st = make_slots(p->rx, p->ry, p->rt);
+    Brick b;
+    int nbuf;
+    if (!choose_layout(p->rx, p->ry, p->rt, p->d, p->precision, st.KP, &b, &nbuf))
+      return VECKM_E_INVAL;
+  }
   return VECKM_OK;
 }
 
@@ -216,14 +225,15 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t) {
 // cut the number of passes over the table; extra slabs hide the latency of
 // the table copies (three or four need the copies split evenly over the
 // waves).
-void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick,
+bool choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick,
                    int* nbuf) {
   const Brick cand[] = {{32, 16, 8}, {32, 16, 4}, {16, 16, 8}, {16, 16, 4},
                         {16, 8, 4},  {8, 8, 4},   {8, 8, 2},   {8, 4, 2}, {4, 4, 1}};
   const int na = precision == VECKM_FP32 ? 4 : 2;
   const bool even = (na * (d / 16) * 64) % (encode_waves() * 64) == 0;  // copies split evenly
   auto fits = [&](const Brick& b, int nb) {
-    return encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
+    return box_sx(b, rx) <= 64 &&
+           encode_lds_need(d, precision, nb, kp, box_dwords(b, rx, ry, rt)) <= 160 * 1024;
   };
   for (const Brick& b : cand)
     if (fits(b, 2)) {
@@ -234,10 +244,11 @@ void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
           *nbuf = nb;
           break;
         }
-      return;
+      return true;
     }
   *brick = Brick{4, 4, 1};
   *nbuf = 2;
+  return false;
 }
 
 // The encoder tilings a context offers: the default layout above first,
@@ -268,6 +279,18 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
         break;
       }
     if (!bigger && t.nbuf <= def.nbuf) continue;  // smaller only for deeper buffering
+    out.push_back(t);
+  }
+  // each of them also with the 8-wave layout (four frequency tiles or more
+  // per wave: D >= 64), where it fits
+  const size_t n = out.size();
+  for (size_t i = 0; i < n && d >= 64; ++i) {
+    Tiling t = out[i];
+    t.layout = 1;
+    const bool even8 = (na * (d / 16) * 64) % (encode_waves(1) * 64) == 0;
+    if (t.nbuf > 2 && !even8) continue;
+    if (encode_lds_need(d, precision, t.nbuf, kp, box_dwords(t.brick, rx, ry, rt), 1) > 160 * 1024)
+      continue;
     out.push_back(t);
   }
   return out;

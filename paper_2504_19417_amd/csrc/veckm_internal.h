@@ -57,17 +57,19 @@ std::vector<uint16_t> make_slot_weights(const SlotTable& t);
 OffsetTable make_offsets(int rx, int ry, int rt);
 // FP64 phases -> fp16 bit patterns [k][j][4] = (cos hi, cos lo, sin hi, sin lo).
 void make_phase_bits(const OffsetTable& t, const double* A, int d, uint16_t* out);
-void choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick, int* nbuf);
+// false when no brick's count box fits in LDS beside two table slabs
+bool choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* brick, int* nbuf);
 // An encoder tiling: brick shape and table slabs buffered in LDS.
 struct Tiling {
   Brick brick{32, 16, 8};
   int nbuf = 2;
+  int layout = 0;  // encoder wave layout: 0 = 16 waves x 2 row tiles, 1 = 8 waves x 4 row tiles
 };
 constexpr int kMaxBrickVoxels = 8192;  // largest brick (the ranking kernel's limit)
 std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp);
-size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol);
-int encode_rows_per_chunk(int d);
-int encode_waves();  // waves per encoder block
+size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol, int layout = 0);
+int encode_rows_per_chunk(int d, int layout);
+int encode_waves(int layout = 0);  // waves per encoder block
 int lds_volume_halves(const Brick& b, int rx, int ry, int rt);
 // The encoder's LDS box of a brick: the brick plus the window halo, widened
 // by kRunPad columns on each side in x so that no 4-offset run of the slot
@@ -163,7 +165,8 @@ struct EncodeTables {
   const int32_t* runs = nullptr;   // KP / 4 run byte offsets
   const uint16_t* wts = nullptr;   // KP slot weights (fp16)
   int K = 0, KP = 0, na = 4;
-  int nbuf = 3;  // k-step slabs of the table buffered in LDS (2 or 3)
+  int nbuf = 3;  // k-step slabs of the table buffered in LDS (2 to 4)
+  int layout = 0;  // encoder wave layout (Tiling::layout)
   int rx = 0, ry = 0, rt = 0;
   Brick brick{32, 16, 8};
   int d = 0;
@@ -202,8 +205,9 @@ void make_paper_tables(const double* A, int d, int width, int height, int max_bi
 constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
 // clear: also return every row's voxel count to zero (calls that query every
 // event: their rows are exactly the counted voxels).
+// rowcnt: when non-NULL, also the neighbour count of every row (int32 [U]).
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream);
+                  bool clear, int num_cus, void* stream, int32_t* rowcnt = nullptr);
 // Per-query outputs; use_qmap: rows from the query -> row map (paper form),
 // else found from each query's voxel (`queries` as in the call, or NULL).
 int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
@@ -215,6 +219,10 @@ int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int nu
 bool mlp_rows_split(int d, int hidden);
 int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
                        const Brick& b, bool use_qmap, float* flow, void* stream);
+// Per-query neighbour counts from the rows' counts (int32 [U], held in
+// w.rowflow); -1 for an invalid query.
+int launch_expand_count(const Batch& bt, const Workspace& w, const int32_t* queries,
+                        const Brick& b, int32_t* counts, void* stream);
 // The count grid of a batch back to zero (after a run that skipped the expansion).
 int launch_clear_counts(const Batch& bt, const Workspace& w, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
@@ -258,6 +266,11 @@ struct Capacity {
   int64_t events = 0, voxels = 0, pairs = 0, bricks = 0, slices = 0;
 };
 Capacity ctx_capacity(const veckm_ctx* c);
+// veckm_flow_batch with slice k's count grid at voxel at[2k] and its pair
+// grid at entry at[2k + 1] of the context's grids (non-overlapping regions
+// that stay put between calls: a server stream's resident grid).
+int flow_batch_at(veckm_ctx* c, const veckm_slice* slices, int32_t count, const int64_t* at,
+                  const veckm_event* events, float* flow, void* stream);
 Capacity slice_need(const veckm_ctx* c, int W, int H, int T, int64_t n);
 int ctx_take_err(veckm_ctx* c, int32_t* host, void* stream);
 // VECKM_OK, VECKM_E_OVERFLOW or VECKM_E_RANGE for a set of device error bits.

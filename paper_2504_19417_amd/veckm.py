@@ -95,6 +95,8 @@ _sig = {
                                     ctypes.c_int64, _P, _P]),
     "veckm_flow": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P, _P]),
+    "veckm_count": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
+                                   ctypes.c_int64, _P, _P]),
     "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
@@ -130,6 +132,8 @@ _sig = {
                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "veckm_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.c_int32]),
     "veckm_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(veckm_serving_stats), ctypes.c_int32]),
+    "veckm_server_stats_sensor": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.POINTER(veckm_serving_stats)]),
     "veckm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "veckm_profile_read": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "veckm_last_rows": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -223,6 +227,11 @@ def veckm_encode(ctx, events_ptr, n, t0, nbins, queries_ptr, m, emb_ptr, stream)
 def veckm_flow(ctx, events_ptr, n, t0, nbins, queries_ptr, m, flow_ptr, stream):
     return _lib.veckm_flow(ctx, events_ptr, int(n), int(t0), int(nbins), queries_ptr, int(m),
                            flow_ptr, stream)
+
+
+def veckm_count(ctx, events_ptr, n, t0, nbins, queries_ptr, m, counts_ptr, stream):
+    return _lib.veckm_count(ctx, events_ptr, int(n), int(t0), int(nbins), queries_ptr, int(m),
+                            counts_ptr, stream)
 
 
 def veckm_encode_batch(ctx, slices, count, events_ptr, emb_ptr, stream):
@@ -353,6 +362,21 @@ class Context:
             raise VeckmError(rc, "veckm_flow")
         return out
 
+    def count(self, events, t0, nbins, queries=None, out=None, stream=None):
+        """Windowed neighbour count (int32) of each queried event."""
+        import torch
+        self._check_inputs(events, queries)
+        n = events.shape[0]
+        m = n if queries is None else queries.shape[0]
+        if out is None:
+            out = torch.empty((m,), dtype=torch.int32, device=events.device)
+        rc = veckm_count(self.handle, events.data_ptr(), n, t0, nbins,
+                         None if queries is None else queries.data_ptr(), m,
+                         out.data_ptr(), self._stream(stream))
+        if rc:
+            raise VeckmError(rc, "veckm_count")
+        return out
+
     def _batch(self, fn, name, width, slices, events, out, stream):
         import torch
         self._check_inputs(events, None)
@@ -380,11 +404,11 @@ class Context:
         return veckm_status(self.handle, self._stream(stream))
 
     def tilings(self):
-        """[(bx, by, bt, slabs)] of the encoder tilings this context offers."""
+        """[(bx, by, bt, slabs, layout)] of the encoder tilings this context offers."""
         n = _lib.veckm_tiling_count(self.handle)
         out = []
         for i in range(n):
-            info = (ctypes.c_int32 * 4)()
+            info = (ctypes.c_int32 * 5)()
             rc = _lib.veckm_tiling_info(self.handle, i, ctypes.cast(info, _P))
             if rc:
                 raise VeckmError(rc, "veckm_tiling_info")
@@ -498,6 +522,14 @@ def veckm_server_stats(server, reset=False):
     rc = _lib.veckm_server_stats(server, ctypes.byref(st), int(bool(reset)))
     if rc:
         raise VeckmError(rc, "veckm_server_stats")
+    return {f: getattr(st, f) for f, _ in veckm_serving_stats._fields_}
+
+
+def veckm_server_stats_sensor(server, width, height):
+    st = veckm_serving_stats()
+    rc = _lib.veckm_server_stats_sensor(server, int(width), int(height), ctypes.byref(st))
+    if rc:
+        raise VeckmError(rc, "veckm_server_stats_sensor")
     return {f: getattr(st, f) for f, _ in veckm_serving_stats._fields_}
 
 
@@ -678,3 +710,6 @@ class Server:
 
     def stats(self, reset=False):
         return veckm_server_stats(self.handle, reset)
+
+    def stats_sensor(self, width, height):
+        return veckm_server_stats_sensor(self.handle, width, height)

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from paper_2504_19417_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -76,14 +77,20 @@ def test_tiny_fp32_all_queries(vk, tiny):
              mlp=tiny["mlp"])
     emb, st = _run_encode(c, tiny["ev"], tiny["t0"], tiny["T"])
     assert st == vk.VECKM_OK
-    e = rel_l2(emb, tiny["emb"])
-    _say("tiny fp32 emb relL2 %.3e maxabs %.3e" % (e, np.abs(emb - tiny["emb"]).max()))
-    assert e <= 1e-4
+    parity.check(emb, tiny["emb"], "fp32", "emb", kp=parity.padded_slots(w.rx, w.ry, w.rt),
+                 say=_say)
     flow, st = _run_flow(c, tiny["ev"], tiny["t0"], tiny["T"])
     assert st == vk.VECKM_OK
-    f = rel_l2(flow, tiny["flow"])
-    _say("tiny fp32 flow relL2 %.3e" % f)
-    assert f <= 1e-3
+    parity.check(flow, tiny["flow"], "fp32", "flow", say=_say)
+    # P1: the windowed count of every event, bit for bit
+    cnt = c.count(torch.from_numpy(tiny["ev"]).cuda(), tiny["t0"], tiny["T"]).cpu().numpy()
+    assert c.status() == vk.VECKM_OK
+    np.testing.assert_array_equal(cnt, tiny["cnt"])
+    q = synth.sample_queries(len(tiny["ev"]), 777, 5).astype(np.int32)
+    cq = c.count(torch.from_numpy(tiny["ev"]).cuda(), tiny["t0"], tiny["T"],
+                 torch.from_numpy(q).cuda()).cpu().numpy()
+    assert c.status() == vk.VECKM_OK
+    np.testing.assert_array_equal(cq, tiny["cnt"][q])
     c.close()
 
 
@@ -155,11 +162,14 @@ def test_ragged_sizes_and_grid_edges(vk, n):
         ev[3, :3] = ev[4, :3] = ev[5, :3] = [W - 1, 0, (1 << 30) + 4]
     A = synth.draw_frequencies(48, 4, 2, 3)
     mlp = synth.init_mlp(48, 64)
-    ref, _ = oracle.encode(ev, A, 4, 2, 3)
+    ref, cnt = oracle.encode(ev, A, 4, 2, 3)
     c = _ctx(vk, W, H, (4, 2, 3), A, T, max(n, 16), mlp=mlp)
     emb, st = _run_encode(c, ev, 1 << 30, T)
     assert st == vk.VECKM_OK
-    assert rel_l2(emb, ref) <= 1e-4
+    parity.check(emb, ref, "fp32", "emb", kp=parity.padded_slots(4, 2, 3), say=_say)
+    got = c.count(torch.from_numpy(ev).cuda(), 1 << 30, T).cpu().numpy()
+    assert c.status() == vk.VECKM_OK
+    np.testing.assert_array_equal(got, cnt)
     flow, st = _run_flow(c, ev, 1 << 30, T)
     assert st == vk.VECKM_OK
     assert rel_l2(flow, oracle.mlp(ref, *mlp)) <= 1e-3
@@ -207,23 +217,40 @@ def test_input_errors_are_reported(vk):
     c.close()
 
 
+def _full_size_sample(ev, t0, n_random, seed, brick=(32, 16, 8), n_faces=4096):
+    """Sampled queries of a full-size slice: n_random seeded events plus up to
+    n_faces events whose voxel lies on a face of the encoder's default brick
+    (where the count box's halo and the brick edges meet)."""
+    q = synth.sample_queries(len(ev), n_random, seed)
+    t = ev[:, 2] - t0
+    face = ((ev[:, 0] % brick[0] == 0) | (ev[:, 0] % brick[0] == brick[0] - 1) |
+            (ev[:, 1] % brick[1] == 0) | (ev[:, 1] % brick[1] == brick[1] - 1) |
+            (t % brick[2] == 0) | (t % brick[2] == brick[2] - 1))
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    fq = np.flatnonzero(face)
+    fq = rng.choice(fq, min(n_faces, len(fq)), replace=False)
+    return np.unique(np.concatenate([q, fq])).astype(np.int64)
+
+
 @pytest.fixture(scope="module")
 def slice1m():
     w = synth.workloads()["slice1m"]
     ev, t0, T = synth.make_slice(w.slices[0])
     A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
     mlp = synth.init_mlp(w.d, w.hidden)
-    q = synth.sample_queries(len(ev), 4096, 77)
+    q = _full_size_sample(ev, t0, 16384, 77)
     emb, cnt = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q)
     return dict(w=w, ev=ev, t0=t0, T=T, A=A, mlp=mlp, q=q, emb=emb,
-                flow=oracle.mlp(emb, *mlp))
+                flow=oracle.mlp(emb, *mlp), cnt_all=oracle.box_count(ev, w.rx, w.ry, w.rt))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
 def test_slice1m_full_run_sampled_parity(vk, slice1m, precision):
     """The 1M-event, 346x260x50, D=128, r=5/3 workload in the launch
-    configuration the benchmark times (all events queried); 4096 sampled
-    rows are compared with the oracle."""
+    configuration the benchmark times (all events queried): about 20k
+    sampled rows (16384 random, the rest on brick faces) against the oracle
+    with whole-sample, per-row and per-element bounds, and the windowed count
+    of every one of the 1M events bit for bit against the exact box count."""
     s = slice1m
     w = s["w"]
     _say("case: slice1m %s full run" % precision)
@@ -231,15 +258,15 @@ def test_slice1m_full_run_sampled_parity(vk, slice1m, precision):
              mlp=s["mlp"])
     emb, st = _run_encode(c, s["ev"], s["t0"], s["T"])
     assert st == vk.VECKM_OK
-    e = rel_l2(emb[s["q"]], s["emb"])
     flow, st = _run_flow(c, s["ev"], s["t0"], s["T"])
     assert st == vk.VECKM_OK
-    f = rel_l2(flow[s["q"]], s["flow"])
-    _say("slice1m %s sampled emb relL2 %.3e flow relL2 %.3e" % (precision, e, f))
-    if precision == "fp32":
-        assert e <= 1e-4 and f <= 1e-3
-    else:
-        assert e <= 2e-3 and f <= 3e-2
+    parity.check(emb[s["q"]], s["emb"], precision, "emb", say=_say)
+    parity.check(flow[s["q"]], s["flow"], precision, "flow", say=_say)
+    # P1: the exact windowed count of every event
+    evt = torch.from_numpy(s["ev"]).cuda()
+    cnt = c.count(evt, s["t0"], s["T"]).cpu().numpy()
+    assert c.status() == vk.VECKM_OK
+    np.testing.assert_array_equal(cnt, s["cnt_all"])
     # modulus bound and determinism at full size
     assert np.hypot(emb[:, :128], emb[:, 128:]).max() <= 1.0 + 1e-5
     emb2, _ = _run_encode(c, s["ev"], s["t0"], s["T"])
@@ -258,21 +285,23 @@ def precision5m():
     ev, t0, T = synth.make_slice(w.slices[0])
     A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
     mlp = synth.init_mlp(w.d, w.hidden)
-    q = synth.sample_queries(len(ev), 1024, 78)
+    q = _full_size_sample(ev, t0, 16384, 78)
     emb, cnt = oracle.encode(ev, A, w.rx, w.ry, w.rt, queries=q)
     return dict(w=w, ev=ev, t0=t0, T=T, A=A, mlp=mlp, q=q, emb=emb,
-                flow=oracle.mlp(emb, *mlp))
+                flow=oracle.mlp(emb, *mlp), cnt_all=oracle.box_count(ev, w.rx, w.ry, w.rt))
 
 
 def test_precision5m_full_run_sampled_parity(vk, precision5m):
     """The precision workload (1280x720, 5M events with textured-blob noise,
     100 bins, D=128, r=5/3) at full size in the benchmark's launch
-    configuration, both forms: 1024 sampled rows against the oracle, and the
-    FP16/BF16 form's flows against the FP32 form's over the whole slice."""
+    configuration, both forms: about 20k sampled rows against the oracle
+    (whole-sample, per-row and per-element bounds), every event's windowed
+    count bit for bit, and the FP16/BF16 form's flows against the FP32
+    form's over the whole slice."""
     s = precision5m
     w = s["w"]
     evt = torch.from_numpy(s["ev"]).cuda()
-    qt = torch.from_numpy(s["q"].astype(np.int64)).cuda()
+    qt = torch.from_numpy(s["q"]).cuda()
     flows = {}
     for precision in ("fp32", "fp16"):
         _say("case: precision5m %s full run" % precision)
@@ -284,14 +313,13 @@ def test_precision5m_full_run_sampled_parity(vk, precision5m):
         flow = c.flow(evt, s["t0"], s["T"]).cpu().numpy()
         torch.cuda.synchronize()
         assert c.status() == vk.VECKM_OK
-        c.close()
-        e = rel_l2(emb_q, s["emb"])
-        f = rel_l2(flow[s["q"]], s["flow"])
-        _say("precision5m %s sampled emb relL2 %.3e flow relL2 %.3e" % (precision, e, f))
         if precision == "fp32":
-            assert e <= 1e-4 and f <= 1e-3
-        else:
-            assert e <= 2e-3 and f <= 3e-2
+            cnt = c.count(evt, s["t0"], s["T"]).cpu().numpy()
+            assert c.status() == vk.VECKM_OK
+            np.testing.assert_array_equal(cnt, s["cnt_all"])
+        c.close()
+        parity.check(emb_q, s["emb"], precision, "emb", say=_say)
+        parity.check(flow[s["q"]], s["flow"], precision, "flow", say=_say)
         assert np.isfinite(flow).all()
         flows[precision] = flow
     d = rel_l2(flows["fp16"], flows["fp32"].astype(np.float64))

@@ -107,6 +107,20 @@ def test_alone_equals_in_mix_and_oracle(vk):
     assert st["slices"] == sum(len(sl) for _, sl in data)
     assert st["batches"] < st["slices"]  # slices shared batches
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    # resident grids: every slice of a stream reused its stream's grid; each
+    # result equals a fresh slice on a context of its own sensor
+    fresh = {}
+    for (W, H), _ in data:
+        if (W, H) not in fresh:
+            c = vk.Context(W, H, *R, A, 16, 20_000, "fp16")
+            c.set_mlp(*mlp)
+            fresh[(W, H)] = c
+    for i, ((W, H), slices) in enumerate(data):
+        for k, (ev, t0, T) in enumerate(slices):
+            f = fresh[(W, H)].flow(torch.from_numpy(ev).cuda(), t0, T).cpu().numpy()
+            assert np.array_equal(f, alone[i][k]), (i, k)
+    for c in fresh.values():
+        c.close()
     # oracle on a sample of each stream's first slice
     for i, (_, slices) in enumerate(data):
         ev = slices[0][0]
@@ -141,6 +155,37 @@ def test_admission_by_capacity_and_close(vk):
     assert e.value.code == vk.VECKM_E_RANGE
     for sid in sids:
         srv.close_stream(sid)
+    srv.close()
+
+
+def test_resident_grid_arena_admission(vk):
+    """Each open stream holds its grids in the server's arena: with room for
+    two 346x260x16 streams a third is refused (as is a larger sensor), a
+    close gives its region back, and slices of streams opened in a reused
+    region give the same flows as before."""
+    _say("case: server grid arena")
+    A = synth.draw_frequencies(D, *R)
+    mlp = synth.init_mlp(D, HIDDEN)
+    srv = _server(vk, A, mlp, max_events=60_000, streams=8, max_voxels=2 * 346 * 260 * 16)
+    a = srv.open_stream(346, 260, 16, 10_000)
+    b = srv.open_stream(346, 260, 16, 10_000)
+    for W, H in ((346, 260), (640, 480)):
+        with pytest.raises(vk.VeckmError) as e:
+            srv.open_stream(W, H, 16, 1000)
+        assert e.value.code == vk.VECKM_E_BUDGET
+    rng = np.random.Generator(np.random.PCG64(12))
+    ev = synth.random_events(rng, 8000, 346, 260, 12, t_base=300)
+    rc, ref = srv.poll(srv.submit(a, ev, 300, 12))
+    assert rc == vk.VECKM_OK
+    srv.close_stream(a)
+    c = srv.open_stream(346, 260, 8, 10_000)  # a smaller stream in the freed region
+    for sid in (b, c):
+        rc, f = srv.poll(srv.submit(sid, ev[ev[:, 2] < 308], 300, 8))
+        assert rc == vk.VECKM_OK
+        rc, f = srv.poll(srv.submit(b, ev, 300, 12))
+        assert rc == vk.VECKM_OK and np.array_equal(f, ref)
+    srv.close_stream(b)
+    srv.close_stream(c)
     srv.close()
 
 

@@ -266,3 +266,25 @@ def test_query_subset_matches_full():
     q = np.array([999, 0, 500, 500, 17])
     sub, cs = oracle.encode(ev, A, 2, 2, 1, queries=q)
     assert np.array_equal(sub, full[q]) and np.array_equal(cs, cf[q])
+
+
+def test_box_count_matches_scan_and_box_filter():
+    """The summed-volume count (Eqn. 17) equals the quadratic scan's count
+    (the definition) bit for bit, with and without a temporal bound, and a
+    scipy box filter of the histogram (an independent route), on events that
+    touch every face of their bounding box."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    ev = synth.random_events(rng, 2500, 33, 21, 9, t_base=-40)
+    ev[0, :3] = [0, 0, -40]
+    ev[1, :3] = [32, 20, -32]
+    for r in ((3, 2, 1), (0, 0, 0), (5, 1, 4), (2, 3, -1)):
+        _, cnt = oracle.encode(ev, np.zeros((4, 3)), *r, search="scan")
+        got = oracle.box_count(ev, *r)
+        np.testing.assert_array_equal(got, cnt)
+        q = rng.integers(0, len(ev), 300)
+        np.testing.assert_array_equal(oracle.box_count(ev, *r, queries=q), cnt[q])
+    hist = np.zeros((33, 21, 9))
+    np.add.at(hist, (ev[:, 0], ev[:, 1], ev[:, 2] + 40), 1)
+    box = scipy.ndimage.convolve(hist, np.ones((7, 5, 3)), mode="constant", cval=0.0)
+    np.testing.assert_array_equal(oracle.box_count(ev, 3, 2, 1),
+                                  box[ev[:, 0], ev[:, 1], ev[:, 2] + 40].astype(np.int64))
