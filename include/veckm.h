@@ -198,6 +198,35 @@ int veckm_encode_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
 int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
                      const veckm_event* events, float* flow, void* stream);
 
+/* ---- allocation-free flow ------------------------------------------------
+   For callers that cannot allocate device memory while they run (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+   veckm_flow_noalloc computes what veckm_flow computes with queries = NULL
+   (every event queried; bit-identical results), but every per-call
+   workspace (count and pair grids, ranks, brick lists, rows, row flows) lives
+   in one static device array of VECKM_NOALLOC_SCRATCH_BYTES that the library
+   holds on each GPU it runs on until the process ends.  Only the context's
+   read-only state is used (phase table, tiling, perceptron weights) and its
+   device error flag (veckm_status reports input errors as usual); the
+   context's own workspaces are not touched.  The call calls no hipMalloc,
+   hipFree or allocating library routine (the device address of the array is
+   looked up once per device, on the first call there).
+     Limits: those of veckm_flow on this context, and the call's workspaces
+     must fit in the array: about 13 W H nbins + (16 + 8 D) n bytes plus the
+     brick lists (a 346 x 260 sensor with 25 bins and 20k events at D = 64
+     needs 50 MB); beyond that it returns VECKM_E_BUDGET and launches nothing.
+     Sharing: every call on one GPU uses the same array and finds it as the
+     last call left it (the count grid is cleared at the start of each call).
+     Calls that overlap on one GPU, on any streams or contexts or threads,
+     race and give undefined results: serialise them (one stream, or
+     synchronise between calls).
+   Returns VECKM_E_INVAL for a window or rt = -1 context, VECKM_E_STATE
+   without a perceptron, VECKM_E_RANGE as veckm_flow, VECKM_E_BUDGET as
+   above, VECKM_E_HIP if the array cannot be located. */
+#define VECKM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int veckm_flow_noalloc(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                       int32_t nbins, float* flow, void* stream);
+
 /* ---- launch graphs (batch forms) ---------------------------------------
    A batch layout that repeats (the same slices, event buffer and output
    buffer on every call, as in a serving loop) can be captured once as a HIP

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1010,6 +1011,104 @@ int veckm_last_rows(veckm_ctx* ctx, void* stream, int64_t* rows) {
   if (hipMemcpy(&u, ctx->w.plan, 4, hipMemcpyDeviceToHost) != hipSuccess) return VECKM_E_HIP;
   *rows = u;
   return VECKM_OK;
+}
+
+// ---- allocation-free flow
+
+}  // extern "C"
+
+namespace {
+
+// The per-call workspaces of veckm_flow_noalloc live in this array (one copy
+// per GPU, held until the process ends).  Host code never passes its name to
+// a kernel: it is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[VECKM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on `device`, looked up with that device
+// current on the first call for it.
+int scratch_on(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxScratchDevices) return VECKM_E_NODEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return VECKM_E_HIP;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return VECKM_E_HIP;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return VECKM_E_HIP;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return VECKM_OK;
+}
+
+// Carves the workspaces of one slice call out of `base` (256-byte aligned
+// pieces); returns the bytes needed.  With base == nullptr only sizes.
+int64_t carve_noalloc(const veckm_ctx* c, const Batch& bt, unsigned char* base, Workspace* w) {
+  const Brick& b = c->et.brick;
+  const int64_t V = bt.nvox, P = bt.npairs, nb = bt.nbricks, n = bt.n;
+  const int64_t U = n < V ? n : V;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> unsigned char* {
+    unsigned char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  w->count = reinterpret_cast<int32_t*>(take(V * 4));
+  w->pairs = reinterpret_cast<uint32_t*>(take(P * 4));
+  w->rank = reinterpret_cast<int32_t*>(take(V * 4));
+  w->qmark = nullptr;  // read only for query subsets
+  w->ulist = reinterpret_cast<int32_t*>(take(nb * b.volume() * 4));
+  w->brick_nq = reinterpret_cast<int32_t*>(take(nb * 4));
+  w->brick_off = reinterpret_cast<int32_t*>(take((nb + 1) * 4));
+  w->order = reinterpret_cast<int32_t*>(take(nb * 16));
+  w->scan_part = reinterpret_cast<int32_t*>(take((scan_tiles(nb) + 1) * kScanNV * 4));
+  w->vox = reinterpret_cast<int32_t*>(take(n * 4));
+  w->qmap = nullptr;  // read only by the paper form
+  w->rows = take(U * 2 * c->p.d * 4);
+  w->rowflow = reinterpret_cast<float*>(take(U * 8));
+  w->plan = reinterpret_cast<int32_t*>(take(64 * 4));
+  w->vmax = V;
+  w->pmax = P;
+  w->nmax = n;
+  w->bmax = nb;
+  w->umax = nb * b.volume();
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int veckm_flow_noalloc(veckm_ctx* ctx, const veckm_event* events, int64_t n, int32_t t0,
+                       int32_t nbins, float* flow, void* stream) {
+  if (!ctx || ctx->window || ctx->paper) return VECKM_E_INVAL;
+  Batch bt;
+  int rc = single_batch(ctx, events, n, t0, nbins, nullptr, n, flow, &bt);
+  if (rc) return rc;
+  if (ctx->mw.hidden == 0) return VECKM_E_STATE;
+  if (n == 0) return VECKM_OK;
+  Workspace w = ctx->w;  // tables, zero page and error flag stay the context's
+  if (carve_noalloc(ctx, bt, nullptr, &w) > (int64_t)VECKM_NOALLOC_SCRATCH_BYTES)
+    return VECKM_E_BUDGET;
+  unsigned char* base = nullptr;
+  rc = scratch_on(ctx->device, &base);
+  if (rc) return rc;
+  carve_noalloc(ctx, bt, base, &w);
+  // the array holds whatever the last call left: the count grid starts at
+  // zero (a fill kernel, no memset)
+  rc = launch_clear_counts(bt, w, stream);
+  if (rc) return rc;
+  return run(ctx, w, bt, events, nullptr, nullptr, flow, stream);
 }
 
 int veckm_status(veckm_ctx* ctx, void* stream) {

@@ -30,6 +30,7 @@ VECKM_E_NODEVICE = -7
 VECKM_E_OVERFLOW = -8
 VECKM_E_STATE = -9
 VECKM_MAX_VOXEL_EVENTS = 1024
+VECKM_NOALLOC_SCRATCH_BYTES = 64 << 20
 VECKM_FP32 = 0
 VECKM_FP16 = 1
 VECKM_STAGE_PREPARE = 0
@@ -97,6 +98,8 @@ _sig = {
                                   ctypes.c_int64, _P, _P]),
     "veckm_count": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P,
                                    ctypes.c_int64, _P, _P]),
+    "veckm_flow_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, _P, _P]),
     "veckm_encode_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_flow_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P]),
     "veckm_status": (ctypes.c_int, [_P, _P]),
@@ -232,6 +235,10 @@ def veckm_flow(ctx, events_ptr, n, t0, nbins, queries_ptr, m, flow_ptr, stream):
 def veckm_count(ctx, events_ptr, n, t0, nbins, queries_ptr, m, counts_ptr, stream):
     return _lib.veckm_count(ctx, events_ptr, int(n), int(t0), int(nbins), queries_ptr, int(m),
                             counts_ptr, stream)
+
+
+def veckm_flow_noalloc(ctx, events_ptr, n, t0, nbins, flow_ptr, stream):
+    return _lib.veckm_flow_noalloc(ctx, events_ptr, int(n), int(t0), int(nbins), flow_ptr, stream)
 
 
 def veckm_encode_batch(ctx, slices, count, events_ptr, emb_ptr, stream):
