@@ -44,11 +44,15 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def compile_source(src: str, out: str) -> str:
-    """gcc -O2 without FMA contraction, OpenMP, as a shared library."""
+def compile_source(src: str, out: str, sanitize: bool = False) -> str:
+    """gcc -O2 without FMA contraction, OpenMP, as a shared library.  With
+    `sanitize`, instrumented by AddressSanitizer and UndefinedBehaviorSanitizer
+    (the library then needs gcc's libasan preloaded into the process)."""
     tmp = out + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
-                           "-shared", src, "-o", tmp, "-lm"])
+    extra = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"] if sanitize else []
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC"] + extra +
+                          ["-shared", src, "-o", tmp, "-lm"])
     os.replace(tmp, out)
     return out
 

@@ -11,6 +11,7 @@
 #include <limits>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "veckm_internal.h"
@@ -20,7 +21,48 @@ using namespace veckm;
 namespace {
 constexpr int kRing = 8;  // slice tables of batch calls in flight per context
 constexpr int64_t kMaxTotalVoxels = std::numeric_limits<int32_t>::max();
+
+// The allocation fault hook: counts allocations since VECKM_FAULT_ALLOC last
+// changed and reports whether this one is the one to fail.
+std::mutex g_fault_mu;
+std::string g_fault_env;
+int64_t g_fault_count = 0;
+
+bool fault_this_alloc() {
+  const char* e = std::getenv("VECKM_FAULT_ALLOC");
+  std::lock_guard<std::mutex> lk(g_fault_mu);
+  const std::string cur = e ? e : "";
+  if (cur != g_fault_env) {
+    g_fault_env = cur;
+    g_fault_count = 0;
+  }
+  const long long n = cur.empty() ? 0 : std::atoll(cur.c_str());
+  if (n <= 0) return false;
+  return ++g_fault_count == n;
+}
 }  // namespace
+
+bool veckm::dev_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_this_alloc()) return false;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
+
+bool veckm::pinned_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_this_alloc()) return false;
+  if (hipHostMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
 
 struct veckm_ctx {
   veckm_params p{};
@@ -79,10 +121,7 @@ template <typename T>
 int dalloc(std::vector<void*>& list, T** out, size_t count) {
   void* p = nullptr;
   if (count == 0) count = 1;
-  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    return VECKM_E_NOMEM;
-  }
+  if (!dev_malloc(&p, count * sizeof(T))) return VECKM_E_NOMEM;
   list.push_back(p);
   *out = static_cast<T*>(p);
   return VECKM_OK;
@@ -557,8 +596,8 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     c->pt.rx = params->rx;
     c->pt.ry = params->ry;
   }
-  if (!rc && hipHostMalloc(reinterpret_cast<void**>(&c->table_host),
-                           (size_t)kRing * c->max_slices * sizeof(SliceDesc)) != hipSuccess) {
+  if (!rc && !pinned_malloc(reinterpret_cast<void**>(&c->table_host),
+                            (size_t)kRing * c->max_slices * sizeof(SliceDesc))) {
     c->table_host = nullptr;
     rc = VECKM_E_NOMEM;
   }
@@ -843,7 +882,7 @@ int veckm_graph_create(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
   if (rc) return rc;
   veckm_graph* gr = new veckm_graph;
   gr->ctx = ctx;
-  if (hipMalloc(&gr->table, tab.size() * sizeof(SliceDesc)) != hipSuccess) {
+  if (!dev_malloc(reinterpret_cast<void**>(&gr->table), tab.size() * sizeof(SliceDesc))) {
     (void)hipGetLastError();
     gr->table = nullptr;
     veckm_graph_destroy(gr);

@@ -165,7 +165,7 @@ int take_flight(veckm_server* s, InFlight* f) {
         if (x) (void)hipEventDestroy(x);
       return VECKM_E_HIP;
     }
-  if (hipHostMalloc(reinterpret_cast<void**>(&g.err), sizeof(int32_t)) != hipSuccess) {
+  if (!pinned_malloc(reinterpret_cast<void**>(&g.err), sizeof(int32_t))) {
     for (hipEvent_t x : {g.copied, g.computed, g.done}) (void)hipEventDestroy(x);
     return VECKM_E_NOMEM;
   }
@@ -385,9 +385,8 @@ int veckm_server_create(const veckm_params* params, int64_t hbm_budget_bytes, in
   if (!rc && hipGetDevice(&s->device) != hipSuccess) rc = VECKM_E_HIP;
   const size_t nev = (size_t)std::max<int64_t>(p.max_events, 1);
   for (int l = 0; !rc && l < kLanes; ++l) {
-    if (hipMalloc(reinterpret_cast<void**>(&s->ev_dev[l]), nev * sizeof(veckm_event)) !=
-            hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&s->flow_dev[l]), nev * 2 * sizeof(float)) != hipSuccess)
+    if (!dev_malloc(reinterpret_cast<void**>(&s->ev_dev[l]), nev * sizeof(veckm_event)) ||
+        !dev_malloc(reinterpret_cast<void**>(&s->flow_dev[l]), nev * 2 * sizeof(float)))
       rc = VECKM_E_NOMEM;
   }
   for (hipStream_t* st : {&s->stream, &s->h2d, &s->d2h})
@@ -464,10 +463,8 @@ int veckm_stream_open(veckm_server* s, int32_t width, int32_t height, int32_t ma
   Stream fresh;
   fresh.slots.resize((size_t)s->depth);
   for (Slot& sl : fresh.slots) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&sl.ev), (size_t)max_events * sizeof(veckm_event)) !=
-            hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&sl.flow), (size_t)max_events * 2 * sizeof(float)) !=
-            hipSuccess) {
+    if (!pinned_malloc(reinterpret_cast<void**>(&sl.ev), (size_t)max_events * sizeof(veckm_event)) ||
+        !pinned_malloc(reinterpret_cast<void**>(&sl.flow), (size_t)max_events * 2 * sizeof(float))) {
       (void)hipGetLastError();
       free_slots(fresh);
       return VECKM_E_NOMEM;

@@ -52,7 +52,7 @@ int veckm_trainer_create(int32_t d, int32_t hidden, int64_t max_rows, const floa
   s.max_splits = kMaxSplits;
   const int64_t np = (int64_t)hidden * s.k2 + 3 * (int64_t)hidden + 2;
   auto alloc = [](float** p, int64_t count) {
-    return hipMalloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(float)) == hipSuccess;
+    return dev_malloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(float));
   };
   bool ok = alloc(&s.theta, np) && alloc(&s.grad, np + 1) && alloc(&s.m1, np) &&
             alloc(&s.m2, np) && alloc(&s.H, max_rows * hidden) && alloc(&s.dZ, max_rows * hidden) &&

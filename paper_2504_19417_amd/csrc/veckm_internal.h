@@ -276,4 +276,14 @@ int ctx_take_err(veckm_ctx* c, int32_t* host, void* stream);
 // VECKM_OK, VECKM_E_OVERFLOW or VECKM_E_RANGE for a set of device error bits.
 int err_code(int32_t bits);
 
+// ------------------------------------------------- allocation (with a test hook)
+// Every device (hipMalloc) and pinned host (hipHostMalloc) allocation of the
+// library goes through these.  With the environment variable
+// VECKM_FAULT_ALLOC=n (n >= 1) the n-th allocation counted from the moment the
+// variable took that value fails as if the device were out of memory, so the
+// error paths that unwind a half-built object can be exercised; unset or 0:
+// no fault.  Each returns true on success and leaves *p null on failure.
+bool dev_malloc(void** p, size_t bytes);
+bool pinned_malloc(void** p, size_t bytes);
+
 }  // namespace veckm

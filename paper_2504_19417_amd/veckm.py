@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libveckm.so")
+# VECKM_LIB names another build of the same library (the host-sanitizer
+# build of the checks); by default the in-tree build.
+LIB_PATH = os.environ.get("VECKM_LIB") or os.path.join(_HERE, "_lib", "libveckm.so")
 
 VECKM_OK = 0
 VECKM_E_INVAL = -1
