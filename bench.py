@@ -46,6 +46,13 @@ def mlp_flops_per_row(d, hidden):
     return 2 * (2 * d) * hidden + 2 * hidden * 2
 
 
+def encode_stage_flops_per_row(K, d, hidden, stages):
+    """Algorithmic flops per row of the encode stage: the encoder's, plus the
+    perceptron's when the encoder ran it itself (no perceptron stage timed)."""
+    fused = stages.get("mlp") is None
+    return encoder_flops_per_row(K, d) + (mlp_flops_per_row(d, hidden) if fused else 0), fused
+
+
 def paper_encode_bytes(W, H, T, d, rows, row_bytes):
     """Algorithmic HBM bytes of the paper form's encode stage (no temporal
     bound): the temporal phase pass reads the T x H x W count grid and writes
@@ -733,11 +740,13 @@ def batch_main(args):
     # the encoder (the dominant kernel) against the fp16 matrix-core peak
     K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
     r16 = res["fp16"]
-    achieved = encoder_flops_per_row(K, w.d) * r16["rows"] / (r16["stages"]["encode"] * 1e-3) / 1e12
+    fpr, fused = encode_stage_flops_per_row(K, w.d, w.hidden, r16["stages"])
+    achieved = fpr * r16["rows"] / (r16["stages"]["encode"] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["fp16_TFLOPs"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp16_TFLOPs"], 4),
                 "traffic": None, "kernel": "k_encode<2", "avg_launch_ms": r16["stages"]["encode"],
-                "rows_per_launch": r16["rows"], "flops_per_row": encoder_flops_per_row(K, w.d)}
+                "rows_per_launch": r16["rows"], "flops_per_row": fpr,
+                "perceptron_in_encoder": fused}
     line = {
         "metric": "normal flows/sec, 64-slice batch in one launch sequence (BF16 perceptron)",
         "value": res["fp16"]["value"], "unit": "flows/s", "n_gpus": 1, "steps": args.steps,
@@ -787,7 +796,8 @@ def precision_main(args):
     vs32 = float(np.linalg.norm(f16 - f32) / np.linalg.norm(f32))
     K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
     rows = res["fp16"]["rows"]
-    achieved = encoder_flops_per_row(K, w.d) * rows / (st16["encode"] * 1e-3) / 1e12
+    fpr, fused = encode_stage_flops_per_row(K, w.d, w.hidden, st16)
+    achieved = fpr * rows / (st16["encode"] * 1e-3) / 1e12
     line = {
         "metric": "normal flows/sec, precision form (FP16 grid, BF16 perceptron) at 5M events",
         "value": n * args.steps / res["fp16"]["elapsed"], "unit": "flows/s", "n_gpus": 1,
@@ -810,7 +820,8 @@ def precision_main(args):
                      "peak": PEAK["fp16_TFLOPs"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK["fp16_TFLOPs"], 4), "traffic": None,
                      "kernel": "k_encode<2", "avg_launch_ms": st16["encode"],
-                     "rows_per_launch": rows, "flops_per_row": encoder_flops_per_row(K, w.d)},
+                     "rows_per_launch": rows, "flops_per_row": fpr,
+                     "perceptron_in_encoder": fused},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
@@ -967,13 +978,17 @@ def main():
     rows = res["fp32"]["rows"]
 
     # dominant kernel of the FP32 form, from the live per-stage event times
+    # (the encoder, which also runs the perceptron when no perceptron stage
+    # was timed)
+    fpr, fused = encode_stage_flops_per_row(K, w.d, w.hidden, st32)
     cand = {
-        "encode": dict(ms=st32["encode"], flops=encoder_flops_per_row(K, w.d) * rows,
+        "encode": dict(ms=st32["encode"], flops=fpr * rows,
                        peak=PEAK["fp16_TFLOPs"], kernel="k_encode<4"),
-        # FP32-form perceptron: fp16 hi/lo operand pairs on the fp16 matrix cores
-        "mlp": dict(ms=st32["mlp"], flops=mlp_flops_per_row(w.d, w.hidden) * rows,
-                    peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_res<2"),
     }
+    if not fused:
+        # FP32-form perceptron: fp16 hi/lo operand pairs on the fp16 matrix cores
+        cand["mlp"] = dict(ms=st32["mlp"], flops=mlp_flops_per_row(w.d, w.hidden) * rows,
+                           peak=PEAK["fp16_TFLOPs"], kernel="k_mlp_res<2")
     dom = max(cand, key=lambda k: cand[k]["ms"])
     c = cand[dom]
     achieved = c["flops"] / (c["ms"] * 1e-3) / 1e12
@@ -981,7 +996,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / c["peak"], 4),
                 "traffic": load_traffic(c["kernel"]), "kernel": c["kernel"],
                 "avg_launch_ms": round(c["ms"], 4), "rows_per_launch": rows,
-                "flops_per_row": c["flops"] // rows,
+                "flops_per_row": c["flops"] // rows, "perceptron_in_encoder": fused,
                 "clock": "HIP events around the kernel's launch on its stream"}
     # the same figure from the committed rocprofv3 kernel trace of this source
     pms = profiled_ms("slice1m", c["kernel"])

@@ -260,22 +260,33 @@ void veckm_graph_destroy(veckm_graph* graph);
    The encoder cuts every slice into bricks of voxels and streams the phase
    table through LDS a few slabs deep (the count box of a brick and the slabs
    share the 160 KB of LDS).  A context offers a small set of tilings (brick
-   shape x buffered slabs x wave layout): index 0 is the default (the largest
-   brick that fits beside two slabs, as many slabs as fit), the others larger
-   bricks with fewer slabs, which pay off where bricks hold few query voxels
-   (sparse slices), and each of those with fewer, wider waves.  Results do not depend on the tiling (bit-identical);
-   only the time does.
+   shape x buffered slabs x wave layout): the largest brick that fits beside
+   two slabs (as many slabs as fit), larger bricks with fewer slabs, which
+   pay off where bricks hold few query voxels (sparse slices), and each of
+   those with other wave layouts.  At D = 64 and 128 index 0 is the default
+   brick in wave layout 3, whose encoder also runs the perceptron (flow
+   calls keep every encoding on the chip); elsewhere index 0 is the default
+   brick in layout 0.  Encodings do not depend on the tiling (bit-identical);
+   flows are bit-identical among layouts 0 and 1 and among layouts 2 and 3,
+   and agree between the two groups to fp32 rounding (the perceptron's sums
+   run in another order).
      veckm_tiling_count     number of tilings (>= 1), or VECKM_E_INVAL
      veckm_tiling_selected  index in use, or VECKM_E_INVAL
      veckm_tiling_info      info[0..4] = brick x, y, t sides, slabs and wave
                             layout (0: 16 waves of 2 row tiles; 1: 8 waves
                             of 4 row tiles, each table fragment feeding
-                            twice the products) of tiling `index` (host
-                            int32[5])
+                            twice the products; 2: 4 waves of 4 row tiles
+                            and 3: 8 waves of 2 row tiles, each wave over
+                            every frequency of its rows, loads pipelined
+                            within the wave, one slab in flight, the
+                            perceptron inside the encoder at D = 64 and 128)
+                            of tiling `index` (host int32[5])
      veckm_tiling_select    use tiling `index` from the next call on
      veckm_tune             times every tiling on the given batch (as for
-                            veckm_encode_batch: the front end and the encoder,
-                            one untimed and `reps` timed runs each, 1 <= reps
+                            veckm_flow_batch when a perceptron is set, else
+                            veckm_encode_batch: the front end, the encoder
+                            and the perceptron, one untimed and `reps` timed
+                            runs each, 1 <= reps
                             <= 100, HIP events on `stream`), selects the
                             fastest for the calls that follow and writes its
                             index to *chosen (may be NULL).  Synchronises

@@ -194,6 +194,8 @@ int64_t bytes_for(const veckm_params* p, const std::vector<Tiling>& tl, int kp, 
   bytes += 64 * 4 + 4 + 64 * 4;                   // plan, err, zero page
   bytes += (int64_t)kRing * slices_of(p) * (int64_t)sizeof(SliceDesc);  // slice tables
   bytes += (int64_t)hidden * (2 * p->d) * 10 + hidden * 12 + 8;  // perceptron (fp32, bf16, fp16 hi/lo W1)
+  if (p->rt >= 0 && (p->d == 64 || p->d == 128))  // W1 in the fused encoder's slab order
+    bytes += (int64_t)hidden * (2 * p->d) * (na / 2) * 2;
   return bytes;
 }
 
@@ -358,7 +360,11 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
   // a window's encode: ev holds the query events, the counts are resident
   if (bt.m == 0) return VECKM_OK;
   // rows the encoder hands to the perceptron (encodings handed out are fp32)
+  // (the one-wave-per-SIMD tiling runs the perceptron itself: no rows at all)
+  const bool fused = flow && !c->paper && c->mw.W1frag && encode_fusable(c->et, c->mw.hidden);
   const int rows = !flow                             ? kRowsF32
+                   : fused                            ? (c->p.precision == VECKM_FP16 ? kFlowBF16
+                                                                                      : kFlowHiLo16)
                    : c->p.precision == VECKM_FP16     ? kRowsBF16
                    : !mlp_rows_split(c->p.d, c->mw.hidden) ? kRowsF32
                    : c->paper                          ? kRowsSplit16
@@ -380,19 +386,21 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
   }
   {
     StageTimer t(c, VECKM_STAGE_ENCODE, stream);
-    // the encoder writes fp32 rows unless the perceptron takes bf16 or hi/lo rows
-    const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 ? rows : kRowsF32;
+    // the encoder writes fp32 rows unless the perceptron takes bf16 or hi/lo
+    // rows, or runs inside the encoder
+    const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 || fused ? rows : kRowsF32;
     const int rc = c->paper ? launch_paper_encode(bt, w, c->pt, c->et.brick, erows, c->num_cus, stream)
                             : launch_encode(bt, w, c->et, erows, clear && !queries,
                                             c->num_cus, stream,
                                             counts ? reinterpret_cast<int32_t*>(w.rowflow)
-                                                   : nullptr);
+                                                   : nullptr,
+                                            &c->mw);
     if (rc) {
       if (clear) (void)launch_clear_counts(bt, w, stream);
       return rc;
     }
   }
-  if (flow) {
+  if (flow && !fused) {
     StageTimer t(c, VECKM_STAGE_MLP, stream);
     const int rc = launch_mlp(w, c->mw, c->p.d, rows, c->num_cus, stream);
     if (rc) {
@@ -711,6 +719,23 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
   ctx->mw.b1 = db1;
   ctx->mw.W2 = dW2;
   ctx->mw.b2 = db2;
+  // W1 in the slab order of the encoder that runs the perceptron itself
+  // (the one-wave-per-SIMD tiling at D = 64 or 128)
+  const int nt = ctx->p.d / 16;
+  if (!ctx->paper && (nt == 4 || nt == 8)) {
+    const std::vector<uint16_t> wf = make_w1_fragments(W1, hidden, ctx->p.d, ctx->et.na, shift);
+    uint16_t* dwf = nullptr;
+    rc = dalloc(ctx->mlp_allocs, &dwf, wf.size());
+    if (rc) {
+      ctx->mw = MlpWeights{};
+      return rc;
+    }
+    if (hipMemcpy(dwf, wf.data(), wf.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
+      ctx->mw = MlpWeights{};
+      return VECKM_E_HIP;
+    }
+    ctx->mw.W1frag = dwf;
+  }
   return VECKM_OK;
 }
 
@@ -962,16 +987,21 @@ int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
     if (e0) (void)hipEventDestroy(e0);
     return VECKM_E_HIP;
   }
-  // the rows the flow path would write (the epilogue differs, the work not)
-  const int rows = ctx->p.precision == VECKM_FP16 ? kRowsBF16
-                   : ctx->mw.hidden > 0 && mlp_rows_split(ctx->p.d, ctx->mw.hidden)
-                       ? kRowsHiLo16
-                       : kRowsF32;
+  // the rows the flow path would write (the epilogue differs, the work not);
+  // with a perceptron set, each tiling is timed with the perceptron as a flow
+  // call runs it (inside the encoder where the tiling allows, else after it)
+  const bool with_mlp = ctx->mw.hidden > 0;
+  const int split_rows = ctx->p.precision == VECKM_FP16 ? kRowsBF16
+                         : with_mlp && mlp_rows_split(ctx->p.d, ctx->mw.hidden)
+                             ? kRowsHiLo16
+                             : kRowsF32;
   const int prev = ctx->tiling;
   int best = -1, rc = VECKM_OK;
   float best_ms = 0.f;
   for (int i = 0; !rc && i < (int)ctx->tilings.size(); ++i) {
     ctx->et = ctx->tilings[(size_t)i];
+    const bool fused = with_mlp && ctx->mw.W1frag && encode_fusable(ctx->et, ctx->mw.hidden);
+    const int rows = fused ? (ctx->p.precision == VECKM_FP16 ? kFlowBF16 : kFlowHiLo16) : split_rows;
     for (int r = 0; !rc && r <= reps; ++r) {  // one untimed run, then reps timed
       if (r == 1 && hipEventRecord(e0, s) != hipSuccess) rc = VECKM_E_HIP;
       Batch bt;
@@ -981,7 +1011,11 @@ int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
       if (!rc && bt.m > 0) {
         // (the encoder returns the counts to zero, as in a batch call)
         rc = launch_prepare(bt, ctx->w, events, nullptr, ctx->et, true, stream);
-        if (!rc) rc = launch_encode(bt, ctx->w, ctx->et, rows, true, ctx->num_cus, stream);
+        if (!rc)
+          rc = launch_encode(bt, ctx->w, ctx->et, rows, true, ctx->num_cus, stream, nullptr,
+                             &ctx->mw);
+        if (!rc && with_mlp && !fused)
+          rc = launch_mlp(ctx->w, ctx->mw, ctx->p.d, rows, ctx->num_cus, stream);
         if (rc) (void)launch_clear_counts(bt, ctx->w, stream);
       }
       const int rc2 = release_slot(ctx, slot, stream);

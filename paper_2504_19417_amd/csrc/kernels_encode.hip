@@ -57,7 +57,20 @@ struct EncArgs {
   void* rows;
   int32_t* plan;
   int32_t* rowcnt;  // per-row neighbour counts, or NULL
+  // the perceptron, when the encoder runs it (kFlow* rows)
+  const uint4* w1frag;  // hidden / 32 slabs (make_w1_fragments)
+  int msteps;           // hidden / 32
+  int hidden;
+  float unscale;        // 2^-shift of the hi/lo W1
+  const float* b1;
+  const float* W2;
+  const float* b2;
+  float2* rowflow;      // one flow per row
 };
+
+__host__ __device__ constexpr bool fused_rows(int rows) { return rows == kFlowBF16 || rows == kFlowHiLo16; }
+// LDS bytes of the perceptron's constants (b1 and both rows of W2)
+__host__ __device__ constexpr size_t mlp_lds_bytes(int hidden) { return (size_t)hidden * 12; }
 
 __device__ inline half8 as_half8(uint4 u) {
   half8 h;
@@ -100,8 +113,12 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 // s_waitcnt immediate (gfx9 encoding) waiting until at most n vector memory
 // operations are outstanding; expcnt and lgkmcnt are left unconstrained.
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+// ... and until at most n (<= 15) LDS operations are outstanding (vmcnt and
+// expcnt unconstrained).
+constexpr int lgkmcnt_imm(int n) { return 15 | (3 << 14) | (7 << 4) | ((n & 15) << 8); }
 
-// Waves per block and the most 16-frequency tiles one wave holds.
+// Waves per block and the most 16-frequency tiles one wave holds (layouts 0
+// and 1; layout 2 holds up to 8).
 constexpr int kEncWaves = 16;
 constexpr int kEncMaxNtw = 4;
 // 16-row tiles each wave holds per chunk.
@@ -115,15 +132,23 @@ __host__ __device__ constexpr size_t slice_table_offset(size_t bytes) { return (
 // Wave layouts of the encoder block: 0 = 16 waves (4 per SIMD) of kEncMt
 // row tiles each; 1 = 8 waves (2 per SIMD) of 2 kEncMt row tiles each
 // (every table fragment read from LDS feeds twice the products; half the
-// waves to hide latency).
-constexpr int enc_waves(int L) { return L == 0 ? kEncWaves : kEncWaves / 2; }
-constexpr int enc_mt(int L) { return L == 0 ? kEncMt : 2 * kEncMt; }
+// waves to hide latency); 2 = 4 waves (one per SIMD) of 2 kEncMt row tiles
+// over up to 8 frequency tiles (128 frequencies: every count gather feeds
+// all of a row's frequencies, every table fragment four row tiles; the
+// accumulators take the register file's accumulation half).
+constexpr int enc_waves(int L) {
+  return L == 0 ? kEncWaves : L == 1 ? kEncWaves / 2 : L == 2 ? kEncWaves / 4 : kEncWaves / 2;
+}
+constexpr int enc_mt(int L) { return L == 0 || L == 3 ? kEncMt : 2 * kEncMt; }
+constexpr int enc_max_ntw(int L) { return L >= 2 ? 2 * kEncMaxNtw : kEncMaxNtw; }
+// layouts whose k-steps are software-pipelined within each wave
+constexpr bool enc_pipelined(int L) { return L >= 2; }
 
 template <int NA, int NT, int L>
 struct EncShape {
   static constexpr int NW = enc_waves(L);       // waves per block
-  static constexpr int NTW = NT < kEncMaxNtw ? NT : kEncMaxNtw;  // frequency tiles per wave
-  static constexpr int WN = NT / NTW;           // waves across frequencies (2 at D = 128, 4 at D = 256)
+  static constexpr int NTW = NT < enc_max_ntw(L) ? NT : enc_max_ntw(L);  // frequency tiles per wave
+  static constexpr int WN = NT / NTW;           // waves across frequencies (layouts 0, 1: 2 at D = 128, 4 at D = 256)
   static constexpr int WM = NW / WN;            // waves across rows
   static constexpr int MT = enc_mt(L);          // 16-row tiles per wave
   static constexpr int CH = WM * MT * 16;       // rows per chunk
@@ -137,11 +162,12 @@ struct EncShape {
 // moves 1 KB pieces.
 template <int SLAB_U4, int NW>
 __device__ inline void issue_slab(const uint4* src, uint4* dst, int wid, int lane) {
+  const uint32_t voff = (uint32_t)lane * 16;
 #pragma unroll
   for (int u = 0; u < (SLAB_U4 + NW * 64 - 1) / (NW * 64); ++u) {
     const int base = u * NW * 64 + wid * 64;
     if (SLAB_U4 % (NW * 64) == 0 || base < SLAB_U4)
-      copy_to_lds16(src + base + lane, lds_offset(dst + base));
+      copy_to_lds16_s(src + base, voff, lds_offset(dst + base));
   }
 }
 
@@ -168,7 +194,10 @@ struct CountWords {
   uint32_t P[MTV > 0 ? MTV : 1][4], Q[MTV > 0 ? MTV : 1][4];
   __device__ inline void fetch(const int32_t* runs_l, const uint32_t* vol2, const int* rb, int ks,
                                int g) {
-    const int2 ro = *reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2);
+    fetch_at(*reinterpret_cast<const int2*>(runs_l + (ks * 4 + g) * 2), vol2, rb);
+  }
+  // the words of the two runs starting at box offsets ro.x and ro.y
+  __device__ inline void fetch_at(int2 ro, const uint32_t* vol2, const int* rb) {
 #pragma unroll
     for (int mt = 0; mt < MTV; ++mt) {
       const uint32_t* p0 = vol2 + (rb[mt] + ro.x);
@@ -338,6 +367,301 @@ __device__ inline void chunk_ksteps_n(int mtv, int nsteps, const uint4* frag, ui
   }
 }
 
+// ---- layout 2: software-pipelined k-steps (one wave per SIMD) -----------
+//
+// With one wave per SIMD nothing else hides a wave's LDS latency, so every
+// load is issued a stage ahead of its use: the count words of k-step ks + 1
+// (the box is resident for the whole brick) while step ks multiplies, and the
+// table fragments of frequency tile nt + kTfAhead while tile nt multiplies.
+// Each accumulator still receives exactly the products of layouts 0 and 1 in
+// the same order, so the results are bit-identical to theirs.
+constexpr int kTfAhead = 1;  // frequency tiles of table fragments in flight
+
+// Pair sums and differences of one k-step's count words (see kstep_compute).
+template <int MTV>
+__device__ inline void pair_sums(const CountWords<MTV>& cw, half8 (&cS)[MTV > 0 ? MTV : 1],
+                                 half8 (&cD)[MTV > 0 ? MTV : 1]) {
+#pragma unroll
+  for (int mt = 0; mt < MTV; ++mt) {
+    uint4 s4, d4;
+    s4.x = pk_sum_swapped(cw.P[mt][0], cw.Q[mt][0]);
+    s4.y = pk_sum_swapped(cw.P[mt][1], cw.Q[mt][1]);
+    s4.z = pk_sum_swapped(cw.P[mt][2], cw.Q[mt][2]);
+    s4.w = pk_sum_swapped(cw.P[mt][3], cw.Q[mt][3]);
+    d4.x = pk_diff_swapped(cw.P[mt][0], cw.Q[mt][0]);
+    d4.y = pk_diff_swapped(cw.P[mt][1], cw.Q[mt][1]);
+    d4.z = pk_diff_swapped(cw.P[mt][2], cw.Q[mt][2]);
+    d4.w = pk_diff_swapped(cw.P[mt][3], cw.Q[mt][3]);
+    cS[mt] = as_half8(s4);
+    cD[mt] = as_half8(d4);
+  }
+}
+
+// What the fused perceptron needs inside a chunk (kFlow* rows).
+struct FuseArgs {
+  const uint4* w1frag;  // slabs of W1 fragments, after the table's k-steps
+  int msteps;           // W1 slabs: two hidden tiles of 16 units each
+  float unscale;
+  const float* mlp_l;   // LDS: b1[hidden], W2[0][hidden], W2[1][hidden]
+  int hidden;
+  float b20, b21;
+  float2* out;          // rowflow
+  int row_first;        // row index of the chunk's first row
+  int nr;               // rows in the chunk
+  int wm;               // this wave's row group
+};
+
+typedef __bf16 bf16x8_e __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+  return f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
+}
+
+// Source of step `st` of a chunk's slab sequence: the table's k-steps, then
+// (fused) the W1 slabs.
+template <int SLAB_U4>
+__device__ inline const uint4* step_src(const uint4* frag, const uint4* w1frag, int nsteps, int st) {
+  return st < nsteps ? frag + (size_t)st * SLAB_U4 : w1frag + (size_t)(st - nsteps) * SLAB_U4;
+}
+
+template <int NA, int NT, int L, int NBUF, int MTV, bool FUSE>
+__device__ inline void chunk_ksteps_p(int nsteps, const uint4* frag, uint4* slab,
+                                      const int32_t* runs_l, const uint16_t* wts_l,
+                                      const uint32_t* vol2, const int (&rb)[EncShape<NA, NT, L>::MT],
+                                      floatx4 (&accR)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                      floatx4 (&accI)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                      float (&cnt)[EncShape<NA, NT, L>::MT], int wn, int wid,
+                                      int lane, const FuseArgs& fz) {
+  using S = EncShape<NA, NT, L>;
+  constexpr int NW = S::NW, NTW = S::NTW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW, WM = S::WM;
+  constexpr int AHEAD = NBUF - 1;
+  constexpr int TA = kTfAhead < NTW ? kTfAhead : NTW - 1;
+  const int g = lane >> 4;
+  const int total = FUSE ? nsteps + fz.msteps : nsteps;  // slabs through the ring
+  const int2* runs2 = reinterpret_cast<const int2*>(runs_l);
+  static_assert(NBUF == 2, "the pipelined layout keeps one slab in flight");
+  CountWords<MTV> cw;
+  int2 ro_next = make_int2(0, 0);
+  if constexpr (MTV > 0) {
+    cw.fetch_at(runs2[g], vol2, rb);
+    if (nsteps > 1) ro_next = runs2[4 + g];
+  }
+  for (int ks = 0; ks < nsteps; ++ks) {
+    // Nothing of this wave is in flight here (with two slab buffers each step
+    // ends waiting for the next slab), so this wait costs nothing; it tells
+    // the compiler's wait insertion, which does not see the slab copies, that
+    // loads it placed before the loop (spill reloads) are complete, instead of
+    // a full wait after the copies below on every step.
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    // the slab AHEAD steps out: its buffer was last read in step ks - 1
+    if (ks + AHEAD < total)
+      issue_slab<SLAB_U4, NW>(step_src<SLAB_U4>(frag, fz.w1frag, nsteps, ks + AHEAD),
+                              slab + ((ks + AHEAD) % NBUF) * SLAB_U4, wid, lane);
+    if constexpr (MTV > 0) {
+      const uint4* sb = slab + (ks % NBUF) * SLAB_U4;
+      const half8 bw = *reinterpret_cast<const half8*>(wts_l + ks * 32 + 8 * g);
+      half8 cS[MTV], cD[MTV];
+      pair_sums<MTV>(cw, cS, cD);
+      // LDS reads complete in the order they were issued (and a wait can
+      // leave at most 15 of them outstanding), so the next step's count
+      // words are gathered only once this step's last table fragments have
+      // landed, just before the last frequency tile's products, which then
+      // cover their latency; issued earlier, they would hold up every table
+      // fragment behind them
+      auto gather_next = [&]() {
+        if (ks + 1 < nsteps) {
+          cw.fetch_at(ro_next, vol2, rb);
+          if (ks + 2 < nsteps) ro_next = runs2[(ks + 2) * 4 + g];
+        }
+      };
+      // table fragments kTfAhead frequency tiles ahead of the products
+      half8 tf[TA + 1][NA];
+#pragma unroll
+      for (int u = 0; u < TA; ++u)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) tf[u][q] = as_half8(sb[(q * NT + wn * NTW + u) * 64 + lane]);
+#pragma unroll
+      for (int nt = 0; nt < NTW; ++nt) {
+        if (nt + TA < NTW)
+#pragma unroll
+          for (int q = 0; q < NA; ++q)
+            tf[(nt + TA) % (TA + 1)][q] = as_half8(sb[(q * NT + wn * NTW + nt + TA) * 64 + lane]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (nt == NTW - 1) {
+          __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));  // the last fragments (requested a tile ago)
+          gather_next();
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        const half8* t = tf[nt % (TA + 1)];
+#pragma unroll
+        for (int mt = 0; mt < MTV; ++mt) {
+          if constexpr (NA == 4) {
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[0], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[2], cD[mt], accI[mt][nt], 0, 0, 0);
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[1], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[3], cD[mt], accI[mt][nt], 0, 0, 0);
+          } else {
+            accR[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[0], cS[mt], accR[mt][nt], 0, 0, 0);
+            accI[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(t[1], cD[mt], accI[mt][nt], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          cnt[mt] = __builtin_amdgcn_fdot2(half2v{bw[2 * e], bw[2 * e + 1]},
+                                           half2v{cS[mt][2 * e], cS[mt][2 * e + 1]}, cnt[mt], false);
+    }
+    // the slab of step ks + 1 has landed (later ones may stay in flight)
+    const int last = ks + AHEAD < total - 1 ? ks + AHEAD : total - 1;
+    wait_slabs<PFW>(last - ks - 1 > 0 ? last - ks - 1 : 0);
+    lds_barrier();
+  }
+  if constexpr (FUSE) {
+    // ---- the perceptron on the chunk's rows, still in registers (Sec. 2.1,
+    //      Eqns. 5-6): x = [Re emb | Im emb] as the B operand of layer 1,
+    //      W1 from the slabs that follow the table's, ReLU and layer 2 on the
+    //      vector ALU.  The lane holds features 16 nt + 4 g + (0..3) of row
+    //      lane & 15; layer-1 step kk takes frequency tiles 2kk' and 2kk' + 1
+    //      (real parts for kk < NT / 2, imaginary parts above), the order the
+    //      W1 fragments were laid out in.
+    static_assert(S::WN == 1, "the fused perceptron needs every frequency of a row in one wave");
+    constexpr int TERMS = NA / 2;
+    constexpr int KK = NT;  // 32-feature steps of layer 1
+    uint4 xh[MTV > 0 ? MTV : 1][KK], xl[TERMS == 2 && MTV > 0 ? MTV : 1][TERMS == 2 ? KK : 1];
+    float p0[MTV > 0 ? MTV : 1], p1[MTV > 0 ? MTV : 1];
+    if constexpr (MTV > 0) {
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt) {
+        float n = cnt[mt];
+        n += __shfl_xor(n, 16);
+        n += __shfl_xor(n, 32);
+        const float rc = __builtin_amdgcn_rcpf(n);
+        // x / n as the encoder's rows are (exact for x = n; 0 without neighbours)
+        auto div = [n, rc](float x) {
+          const float qq = x * rc;
+          return n > 0.f ? fmaf(fmaf(-qq, n, x), rc, qq) : 0.f;
+        };
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+          const int t0 = 2 * (kk % (NT / 2));
+          const floatx4 a0 = kk < NT / 2 ? accR[mt][t0] : accI[mt][t0];
+          const floatx4 a1 = kk < NT / 2 ? accR[mt][t0 + 1] : accI[mt][t0 + 1];
+          const float v[8] = {div(a0[0]), div(a0[1]), div(a0[2]), div(a0[3]),
+                              div(a1[0]), div(a1[1]), div(a1[2]), div(a1[3])};
+          if constexpr (TERMS == 2) {
+            half8 h, l;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              h[e] = (_Float16)v[e];
+              l[e] = (_Float16)(v[e] - (float)h[e]);
+            }
+            __builtin_memcpy(&xh[mt][kk], &h, 16);
+            __builtin_memcpy(&xl[mt][kk], &l, 16);
+          } else {
+            xh[mt][kk] = make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]),
+                                    pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7]));
+          }
+        }
+        p0[mt] = 0.f;
+        p1[mt] = 0.f;
+      }
+    }
+    for (int ms = 0; ms < fz.msteps; ++ms) {
+      const int st = nsteps + ms;
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));  // as in the k-steps: nothing in flight here
+      if (st + AHEAD < total)
+        issue_slab<SLAB_U4, NW>(step_src<SLAB_U4>(frag, fz.w1frag, nsteps, st + AHEAD),
+                                slab + ((st + AHEAD) % NBUF) * SLAB_U4, wid, lane);
+      if constexpr (MTV > 0) {
+        const uint4* sb = slab + (st % NBUF) * SLAB_U4;
+#pragma unroll
+        for (int tile = 0; tile < 2; ++tile) {
+          floatx4 h[MTV];
+#pragma unroll
+          for (int mt = 0; mt < MTV; ++mt) h[mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kk = 0; kk < KK; ++kk) {
+            const uint4 wh = sb[(tile * NT + kk) * 64 + lane];
+            if constexpr (TERMS == 2) {
+              const uint4 wl = sb[((2 + tile) * NT + kk) * 64 + lane];
+#pragma unroll
+              for (int mt = 0; mt < MTV; ++mt) {
+                h[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(wh), as_half8(xh[mt][kk]), h[mt], 0, 0, 0);
+                h[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(wl), as_half8(xh[mt][kk]), h[mt], 0, 0, 0);
+                h[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_half8(wh), as_half8(xl[mt][kk]), h[mt], 0, 0, 0);
+              }
+            } else {
+              bf16x8_e wb;
+              __builtin_memcpy(&wb, &wh, 16);
+#pragma unroll
+              for (int mt = 0; mt < MTV; ++mt) {
+                bf16x8_e xb;
+                __builtin_memcpy(&xb, &xh[mt][kk], 16);
+                h[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb, xb, h[mt], 0, 0, 0);
+              }
+            }
+          }
+          // layer 2: the lane holds hidden units 16 (2 ms + tile) + 4 g + i
+          const int u0 = (2 * ms + tile) * 16 + 4 * g;
+          const float4 bb = *reinterpret_cast<const float4*>(fz.mlp_l + u0);
+          const float4 wa = *reinterpret_cast<const float4*>(fz.mlp_l + fz.hidden + u0);
+          const float4 wb2 = *reinterpret_cast<const float4*>(fz.mlp_l + 2 * fz.hidden + u0);
+          const float bv[4] = {bb.x, bb.y, bb.z, bb.w}, w0[4] = {wa.x, wa.y, wa.z, wa.w},
+                      w1[4] = {wb2.x, wb2.y, wb2.z, wb2.w};
+#pragma unroll
+          for (int mt = 0; mt < MTV; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float hv = fmaxf(fmaf(h[mt][i], fz.unscale, bv[i]), 0.f);
+              p0[mt] = fmaf(w0[i], hv, p0[mt]);
+              p1[mt] = fmaf(w1[i], hv, p1[mt]);
+            }
+        }
+      }
+      const int last = st + AHEAD < total - 1 ? st + AHEAD : total - 1;
+      wait_slabs<PFW>(last - st - 1 > 0 ? last - st - 1 : 0);
+      lds_barrier();
+    }
+    // ---- one flow per row: the 4 lanes of a row hold partial sums
+    if constexpr (MTV > 0) {
+#pragma unroll
+      for (int mt = 0; mt < MTV; ++mt) {
+        float f0 = p0[mt], f1 = p1[mt];
+        f0 += __shfl_xor(f0, 16);
+        f1 += __shfl_xor(f1, 16);
+        f0 += __shfl_xor(f0, 32);
+        f1 += __shfl_xor(f1, 32);
+        const int r = (mt * WM + fz.wm) * 16 + (lane & 15);
+        if (lane < 16 && r < fz.nr) fz.out[fz.row_first + r] = make_float2(f0 + fz.b20, f1 + fz.b21);
+      }
+    }
+  }
+}
+
+template <int NA, int NT, int L, int NBUF, int M, bool FUSE>
+__device__ inline void chunk_ksteps_pn(int mtv, int nsteps, const uint4* frag, uint4* slab,
+                                       const int32_t* runs_l, const uint16_t* wts_l,
+                                       const uint32_t* vol2, const int (&rb)[EncShape<NA, NT, L>::MT],
+                                       floatx4 (&accR)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                       floatx4 (&accI)[EncShape<NA, NT, L>::MT][EncShape<NA, NT, L>::NTW],
+                                       float (&cnt)[EncShape<NA, NT, L>::MT], int wn, int wid,
+                                       int lane, const FuseArgs& fz) {
+  if constexpr (M == 0) {
+    chunk_ksteps_p<NA, NT, L, NBUF, 0, FUSE>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR, accI,
+                                             cnt, wn, wid, lane, fz);
+  } else {
+    if (mtv == M)
+      chunk_ksteps_p<NA, NT, L, NBUF, M, FUSE>(nsteps, frag, slab, runs_l, wts_l, vol2, rb, accR,
+                                               accI, cnt, wn, wid, lane, fz);
+    else
+      chunk_ksteps_pn<NA, NT, L, NBUF, M - 1, FUSE>(mtv, nsteps, frag, slab, runs_l, wts_l, vol2, rb,
+                                                    accR, accI, cnt, wn, wid, lane, fz);
+  }
+}
+
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 half4v __attribute__((ext_vector_type(4)));
 
@@ -360,9 +684,14 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
   // is two aligned dword reads.  Box rows are kRunPad voxels wider than the
   // halo on each side, so runs (padding slots included) stay inside a row.
   uint32_t* vol2 = reinterpret_cast<uint32_t*>(item + 4);
-  // the slice descriptors of a batch, when they fit
+  // the perceptron's b1 and W2 (fused rows), then the slice descriptors of a
+  // batch, when they fit
+  constexpr bool FUSE = fused_rows(ROWS);
+  static_assert(!FUSE || enc_pipelined(L), "the perceptron runs inside the pipelined layouts only");
+  const size_t base_bytes = NBUF * SLAB_U4 * 16 + a.nsteps * 32 * 3 + CH * 4 + 16 + a.vol * 4;
+  float* mlp_l = reinterpret_cast<float*>(smem + slice_table_offset(base_bytes));
   SliceDesc* stab = reinterpret_cast<SliceDesc*>(
-      smem + slice_table_offset(NBUF * SLAB_U4 * 16 + a.nsteps * 32 * 3 + CH * 4 + 16 + a.vol * 4));
+      smem + slice_table_offset(base_bytes + (FUSE ? mlp_lds_bytes(a.hidden) : 0)));
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -374,6 +703,13 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
   for (int k = tid; k < KP; k += NW * 64) wts_l[k] = a.wts[k];
   for (int k = tid; k < a.lds_slices * (int)(sizeof(SliceDesc) / 4); k += NW * 64)
     reinterpret_cast<int32_t*>(stab)[k] = reinterpret_cast<const int32_t*>(a.bt.table)[k];
+  if constexpr (FUSE) {
+    for (int k = tid; k < a.hidden; k += NW * 64) {
+      mlp_l[k] = a.b1[k];
+      mlp_l[a.hidden + k] = a.W2[k];
+      mlp_l[2 * a.hidden + k] = a.W2[a.hidden + k];
+    }
+  }
 
   // Work items come from a shared counter, in longest-first order, one
   // brick at a time (taking the next brick ahead of time upsets the balance
@@ -448,7 +784,7 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
         }
       }
       // first slabs of the table
-      if constexpr (kEncPairSteps && NBUF == 4) {
+      if constexpr (kEncPairSteps && NBUF == 4 && !enc_pipelined(L)) {
         // the first pair (and the box) has landed
 #pragma unroll
         for (int u = 0; u < 2; ++u)
@@ -456,11 +792,14 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
             issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
         __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
       } else {
+        // (fused rows: the W1 slabs follow the table's in the same ring)
+        const int steps = a.nsteps + (FUSE ? a.msteps : 0);
 #pragma unroll
         for (int u = 0; u < AHEAD; ++u)
-          if (u < a.nsteps)
-            issue_slab<SLAB_U4, NW>(a.frag + (size_t)u * SLAB_U4, slab + u * SLAB_U4, wid, lane);
-        wait_slabs<PFW>((a.nsteps < AHEAD ? a.nsteps : AHEAD) - 1);  // slab 0 (and the box) landed
+          if (u < steps)
+            issue_slab<SLAB_U4, NW>(step_src<SLAB_U4>(a.frag, a.w1frag, a.nsteps, u),
+                                    slab + u * SLAB_U4, wid, lane);
+        wait_slabs<PFW>((steps < AHEAD ? steps : AHEAD) - 1);  // slab 0 (and the box) landed
       }
       lds_barrier();
 
@@ -487,8 +826,25 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
           accI[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
       }
-      chunk_ksteps_n<NA, NT, L, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb, accR,
-                                       accI, cnt, wn, wid, lane);
+      if constexpr (enc_pipelined(L)) {
+        FuseArgs fz;
+        fz.w1frag = a.w1frag;
+        fz.msteps = FUSE ? a.msteps : 0;
+        fz.unscale = a.unscale;
+        fz.mlp_l = mlp_l;
+        fz.hidden = a.hidden;
+        fz.b20 = FUSE ? a.b2[0] : 0.f;
+        fz.b21 = FUSE ? a.b2[1] : 0.f;
+        fz.out = a.rowflow;
+        fz.row_first = row0 + c0;
+        fz.nr = nr;
+        fz.wm = wm;
+        chunk_ksteps_pn<NA, NT, L, NBUF, MT, FUSE>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2,
+                                                   rb, accR, accI, cnt, wn, wid, lane, fz);
+        if constexpr (FUSE) continue;  // flows written; no rows leave the chip
+      } else
+        chunk_ksteps_n<NA, NT, L, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb,
+                                            accR, accI, cnt, wn, wid, lane);
 
       // ---- normalise by the neighbour count and write the rows: the lane
       //      holds frequencies 16 nt + 4 (lane >> 4) + (0..3) of row lane & 15
@@ -574,7 +930,7 @@ static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
 // Rows per chunk and LDS bytes of the encoder for a given D and wave layout
 // (the host-side mirror of EncShape::CH).
 static int chunk_rows(int nt, int layout) {
-  const int ntw = nt < kEncMaxNtw ? nt : kEncMaxNtw, wn = nt / ntw;
+  const int ntw = nt < enc_max_ntw(layout) ? nt : enc_max_ntw(layout), wn = nt / ntw;
   const int wm = enc_waves(layout) / wn;
   return wm * enc_mt(layout) * 16;
 }
@@ -585,10 +941,11 @@ size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol, int layo
          16 + (size_t)vol * 4;
 }
 
-template <int NA, int NT, int L, int NBUF>
-static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
-                    hipStream_t s) {
+template <int NA, int NT, int L, int NBUF, int ROWS>
+static int launch_rows(const EncArgs& a, const EncodeTables& et, int num_cus, hipStream_t s) {
+  constexpr bool FUSE = fused_rows(ROWS);
   size_t lds = encode_lds_bytes<NA, NT, L, NBUF>(et, a.vol);
+  if (FUSE) lds = slice_table_offset(lds) + mlp_lds_bytes(a.hidden);
   if (lds > 160 * 1024) return VECKM_E_INVAL;
   // a batch's slice descriptors go to LDS when they fit beside the rest
   EncArgs b = a;
@@ -598,48 +955,66 @@ static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_
     b.lds_slices = a.bt.nslices;
     lds = with_tab;
   }
-  if (rows == kRowsHiLo16 && NA != 4) return VECKM_E_INVAL;  // hi/lo rows: the FP32 form only
-  constexpr int HL = NA == 4 ? kRowsHiLo16 : kRowsF32;
-  const void* fn =
-      rows == kRowsBF16     ? reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, kRowsBF16>)
-      : rows == kRowsHiLo16 ? reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, HL>)
-                            : reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, kRowsF32>);
+  const void* fn = reinterpret_cast<const void*>(&k_encode<NA, NT, L, NBUF, ROWS>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return VECKM_E_HIP;
   const int per_cu = (int)((160 * 1024) / lds);
   int grid = num_cus * (per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu));
   if (grid > b.bt.nbricks) grid = a.bt.nbricks;
   constexpr int threads = EncShape<NA, NT, L>::NW * 64;
-  if (rows == kRowsBF16)
-    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, kRowsBF16>), dim3(grid), dim3(threads), lds, s, b);
-  else if (rows == kRowsHiLo16)
-    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, HL>), dim3(grid), dim3(threads), lds, s, b);
-  else
-    hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, kRowsF32>), dim3(grid), dim3(threads), lds, s, b);
+  hipLaunchKernelGGL((k_encode<NA, NT, L, NBUF, ROWS>), dim3(grid), dim3(threads), lds, s, b);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+template <int NA, int NT, int L, int NBUF>
+static int launch_t(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
+                    hipStream_t s) {
+  if (rows == kRowsHiLo16 && NA != 4) return VECKM_E_INVAL;  // hi/lo rows: the FP32 form only
+  constexpr int HL = NA == 4 ? kRowsHiLo16 : kRowsF32;
+  if (fused_rows(rows)) {
+    // the perceptron inside the encoder: one wave holds all of a row's frequencies
+    if constexpr (enc_pipelined(L) && EncShape<NA, NT, L>::WN == 1) {
+      constexpr int FR = NA == 4 ? kFlowHiLo16 : kFlowBF16;
+      if (rows != FR) return VECKM_E_INVAL;
+      return launch_rows<NA, NT, L, NBUF, FR>(a, et, num_cus, s);
+    }
+    return VECKM_E_INVAL;
+  }
+  if (rows == kRowsBF16) return launch_rows<NA, NT, L, NBUF, kRowsBF16>(a, et, num_cus, s);
+  if (rows == kRowsHiLo16) return launch_rows<NA, NT, L, NBUF, HL>(a, et, num_cus, s);
+  return launch_rows<NA, NT, L, NBUF, kRowsF32>(a, et, num_cus, s);
 }
 
 static_assert(EncShape<4, 8, 0>::CH == 8 * kEncMt * 16 && EncShape<2, 16, 0>::CH == 4 * kEncMt * 16 &&
                   EncShape<4, 1, 0>::CH == 16 * kEncMt * 16 &&
-                  EncShape<4, 8, 1>::CH == 4 * 2 * kEncMt * 16,
+                  EncShape<4, 8, 1>::CH == 4 * 2 * kEncMt * 16 &&
+                  EncShape<4, 8, 2>::CH == 4 * 2 * kEncMt * 16 &&
+                  EncShape<2, 16, 2>::CH == 2 * 2 * kEncMt * 16,
               "chunk_rows mirrors EncShape");
 
 template <int NA, int NT, int L>
 static int launch_nb(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                      hipStream_t s) {
-  if constexpr (EncShape<NA, NT, L>::EVEN) {
-    if (et.nbuf == 4) return launch_t<NA, NT, L, 4>(a, et, rows, num_cus, s);
-    if (et.nbuf == 3) return launch_t<NA, NT, L, 3>(a, et, rows, num_cus, s);
+  if constexpr (enc_pipelined(L)) {  // the pipelined layouts keep one slab in flight
+    if (et.nbuf != 2) return VECKM_E_INVAL;
+    return launch_t<NA, NT, L, 2>(a, et, rows, num_cus, s);
+  } else {
+    if constexpr (EncShape<NA, NT, L>::EVEN) {
+      if (et.nbuf == 4) return launch_t<NA, NT, L, 4>(a, et, rows, num_cus, s);
+      if (et.nbuf == 3) return launch_t<NA, NT, L, 3>(a, et, rows, num_cus, s);
+    }
+    return launch_t<NA, NT, L, 2>(a, et, rows, num_cus, s);
   }
-  return launch_t<NA, NT, L, 2>(a, et, rows, num_cus, s);
 }
 
 template <int NA, int NT>
 static int launch_layout(const EncArgs& a, const EncodeTables& et, int rows, int num_cus,
                          hipStream_t s) {
-  // the 8-wave layout only where a wave holds several frequency tiles
+  // the 8- and 4-wave layouts only where a wave holds several frequency tiles
   if constexpr (NT >= 4) {
     if (et.layout == 1) return launch_nb<NA, NT, 1>(a, et, rows, num_cus, s);
+    if (et.layout == 2) return launch_nb<NA, NT, 2>(a, et, rows, num_cus, s);
+    if (et.layout == 3) return launch_nb<NA, NT, 3>(a, et, rows, num_cus, s);
   }
   return launch_nb<NA, NT, 0>(a, et, rows, num_cus, s);
 }
@@ -661,10 +1036,38 @@ static int dispatch_nt(const EncArgs& a, const EncodeTables& et, int rows, int n
 int encode_rows_per_chunk(int d, int layout) { return chunk_rows(d / 16, layout); }
 int encode_waves(int layout) { return enc_waves(layout); }
 
+bool encode_fusable(const EncodeTables& et, int hidden) {
+  const int nt = et.d / 16;
+  if ((et.layout != 2 && et.layout != 3) || (nt != 4 && nt != 8) || hidden < 64 || hidden % 32)
+    return false;
+  const int vol = box_dwords(et.brick, et.rx, et.ry, et.rt);
+  const size_t lds = slice_table_offset(encode_lds_need(et.d, et.na == 4 ? VECKM_FP32 : VECKM_FP16,
+                                                        et.nbuf, et.KP, vol, et.layout)) +
+                     mlp_lds_bytes(hidden);
+  return lds <= 160 * 1024;
+}
+
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream, int32_t* rowcnt) {
+                  bool clear, int num_cus, void* stream, int32_t* rowcnt, const MlpWeights* mw) {
   EncArgs a;
   a.rowcnt = rowcnt;
+  a.w1frag = nullptr;
+  a.msteps = 0;
+  a.hidden = 0;
+  a.unscale = 1.f;
+  a.b1 = a.W2 = a.b2 = nullptr;
+  a.rowflow = nullptr;
+  if (fused_rows(rows)) {
+    if (!mw || !mw->W1frag || !encode_fusable(et, mw->hidden)) return VECKM_E_INVAL;
+    a.w1frag = reinterpret_cast<const uint4*>(mw->W1frag);
+    a.msteps = mw->hidden / 32;
+    a.hidden = mw->hidden;
+    a.unscale = et.na == 4 ? mw->unscale : 1.f;  // the bf16 W1 is not scaled
+    a.b1 = mw->b1;
+    a.W2 = mw->W2;
+    a.b2 = mw->b2;
+    a.rowflow = reinterpret_cast<float2*>(w.rowflow);
+  }
   a.bt = bt;
   a.b = et.brick;
   a.rx = et.rx;

@@ -30,14 +30,24 @@ __device__ inline uint32_t lds_offset(const void* p) {
 }
 
 // gfx950 global->LDS copies: lane i's 16 (4) bytes at `src` go to LDS byte
-// lds_base + 16 i (4 i); lds_base must be wave-uniform.  The leading s_nop is
-// the wait state the hardware needs between the M0 write and the copy.
+// lds_base + 16 i (4 i); lds_base must be wave-uniform.  The leading s_nop 4
+// gives the five wait states the hardware needs between a vector-ALU write of
+// a scalar register (an SGPR spill reload by v_readlane, a v_readfirstlane
+// into M0) and a vector memory instruction that reads it (the M0 base, the
+// scalar base address); the compiler's hazard pass does not look inside
+// inline asm, so the helpers carry the wait themselves.
 __device__ inline void copy_to_lds16(const void* src, uint32_t lds_base) {
-  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+  asm volatile("s_nop 4\n\tglobal_load_lds_dwordx4 %0, off"
                :: "v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(lds_base)) : "memory");
 }
+// The same with a wave-uniform base address (scalar registers) plus the
+// lane's 32-bit byte offset: no 64-bit address per copy in vector registers.
+__device__ inline void copy_to_lds16_s(const void* sbase, uint32_t voff, uint32_t lds_base) {
+  asm volatile("s_nop 4\n\tglobal_load_lds_dwordx4 %0, %1"
+               :: "v"(voff), "s"(sbase), "{m0}"(__builtin_amdgcn_readfirstlane(lds_base)) : "memory");
+}
 __device__ inline void copy_to_lds4(const void* src, uint32_t lds_base) {
-  asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off"
+  asm volatile("s_nop 4\n\tglobal_load_lds_dword %0, off"
                :: "v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(lds_base)) : "memory");
 }
 

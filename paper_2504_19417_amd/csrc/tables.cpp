@@ -281,19 +281,72 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
     if (!bigger && t.nbuf <= def.nbuf) continue;  // smaller only for deeper buffering
     out.push_back(t);
   }
-  // each of them also with the 8-wave layout (four frequency tiles or more
-  // per wave: D >= 64), where it fits
+  // each of them also with the other wave layouts (four frequency tiles or
+  // more per wave: D >= 64), where they fit: 8 waves of 4 row tiles over half
+  // the frequencies (1); 4 (2) or 8 (3) waves over every frequency of their
+  // rows, whose loads are pipelined within each wave with one slab in flight
+  // (and whose encoder can run the perceptron itself)
   const size_t n = out.size();
-  for (size_t i = 0; i < n && d >= 64; ++i) {
-    Tiling t = out[i];
-    t.layout = 1;
-    const bool even8 = (na * (d / 16) * 64) % (encode_waves(1) * 64) == 0;
-    if (t.nbuf > 2 && !even8) continue;
-    if (encode_lds_need(d, precision, t.nbuf, kp, box_dwords(t.brick, rx, ry, rt), 1) > 160 * 1024)
-      continue;
-    out.push_back(t);
-  }
+  for (int layout = 1; layout <= 3; ++layout)
+    for (size_t i = 0; i < n && d >= 64; ++i) {
+      Tiling t = out[i];
+      t.layout = layout;
+      if (layout >= 2) {
+        t.nbuf = 2;
+        bool dup = false;
+        for (size_t k = n; k < out.size(); ++k)
+          dup = dup || (out[k].layout == layout && out[k].brick.bx == t.brick.bx &&
+                        out[k].brick.by == t.brick.by && out[k].brick.bt == t.brick.bt);
+        if (dup) continue;
+      }
+      const bool even_l = (na * (d / 16) * 64) % (encode_waves(layout) * 64) == 0;
+      if (t.nbuf > 2 && !even_l) continue;
+      if (encode_lds_need(d, precision, t.nbuf, kp, box_dwords(t.brick, rx, ry, rt), layout) >
+          160 * 1024)
+        continue;
+      out.push_back(t);
+    }
+  // where the encoder can run the perceptron itself (D = 64 or 128), the
+  // 8-wave pipelined layout on the default brick comes first: it measured
+  // fastest for flows on dense slices (fused perceptron, no rows in HBM)
+  if (d == 64 || d == 128)
+    for (size_t k = 1; k < out.size(); ++k)
+      if (out[k].layout == 3 && out[k].brick.bx == def.brick.bx && out[k].brick.by == def.brick.by &&
+          out[k].brick.bt == def.brick.bt) {
+        const Tiling t = out[k];
+        out.erase(out.begin() + (long)k);
+        out.insert(out.begin(), t);
+        break;
+      }
   return out;
+}
+
+std::vector<uint16_t> make_w1_fragments(const float* W1, int hidden, int d, int na, int shift) {
+  const int nt = d / 16, terms = na / 2, msteps = hidden / 32, k2 = 2 * d;
+  std::vector<uint16_t> frag((size_t)msteps * na * nt * 64 * 8, 0);
+  size_t idx = 0;
+  for (int ms = 0; ms < msteps; ++ms)
+    for (int q = 0; q < na; ++q)
+      for (int kk = 0; kk < nt; ++kk)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < 8; ++e, ++idx) {
+            const int t = q / 2, tile = q % 2;
+            const int h = (2 * ms + tile) * 16 + (lane & 15);
+            const int g = lane >> 4;
+            // feature: tile 2kk' (e < 4) or 2kk' + 1 (e >= 4) of the real
+            // (kk < nt / 2) or imaginary parts, lane group g, element e % 4
+            const int kp = kk % (nt / 2);
+            const int f = (kk < nt / 2 ? 0 : d) + 32 * kp + 16 * (e >> 2) + 4 * g + (e & 3);
+            const float w = W1[(size_t)h * k2 + f];
+            if (terms == 1) {
+              frag[idx] = bf16_bits_rne(w);
+            } else {
+              const double v = std::ldexp((double)w, shift);
+              const uint16_t hi = fp16_bits_rne(v);
+              frag[idx] = t == 0 ? hi : fp16_bits_rne(v - fp16_to_double(hi));
+            }
+          }
+  return frag;
 }
 
 }  // namespace veckm

@@ -63,7 +63,8 @@ bool choose_layout(int rx, int ry, int rt, int d, int precision, int kp, Brick* 
 struct Tiling {
   Brick brick{32, 16, 8};
   int nbuf = 2;
-  int layout = 0;  // encoder wave layout: 0 = 16 waves x 2 row tiles, 1 = 8 waves x 4 row tiles
+  int layout = 0;  // encoder wave layout: 0 = 16 waves x 2 row tiles, 1 = 8 waves x 4 row tiles,
+                   // 2 = 4 and 3 = 8 pipelined waves over all frequencies of their rows
 };
 constexpr int kMaxBrickVoxels = 8192;  // largest brick (the ranking kernel's limit)
 std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp);
@@ -180,6 +181,11 @@ constexpr int kRowsSplit16 = 2;  // fp32 rows split into fp16 hi/lo in the perce
 constexpr int kRowsHiLo16 = 3;   // rows written as fp16 hi/lo pairs by the encoder: each group of
                                  // 4 consecutive elements is a 16-byte unit [hi x 4, lo x 4]
                                  // (FP32 form)
+// The encoder runs the perceptron itself and writes one flow per row (no
+// rows leave the chip): bf16 operands (FP16 form) or fp16 hi/lo operands
+// (FP32 form).  Only with the one-wave-per-SIMD layout at D = 64 or 128.
+constexpr int kFlowBF16 = 4;
+constexpr int kFlowHiLo16 = 5;
 
 struct MlpWeights {
   int hidden = 0;
@@ -191,7 +197,20 @@ struct MlpWeights {
   const float* b1 = nullptr;
   const float* W2 = nullptr;       // 2 x hidden
   const float* b2 = nullptr;
+  // W1 in the fused encoder's slab order (make_w1_fragments), or NULL
+  const uint16_t* W1frag = nullptr;
 };
+
+// W1 laid out as table slabs of the fused encoder (layout 2, WN = 1): slab s
+// holds hidden tiles 2s and 2s + 1 (16 units each) for every 32-feature step
+// kk of layer 1, fragment (t * 2 + tile, kk) as the MFMA A operand (64 lanes
+// x 8 halves; t = 0 for the bf16 or fp16-hi term, 1 for the fp16-lo term of
+// W1 * 2^shift).  Feature order within a step matches the encoder's
+// accumulator layout (frequency tiles 2kk' and 2kk' + 1 of the real parts
+// for kk < D / 32, of the imaginary parts above).
+std::vector<uint16_t> make_w1_fragments(const float* W1, int hidden, int d, int na, int shift);
+// Whether the encoder can run the perceptron itself for this tiling and width.
+bool encode_fusable(const EncodeTables& et, int hidden);
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream);
@@ -207,7 +226,8 @@ constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
 // event: their rows are exactly the counted voxels).
 // rowcnt: when non-NULL, also the neighbour count of every row (int32 [U]).
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream, int32_t* rowcnt = nullptr);
+                  bool clear, int num_cus, void* stream, int32_t* rowcnt = nullptr,
+                  const MlpWeights* mw = nullptr);
 // Per-query outputs; use_qmap: rows from the query -> row map (paper form),
 // else found from each query's voxel (`queries` as in the call, or NULL).
 int launch_expand_emb(const Batch& bt, const Workspace& w, const int32_t* queries,
