@@ -86,6 +86,7 @@ struct veckm_ctx {
   int max_slices = 1;
   std::vector<void*> allocs;
   std::vector<void*> mlp_allocs;
+  uint16_t* w1_slot = nullptr;  // W1 slabs after the phase table's (fusable widths)
   // Slice tables of batch calls: pinned staging and device copies, one slot
   // per call in flight; a slot is reused once the call that used it is done.
   SliceDesc* table_host = nullptr;
@@ -194,8 +195,8 @@ int64_t bytes_for(const veckm_params* p, const std::vector<Tiling>& tl, int kp, 
   bytes += 64 * 4 + 4 + 64 * 4;                   // plan, err, zero page
   bytes += (int64_t)kRing * slices_of(p) * (int64_t)sizeof(SliceDesc);  // slice tables
   bytes += (int64_t)hidden * (2 * p->d) * 10 + hidden * 12 + 8;  // perceptron (fp32, bf16, fp16 hi/lo W1)
-  if (p->rt >= 0 && (p->d == 64 || p->d == 128))  // W1 in the fused encoder's slab order
-    bytes += (int64_t)hidden * (2 * p->d) * (na / 2) * 2;
+  if (p->rt >= 0 && (p->d == 64 || p->d == 128))  // room for W1 after the phase table
+    bytes += (int64_t)kMaxHidden * (2 * p->d) * (na / 2) * 2;
   return bytes;
 }
 
@@ -557,7 +558,15 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   uint32_t* dzeros = nullptr;
   float* rows = nullptr;
   rc = VECKM_OK;
-  rc = rc ? rc : dalloc(c->allocs, &dfrag, frag.size());
+  // the phase table's slabs, then room for W1 in the same slab order (the
+  // fused encoder streams both through one ring: one contiguous array)
+  const int nt = params->d / 16;
+  const bool fusable = !c->paper && (nt == 4 || nt == 8);
+  const size_t w1_room = fusable ? (size_t)(kMaxHidden / 32) * et.na * nt * 64 * 8 : 0;
+  // (2 MB at least: one large page for the whole slab stream)
+  const size_t frag_halves = std::max(frag.size() + w1_room, (size_t)1 << 20);
+  rc = rc ? rc : dalloc(c->allocs, &dfrag, frag_halves);
+  c->w1_slot = fusable && !rc ? dfrag + frag.size() : nullptr;
   for (size_t i = 0; i < tl.size(); ++i) rc = rc ? rc : dalloc(c->allocs, &druns[i], st.KP / 4);
   rc = rc ? rc : dalloc(c->allocs, &dwts, wts.size());
   rc = rc ? rc : dalloc(c->allocs, &dzeros, 64);
@@ -671,7 +680,7 @@ void veckm_destroy(veckm_ctx* ctx) {
 int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* b1,
                   const float* W2, const float* b2) {
   if (!ctx || !W1 || !b1 || !W2 || !b2) return VECKM_E_INVAL;
-  if (hidden < 64 || hidden > 512 || hidden % 64) return VECKM_E_INVAL;
+  if (hidden < 64 || hidden > kMaxHidden || hidden % 64) return VECKM_E_INVAL;
   const int K2 = 2 * ctx->p.d;
   (void)hipDeviceSynchronize();
   for (void* p : ctx->mlp_allocs) (void)hipFree(p);
@@ -719,22 +728,15 @@ int veckm_set_mlp(veckm_ctx* ctx, int32_t hidden, const float* W1, const float* 
   ctx->mw.b1 = db1;
   ctx->mw.W2 = dW2;
   ctx->mw.b2 = db2;
-  // W1 in the slab order of the encoder that runs the perceptron itself
-  // (the one-wave-per-SIMD tiling at D = 64 or 128)
-  const int nt = ctx->p.d / 16;
-  if (!ctx->paper && (nt == 4 || nt == 8)) {
+  // W1 in the slab order of the encoder that runs the perceptron itself (the
+  // pipelined wave layouts at D = 64 or 128), right after the phase table
+  if (ctx->w1_slot) {
     const std::vector<uint16_t> wf = make_w1_fragments(W1, hidden, ctx->p.d, ctx->et.na, shift);
-    uint16_t* dwf = nullptr;
-    rc = dalloc(ctx->mlp_allocs, &dwf, wf.size());
-    if (rc) {
-      ctx->mw = MlpWeights{};
-      return rc;
-    }
-    if (hipMemcpy(dwf, wf.data(), wf.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(ctx->w1_slot, wf.data(), wf.size() * 2, hipMemcpyHostToDevice) != hipSuccess) {
       ctx->mw = MlpWeights{};
       return VECKM_E_HIP;
     }
-    ctx->mw.W1frag = dwf;
+    ctx->mw.W1frag = ctx->w1_slot;
   }
   return VECKM_OK;
 }

@@ -201,6 +201,9 @@ struct MlpWeights {
   const uint16_t* W1frag = nullptr;
 };
 
+// Widest perceptron hidden layer a context accepts.
+constexpr int kMaxHidden = 512;
+
 // W1 laid out as table slabs of the fused encoder (layout 2, WN = 1): slab s
 // holds hidden tiles 2s and 2s + 1 (16 units each) for every 32-feature step
 // kk of layer 1, fragment (t * 2 + tile, kk) as the MFMA A operand (64 lanes
