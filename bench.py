@@ -396,10 +396,12 @@ PROFILE_WORKLOADS = {
 }
 PROFILE_NOTES = {
     "slice1m": "Each form runs 2 warm-up + 5 timed steps (7 calls per form; the 10k-query "
-               "run is skipped).  The `<4, ...>` encoder (writing fp16 hi/lo rows) and "
-               "`k_mlp_res<2, ...>` belong to the FP32 form, the `<2, ...>` encoder and "
-               "`k_mlp_res<0, ...>` to the FP16/BF16 form; the small kernels serve both.  "
-               "`__amd_rocclr_*` are runtime copies and fills outside the steps.",
+               "run is skipped).  The encoders run the perceptron themselves (template "
+               "arguments: operand terms, slab tiles, wave layout, ring depth, row format): "
+               "`k_encode<4, 8, 3, 2, 5>` is the FP32 form (fp16 hi/lo operands), "
+               "`k_encode<2, 8, 3, 2, 4>` the FP16/BF16 form (bf16 perceptron); the front-end "
+               "and expansion kernels serve both.  `__amd_rocclr_*` are runtime copies and "
+               "fills outside the steps.",
     "paper_k8": "Three runs of 2 warm-up + 5 timed steps: FP32 form over all events, FP16/BF16 "
                 "form over all events, FP32 form over the 10k-query subset (7 calls each).  "
                 "`k_paper_rows<false>` and `k_mlp_split` serve the FP32 runs (all events and 10k "
@@ -409,10 +411,13 @@ PROFILE_NOTES = {
 }
 PROFILE_NOTES["paper_k10"] = PROFILE_NOTES["paper_k8"]
 PROFILE_NOTES["precision5m"] = (
-    "Each form runs 2 warm-up + 5 timed steps (7 calls per form).  `k_encode<2, ...>` and "
-    "`k_mlp_res<0, ...>` belong to the FP16/BF16 form, `k_encode<4, ...>` (writing fp16 hi/lo "
-    "rows) and `k_mlp_res<2, ...>` to the FP32 form; the front-end kernels serve both.  The "
-    "brick scan runs as three launches (23,400 bricks: three 8192-brick tiles).")
+    "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end, encoder "
+    "and perceptron), 2 warm-up and 5 timed steps.  Template arguments of `k_encode`: operand "
+    "terms (2: FP16/BF16 form, 4: FP32 form's hi/lo), slab tiles, wave layout, ring depth, row "
+    "format (1: bf16 rows, 3: hi/lo rows, both for `k_mlp_res`; 4 and 5: perceptron inside the "
+    "encoder, bf16 and hi/lo operands).  The fused `<2, 8, 3, 2, 4>` and `<4, 8, 3, 2, 5>` are "
+    "the tuner's picks and run the timed steps; the rest are tuner trials.  The brick scan "
+    "runs as three launches (23,400 bricks: three 8192-brick tiles).")
 PROFILE_NOTES["batch64"] = (
     "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end and "
     "encoder), 1 warm-up and 3 timed steps.  FP16 form tilings: `k_encode<2, 8, 4, 1>` is the "
@@ -517,6 +522,66 @@ def summarize_traffic(fetch_dir, write_dir, command):
                     "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
                     "hbm_bytes_per_launch": out["all"][name]["hbm_bytes"]})
     return out
+
+
+COUNTER_NOTES = {
+    "MfmaUtil": "matrix cores busy, % of kernel time (SQ_VALU_MFMA_BUSY_CYCLES over "
+                "GRBM_GUI_ACTIVE x 1024 SIMDs)",
+    "MfmaFlopsF16": "fp16 matrix-core flops per dispatch (SQ_INSTS_VALU_MFMA_MOPS_F16 x 512)",
+    "MfmaFlopsBF16": "bf16 matrix-core flops per dispatch (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512)",
+    "LdsUtil": "LDS busy with indexed reads and writes, % of kernel time (SQ_LDS_IDX_ACTIVE)",
+    "LdsBankConflict": "LDS cycles lost to bank conflicts per conflict-free LDS cycle "
+                       "(SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT))",
+    "TCC_HIT_sum": "L2 hits per dispatch", "TCC_MISS_sum": "L2 misses per dispatch",
+    "TCP_TCC_READ_REQ_sum": "vector L1 -> L2 read requests per dispatch",
+    "TCP_TCC_READ_REQ_LATENCY_sum": "summed latency of those requests (cycles)",
+}
+
+
+def summarize_counters(dirs, command, workload="slice1m"):
+    """Markdown summary of rocprofv3 --pmc runs (derived and raw counters),
+    one row per kernel of the library, counters averaged over dispatches."""
+    import csv
+    acc = {}
+    for d in dirs:
+        for row in csv.DictReader(open(_find_csv(d, "counter_collection.csv"))):
+            name = row["Kernel_Name"]
+            if "veckm::" not in name:
+                continue
+            c = acc.setdefault(name, {})
+            v = c.setdefault(row["Counter_Name"], [0.0, 0])
+            v[0] += float(row["Counter_Value"])
+            v[1] += 1
+    cols = [k for k in COUNTER_NOTES if any(k in c for c in acc.values())]
+    out = ["# Hardware counters: " + PROFILE_WORKLOADS[workload], "",
+           "Commands (R = repository root, one MI355X, ROCm 7.2; each --pmc pass is a run "
+           "of its own):", ""]
+    out += ["    " + c for c in command.split(" ; ")]
+    out += ["", "Counters (averages over the dispatches of each kernel):", ""]
+    out += ["* `%s`: %s" % (k, COUNTER_NOTES[k]) for k in cols]
+    derived = "TCC_HIT_sum" in cols and "TCC_MISS_sum" in cols
+    lat = "TCP_TCC_READ_REQ_sum" in cols and "TCP_TCC_READ_REQ_LATENCY_sum" in cols
+    if derived:
+        out.append("* L2 hit %: TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)")
+    if lat:
+        out.append("* L1->L2 read latency: TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum")
+    head = ["kernel"] + ["`%s`" % k for k in cols] + (["L2 hit %"] if derived else []) + \
+        (["L1->L2 read latency (cycles)"] if lat else [])
+    out += ["", "| " + " | ".join(head) + " |", "|---|" + "---:|" * (len(head) - 1)]
+    for name in sorted(acc):
+        c = {k: v[0] / v[1] for k, v in acc[name].items()}
+        cells = []
+        for k in cols:
+            v = c.get(k)
+            cells.append("" if v is None else ("%.4g" % v))
+        if derived:
+            h, m = c.get("TCC_HIT_sum"), c.get("TCC_MISS_sum")
+            cells.append("" if h is None or m is None or h + m == 0 else "%.1f" % (100 * h / (h + m)))
+        if lat:
+            r, l = c.get("TCP_TCC_READ_REQ_sum"), c.get("TCP_TCC_READ_REQ_LATENCY_sum")
+            cells.append("" if not r or l is None else "%.0f" % (l / r))
+        out.append("| `%s` | %s |" % (name.replace("|", "\\|")[:100], " | ".join(cells)))
+    return "\n".join(out) + "\n"
 
 
 def paper_main(args, name):
@@ -685,15 +750,19 @@ def window_main(args):
 
 
 def batch_main(args):
-    """The batched form: 64 slices (lognormal 10k-500k events, 346x260 and
-    640x480 sensors, 50 bins, D = 128, r = 5/3) in one launch sequence per
-    step, every event queried; FP16/BF16 form (the configuration's precision)
-    and FP32 form."""
+    """The batched form: 64 slices in one launch sequence per step, every
+    event queried, D = 128, r = 5/3, 50 bins, 346x260 and 640x480 sensors.
+    `batch64`: lognormal 10k-500k events per slice; `batch64x10k`: 10k events
+    per slice (launch overhead dominates).  Each form (FP16/BF16, the
+    configuration's precision, and FP32) is timed twice on the same inputs:
+    replaying the launch graph captured for the batch (the timed value) and
+    calling flow_batch eagerly; the two give bit-identical flows."""
     import torch
     import oracle
     from paper_2504_19417_amd import synth, veckm as vk
 
-    w = synth.workloads()["batch64"]
+    wl = args.workload
+    w = synth.workloads()[wl]
     parts = [synth.make_slice(s) for s in w.slices]
     A = synth.draw_frequencies(w.d, w.rx, w.ry, w.rt)
     mlp = synth.init_mlp(w.d, w.hidden)
@@ -720,12 +789,29 @@ def batch_main(args):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
         st = {k: (round(v[0] / v[1], 4) if v[1] else None) for k, v in c.profile_read().items()}
+        c.profile(False)
         status = c.status()
         rows = c.last_rows()
         flows = out.cpu().numpy()
+        # the same batch through its captured launch graph
+        gout = torch.empty((n, 2), device="cuda")
+        g = c.graph(specs, evt, gout, flow=True)
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch()
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t) / args.steps
+        gflows = gout.cpu().numpy()
+        g.close()
+        status = status or c.status()
         c.close()
         if status != vk.VECKM_OK:
             raise RuntimeError("input error reported by the device")
+        if not np.array_equal(gflows, flows):
+            raise RuntimeError("graph replay differs from the eager batch call")
         # 16 sampled events per slice against the oracle
         got, ref, off = [], [], 0
         for k, (e, t0, T) in enumerate(parts):
@@ -735,7 +821,8 @@ def batch_main(args):
             got.append(flows[off + q])
             off += len(e)
         got, ref = np.concatenate(got).astype(np.float64), np.concatenate(ref)
-        res[form] = dict(value=n / dt, ms=dt * 1e3, stages=st, tiling=list(tiling), rows=rows,
+        res[form] = dict(value=n / dtg, ms=dtg * 1e3, eager_value=n / dt, eager_ms=dt * 1e3,
+                         stages=st, tiling=list(tiling), rows=rows,
                          err=float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
     # the encoder (the dominant kernel) against the fp16 matrix-core peak
     K = ((2 * w.rx + 1) * (2 * w.ry + 1) * (2 * w.rt + 1) + 1) // 2
@@ -747,20 +834,28 @@ def batch_main(args):
                 "traffic": None, "kernel": "k_encode<2", "avg_launch_ms": r16["stages"]["encode"],
                 "rows_per_launch": r16["rows"], "flops_per_row": fpr,
                 "perceptron_in_encoder": fused}
+    sizes = "lognormal 10k-500k events" if wl == "batch64" else "10k events each"
+
+    def eager(r):
+        return {"value": r["eager_value"], "ms_per_step": round(r["eager_ms"], 4)}
+
     line = {
-        "metric": "normal flows/sec, 64-slice batch in one launch sequence (BF16 perceptron)",
+        "metric": "normal flows/sec, 64-slice batch replayed as one captured launch graph "
+                  "(BF16 perceptron)",
         "value": res["fp16"]["value"], "unit": "flows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(res["fp16"]["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
         "data": "synthetic (seeded moving edges + 10% uniform noise, 64 slices)",
-        "config": {"workload": "batch64", "slices": 64, "events": n,
+        "config": {"workload": wl, "slices": 64, "events": n, "slice_sizes": sizes,
                    "sensors": "346x260 / 640x480", "bins": 50, "d": w.d, "radius_xy": w.rx,
                    "radius_t": w.rt, "hidden": w.hidden, "queries": "all events",
                    "tiling_brick_slabs": res["fp16"]["tiling"]},
+        "eager_flow_batch": eager(res["fp16"]),
         "stages_ms": res["fp16"]["stages"],
         "err_vs_oracle": {"flow_relL2_sampled": res["fp16"]["err"]},
         "fp32": {"value": res["fp32"]["value"], "ms_per_step": round(res["fp32"]["ms"], 4),
+                 "eager_flow_batch": eager(res["fp32"]),
                  "stages_ms": res["fp32"]["stages"], "tiling_brick_slabs": res["fp32"]["tiling"],
                  "err_vs_oracle": {"flow_relL2_sampled": res["fp32"]["err"]}},
         "roofline": roofline, "cpu_baseline": None,
@@ -886,7 +981,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="slice1m",
                     choices=["slice1m", "paper_k8", "paper_k10", "window", "train", "batch64",
-                             "precision5m"],
+                             "batch64x10k", "precision5m"],
                     help="slice1m: the bounded-window 1M-event slice (the headline line); "
                          "paper_k8 / paper_k10: the paper's own form at its recipes")
     ap.add_argument("--steps", type=int, default=20)
@@ -906,11 +1001,17 @@ def main():
     ap.add_argument("--summarize-kernels", metavar="STATS_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into "
                          "profiles/kernels_<workload>.md and exit (no GPU needed)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
+                    help="summarise rocprofv3 --pmc runs (MFMA, LDS and L2 counters) into "
+                         "profiles/counters_<workload>.md and exit (no GPU needed)")
     ap.add_argument("--command", default="", help="commands recorded with the summaries "
                                                   "(separated by ' ; ')")
     args = ap.parse_args()
-    if args.summarize_traffic or args.summarize_kernels:
+    if args.summarize_traffic or args.summarize_kernels or args.summarize_counters:
         wl = args.workload
+        if args.summarize_counters:
+            with open(os.path.join(ROOT, "profiles", "counters_%s.md" % wl), "w") as f:
+                f.write(summarize_counters(args.summarize_counters, args.command, wl))
         if args.summarize_traffic:
             rec = summarize_traffic(*args.summarize_traffic, args.command)
             if wl == "slice1m":  # the headline line's roofline reads this record
@@ -936,7 +1037,7 @@ def main():
     if args.workload == "train":
         train_main(args)
         return
-    if args.workload == "batch64":
+    if args.workload in ("batch64", "batch64x10k"):
         batch_main(args)
         return
     if args.workload == "precision5m":

@@ -100,6 +100,13 @@ def workloads() -> dict:
     w["batch64"] = Workload("batch64", slices, d=128, rx=5, ry=5, rt=3, hidden=256,
                             precision="fp16",
                             notes="64 slices, lognormal 10k-500k events, 346x260 / 640x480")
+    # the launch-bound end of the batched form: 64 slices of 10k events each
+    # (the lower clip of the lognormal mix), same sensors
+    slices = [SliceSpec(*((346, 260) if coins[i] == 0 else (640, 480)), 50, 10_000, 32,
+                        seed=3000 + i, t_base=2_000_000 + 50 * i) for i in range(64)]
+    w["batch64x10k"] = Workload("batch64x10k", slices, d=128, rx=5, ry=5, rt=3, hidden=256,
+                                precision="fp16",
+                                notes="64 slices of 10k events, 346x260 / 640x480")
     w["paper_k8"] = Workload(
         "paper_k8", [SliceSpec(640, 480, 32, 500_000, 32, seed=1006)],
         d=64, rx=8, ry=8, rt=-1, hidden=128,
