@@ -146,7 +146,7 @@ int64_t pair_entries_of(const veckm_params* p) {
 }
 
 struct Sizes {
-  int64_t V, P, nb, ulist, U, n;
+  int64_t V, P, nb, ulist, lines, U, n;
 };
 
 // Workspace sizes for every tiling a context may use: the most bricks and
@@ -157,10 +157,12 @@ Sizes sizes_for(const veckm_params* p, const std::vector<Tiling>& tl) {
   s.P = pair_entries_of(p);
   s.nb = 0;
   s.ulist = 0;
+  s.lines = 0;
   for (const Tiling& t : tl) {
     const int64_t nb = slices_of(p) * bricks_of(p->width, p->height, p->max_bins, t.brick);
     s.nb = std::max(s.nb, nb);
     s.ulist = std::max(s.ulist, nb * t.brick.volume());
+    s.lines = std::max(s.lines, nb * t.brick.by * t.brick.bt);
   }
   s.n = p->max_events;
   s.U = s.n < s.V ? s.n : s.V;
@@ -184,11 +186,12 @@ int64_t bytes_for(const veckm_params* p, const std::vector<Tiling>& tl, int kp, 
     bytes += (int64_t)(p->max_bins + p->width + p->height) * p->d * 8;
   }
   bytes += s.V * (4 + 4 + 1);                     // count, rank, qmark
-  if (p->rt >= 0) bytes += s.P * 4;               // pair grid
+  if (p->rt >= 0) bytes += s.P * 4 + s.lines;     // pair grid, brick row flags
   bytes += s.ulist * 4;                           // ulist
   bytes += (6 * s.nb + 1) * 4;                    // brick_nq, brick_off, order
   bytes += (scan_tiles(s.nb) + 1) * kScanNV * 4;  // brick-scan partials
   bytes += s.n * (4 + 4);                         // vox, qmap
+  if (p->rt >= 0) bytes += s.U * 8 + kp;          // single-row list, its box's run offsets
   bytes += s.U * 2 * p->d * 4 + s.U * 8;          // rows (fp32 size), rowflow
   bytes += (int64_t)kp * p->d * na * 2 + kp * 2;  // phase table, weights
   bytes += (int64_t)tl.size() * kp;               // run offsets (one table per tiling)
@@ -371,17 +374,18 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
                    : c->paper                          ? kRowsSplit16
                                                       : kRowsHiLo16;
   // slice calls (not the paper form; a window's counts are resident) find
-  // the count grid zero and leave it zero: with every event queried the
-  // encoder clears its rows' voxels (exactly the counted ones), a query
-  // subset clears the grid after its expansion, and so does a call whose
-  // launches fail
+  // the count grid, the pair grid and the row flags zero and leave them
+  // zero: the ranking kernel clears the flags, and after the expansion the
+  // events' voxels are cleared; a call whose launches fail clears all three
+  // grids densely
   const bool clear = !c->paper && !c->window;
+  const int64_t nlines = (int64_t)bt.nbricks * c->et.brick.by * c->et.brick.bt;
   {
     StageTimer t(c, VECKM_STAGE_PREPARE, stream);
     const int rc = c->window ? launch_window_prepare(bt, w, ev, c->et, stream)
                              : launch_prepare(bt, w, ev, queries, c->et, !c->paper, stream);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, w, stream);
+      if (clear) (void)launch_clear_grids(bt, w, nlines, stream);
       return rc;
     }
   }
@@ -391,13 +395,12 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
     // rows, or runs inside the encoder
     const int erows = rows == kRowsBF16 || rows == kRowsHiLo16 || fused ? rows : kRowsF32;
     const int rc = c->paper ? launch_paper_encode(bt, w, c->pt, c->et.brick, erows, c->num_cus, stream)
-                            : launch_encode(bt, w, c->et, erows, clear && !queries,
-                                            c->num_cus, stream,
+                            : launch_encode(bt, w, c->et, erows, c->num_cus, stream,
                                             counts ? reinterpret_cast<int32_t*>(w.rowflow)
                                                    : nullptr,
                                             &c->mw);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, w, stream);
+      if (clear) (void)launch_clear_grids(bt, w, nlines, stream);
       return rc;
     }
   }
@@ -405,7 +408,7 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
     StageTimer t(c, VECKM_STAGE_MLP, stream);
     const int rc = launch_mlp(w, c->mw, c->p.d, rows, c->num_cus, stream);
     if (rc) {
-      if (clear) (void)launch_clear_counts(bt, w, stream);
+      if (clear) (void)launch_clear_grids(bt, w, nlines, stream);
       return rc;
     }
   }
@@ -415,8 +418,8 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
   int rc = flow     ? launch_expand_flow(bt, w, q, c->et.brick, c->paper, flow, stream)
            : counts ? launch_expand_count(bt, w, q, c->et.brick, counts, stream)
                     : launch_expand_emb(bt, w, q, c->et.brick, c->paper, c->p.d, emb, stream);
-  if (clear && (q || rc)) {
-    const int rc2 = launch_clear_counts(bt, w, stream);
+  if (clear) {
+    const int rc2 = rc ? launch_clear_grids(bt, w, nlines, stream) : launch_clear_events(bt, w, stream);
     rc = rc ? rc : rc2;
   }
   return rc;
@@ -572,6 +575,7 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &dzeros, 64);
   rc = rc ? rc : dalloc(c->allocs, &w.count, (size_t)s.V);
   if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &w.pairs, (size_t)s.P);
+  if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &w.lines, (size_t)s.lines);
   rc = rc ? rc : dalloc(c->allocs, &w.rank, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.qmark, (size_t)s.V);
   rc = rc ? rc : dalloc(c->allocs, &w.ulist, (size_t)s.ulist);
@@ -579,6 +583,9 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
   rc = rc ? rc : dalloc(c->allocs, &w.brick_off, (size_t)s.nb + 1);
   rc = rc ? rc : dalloc(c->allocs, &w.order, (size_t)s.nb * 4);
   rc = rc ? rc : dalloc(c->allocs, &w.scan_part, (size_t)((scan_tiles(s.nb) + 1) * kScanNV));
+  int32_t* druns1 = nullptr;
+  if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &w.srow, (size_t)(2 * s.U));
+  if (!c->paper) rc = rc ? rc : dalloc(c->allocs, &druns1, st.KP / 4);
   rc = rc ? rc : dalloc(c->allocs, &w.vox, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &w.qmap, (size_t)s.n);
   rc = rc ? rc : dalloc(c->allocs, &rows, (size_t)(s.U * 2 * params->d));
@@ -630,12 +637,21 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     if (hipMemcpy(druns[i], runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
       rc = VECKM_E_HIP;
   }
+  if (!rc && druns1) {  // a single voxel's count box (rows of bricks with few rows)
+    const std::vector<int32_t> runs = make_run_offsets(st, Brick{1, 1, 1}, params->rx, params->ry);
+    if (hipMemcpy(druns1, runs.data(), runs.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      rc = VECKM_E_HIP;
+  }
   if (!rc && hipMemcpy(dwts, wts.data(), wts.size() * 2, hipMemcpyHostToDevice) != hipSuccess)
     rc = VECKM_E_HIP;
   if (!rc && hipMemset(dzeros, 0, 64 * sizeof(uint32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.err, 0, sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.qmark, 0, (size_t)s.V) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.count, 0, (size_t)s.V * 4) != hipSuccess) rc = VECKM_E_HIP;
+  if (!rc && !c->paper &&
+      (hipMemset(w.pairs, 0, (size_t)s.P * 4) != hipSuccess ||
+       hipMemset(w.lines, 0, (size_t)s.lines) != hipSuccess))
+    rc = VECKM_E_HIP;
   if (!rc && hipMemset(w.plan, 0, 64 * sizeof(int32_t)) != hipSuccess) rc = VECKM_E_HIP;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = VECKM_E_HIP;
   if (rc) {
@@ -657,6 +673,12 @@ int veckm_create(const veckm_params* params, veckm_ctx** out) {
     t.nbuf = tl[i].nbuf;
     t.layout = tl[i].layout;
     t.runs = druns[i];
+    // single rows: as many single-voxel boxes as fit in the brick's box (up
+    // to one 16-row tile); worth it from 8 on
+    t.runs1 = druns1;
+    const int vol1 = box_dwords(Brick{1, 1, 1}, params->rx, params->ry, rt_enc);
+    t.rs = std::min(16, box_dwords(t.brick, params->rx, params->ry, rt_enc) / vol1);
+    t.sp = druns1 && t.rs >= 8 ? kSparseBelow : 0;
     c->tilings.push_back(t);
   }
   c->et = c->tilings[0];
@@ -1011,14 +1033,19 @@ int veckm_tune(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
       // (the output argument is only checked for presence; nothing is written)
       if (!rc) rc = multi_batch(ctx, slices, count, events, events, stream, &bt, &slot);
       if (!rc && bt.m > 0) {
-        // (the encoder returns the counts to zero, as in a batch call)
+        // (the grids return to zero as in a batch call)
         rc = launch_prepare(bt, ctx->w, events, nullptr, ctx->et, true, stream);
         if (!rc)
-          rc = launch_encode(bt, ctx->w, ctx->et, rows, true, ctx->num_cus, stream, nullptr,
+          rc = launch_encode(bt, ctx->w, ctx->et, rows, ctx->num_cus, stream, nullptr,
                              &ctx->mw);
         if (!rc && with_mlp && !fused)
           rc = launch_mlp(ctx->w, ctx->mw, ctx->p.d, rows, ctx->num_cus, stream);
-        if (rc) (void)launch_clear_counts(bt, ctx->w, stream);
+        const int rc3 =
+            rc ? launch_clear_grids(bt, ctx->w,
+                                    (int64_t)bt.nbricks * ctx->et.brick.by * ctx->et.brick.bt,
+                                    stream)
+               : launch_clear_events(bt, ctx->w, stream);
+        rc = rc ? rc : rc3;
       }
       const int rc2 = release_slot(ctx, slot, stream);
       rc = rc ? rc : rc2;
@@ -1140,6 +1167,7 @@ int64_t carve_noalloc(const veckm_ctx* c, const Batch& bt, unsigned char* base, 
   };
   w->count = reinterpret_cast<int32_t*>(take(V * 4));
   w->pairs = reinterpret_cast<uint32_t*>(take(P * 4));
+  w->lines = take(nb * b.by * b.bt);
   w->rank = reinterpret_cast<int32_t*>(take(V * 4));
   w->qmark = nullptr;  // read only for query subsets
   w->ulist = reinterpret_cast<int32_t*>(take(nb * b.volume() * 4));
@@ -1147,6 +1175,7 @@ int64_t carve_noalloc(const veckm_ctx* c, const Batch& bt, unsigned char* base, 
   w->brick_off = reinterpret_cast<int32_t*>(take((nb + 1) * 4));
   w->order = reinterpret_cast<int32_t*>(take(nb * 16));
   w->scan_part = reinterpret_cast<int32_t*>(take((scan_tiles(nb) + 1) * kScanNV * 4));
+  w->srow = reinterpret_cast<int32_t*>(take(U * 8));
   w->vox = reinterpret_cast<int32_t*>(take(n * 4));
   w->qmap = nullptr;  // read only by the paper form
   w->rows = take(U * 2 * c->p.d * 4);
@@ -1179,9 +1208,10 @@ int veckm_flow_noalloc(veckm_ctx* ctx, const veckm_event* events, int64_t n, int
   rc = scratch_on(ctx->device, &base);
   if (rc) return rc;
   carve_noalloc(ctx, bt, base, &w);
-  // the array holds whatever the last call left: the count grid starts at
-  // zero (a fill kernel, no memset)
-  rc = launch_clear_counts(bt, w, stream);
+  // the array holds whatever the last call left: the count and pair grids
+  // and the row flags start at zero (fill kernels, no memset)
+  rc = launch_clear_grids(bt, w, bt.nbricks * (int64_t)ctx->et.brick.by * ctx->et.brick.bt,
+                          stream);
   if (rc) return rc;
   return run(ctx, w, bt, events, nullptr, nullptr, flow, stream);
 }

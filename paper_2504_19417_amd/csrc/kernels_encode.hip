@@ -44,10 +44,12 @@ struct EncArgs {
   int K, nsteps;
   int SX, SY, ST, vol;
   int D;
-  int32_t* count;      // the count grid: the rows' voxels are returned to zero when clear
-  int clear;
   const int32_t* ulist;
-  const int4* order;  // work list: {brick, rows, first row, slice}
+  const int4* order;  // work list: {brick, rows, first row, slice}, or for single rows
+                      // {kSparseTag | item, rows, first row, first entry of srow}
+  const int2* srow;   // {brick, brick-local voxel} of each single row
+  const int32_t* runs1;  // run offsets of a single voxel's count box
+  int SX1, SY1, ST1, vol1;  // that box (x width, y and t extents, dwords)
   int lds_slices;     // slices whose descriptors are copied to LDS (0: read them from global)
   const uint4* frag;
   const int32_t* runs;
@@ -676,7 +678,8 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint4* slab = reinterpret_cast<uint4*>(smem);
   int32_t* runs_l = reinterpret_cast<int32_t*>(slab + NBUF * SLAB_U4);
-  uint16_t* wts_l = reinterpret_cast<uint16_t*>(runs_l + a.nsteps * 8);
+  int32_t* runs1_l = runs_l + a.nsteps * 8;
+  uint16_t* wts_l = reinterpret_cast<uint16_t*>(runs1_l + a.nsteps * 8);
   int32_t* rowbase = reinterpret_cast<int32_t*>(wts_l + a.nsteps * 32);
   int32_t* item = rowbase + CH;
   // Count box as overlapping fp16 pairs: dword i holds the counts of box
@@ -688,7 +691,7 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
   // batch, when they fit
   constexpr bool FUSE = fused_rows(ROWS);
   static_assert(!FUSE || enc_pipelined(L), "the perceptron runs inside the pipelined layouts only");
-  const size_t base_bytes = NBUF * SLAB_U4 * 16 + a.nsteps * 32 * 3 + CH * 4 + 16 + a.vol * 4;
+  const size_t base_bytes = NBUF * SLAB_U4 * 16 + a.nsteps * 32 * 4 + CH * 4 + 16 + a.vol * 4;
   float* mlp_l = reinterpret_cast<float*>(smem + slice_table_offset(base_bytes));
   SliceDesc* stab = reinterpret_cast<SliceDesc*>(
       smem + slice_table_offset(base_bytes + (FUSE ? mlp_lds_bytes(a.hidden) : 0)));
@@ -699,7 +702,10 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
   const int KP = a.nsteps * 32;
   const int BV = a.b.bx * a.b.by * a.b.bt;
   const int D = a.D;
-  for (int k = tid; k < KP / 4; k += NW * 64) runs_l[k] = a.runs[k];
+  for (int k = tid; k < KP / 4; k += NW * 64) {
+    runs_l[k] = a.runs[k];
+    runs1_l[k] = a.runs1 ? a.runs1[k] : 0;  // (no single rows without it)
+  }
   for (int k = tid; k < KP; k += NW * 64) wts_l[k] = a.wts[k];
   for (int k = tid; k < a.lds_slices * (int)(sizeof(SliceDesc) / 4); k += NW * 64)
     reinterpret_cast<int32_t*>(stab)[k] = reinterpret_cast<const int32_t*>(a.bt.table)[k];
@@ -729,25 +735,54 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
     const int nq = __builtin_amdgcn_readfirstlane(cur.y);
     const int row0 = __builtin_amdgcn_readfirstlane(cur.z);
     const int si = __builtin_amdgcn_readfirstlane(cur.w);
+    const bool single = (bid & kSparseTag) != 0;  // (uniform)
+    const int32_t* rl = single ? runs1_l : runs_l;
 
-    // the brick's first voxel in the count grid and the grid's strides (for
-    // returning the rows' counts to zero: nothing reads them after ranking)
-    int vlo = 0, vhi = 0, vW = 0, vH = 0;
-    // ---- the brick's count box: one global->LDS copy per box row from the
-    //      pair grid (lanes outside the slice read zeros); it has landed once
-    //      the first chunk's prologue wait returns
-    {
+    if (single) {
+      // ---- single rows (from bricks with few rows): row r gets its own count
+      //      box, a single voxel's, at vol2 + r vol1; wave w copies the boxes
+      //      of rows w, w + NW, ...  (rows srow[si .. si + nq))
+      for (int r = wid; r < nq; r += NW) {
+        const int2 e = a.srow[si + r];
+        const int gb = __builtin_amdgcn_readfirstlane(e.x);
+        const int li = __builtin_amdgcn_readfirstlane(e.y);
+        int s_ix = 0;
+        if (a.bt.nslices > 1) {
+          int hi = a.bt.nslices - 1;
+          while (s_ix < hi) {
+            const int mid = (s_ix + hi + 1) >> 1;
+            const int bo = a.lds_slices ? stab[mid].brick_off : a.bt.table[mid].brick_off;
+            if (bo <= gb) s_ix = mid; else hi = mid - 1;
+          }
+        }
+        const SliceDesc sl =
+            a.bt.nslices == 1 ? a.bt.s0 : a.lds_slices ? stab[s_ix] : a.bt.table[s_ix];
+        const int lb = gb - sl.brick_off;
+        const int bxi = lb % sl.nbx, byi = (lb / sl.nbx) % sl.nby, bti = lb / (sl.nbx * sl.nby);
+        const int vx = bxi * a.b.bx + li % a.b.bx, vy = byi * a.b.by + (li / a.b.bx) % a.b.by,
+                  vt = bti * a.b.bt + li / (a.b.bx * a.b.by);
+        // the box is vol1 consecutive dwords in LDS (rows of SX1): each copy
+        // fills 64 of them, whatever box rows they belong to
+        for (int d0 = 0; d0 < a.vol1; d0 += 64) {
+          const int d = d0 + lane, rr = d / a.SX1, xi = d - rr * a.SX1;
+          const int x = vx - a.rx - kRunPad + xi, y = vy - a.ry + rr % a.SY1,
+                    t = vt - a.rt + rr / a.SY1;
+          const bool in = x >= -1 && x < sl.W &&  // the pair grid has a column for x = -1
+                          (unsigned)y < (unsigned)sl.H && (unsigned)t < (unsigned)sl.T;
+          const int tp = t + sl.tshift < sl.T ? t + sl.tshift : t + sl.tshift - sl.T;
+          const uint32_t* src =
+              in ? a.pairs + sl.pair_off + ((int64_t)tp * sl.H + y) * (sl.W + 1) + (x + 1)
+                 : a.zeros + lane;
+          if (d < a.vol1) copy_to_lds4(src, lds_offset(vol2 + r * a.vol1 + d0));
+        }
+      }
+    } else {
+      // ---- the brick's count box: one global->LDS copy per box row from the
+      //      pair grid (lanes outside the slice read zeros); it has landed once
+      //      the first chunk's prologue wait returns
       const SliceDesc sl = a.bt.nslices == 1 ? a.bt.s0 : a.lds_slices ? stab[si] : a.bt.table[si];
       const int lb = bid - sl.brick_off;
       const int bxi = lb % sl.nbx, byi = (lb / sl.nbx) % sl.nby, bti = lb / (sl.nbx * sl.nby);
-      if (a.clear) {
-        const int64_t vorg = sl.grid_off +
-                             ((int64_t)(bti * a.b.bt) * sl.H + byi * a.b.by) * sl.W + bxi * a.b.bx;
-        vlo = __builtin_amdgcn_readfirstlane((int)(uint32_t)vorg);
-        vhi = __builtin_amdgcn_readfirstlane((int)(vorg >> 32));
-        vW = __builtin_amdgcn_readfirstlane(sl.W);
-        vH = __builtin_amdgcn_readfirstlane(sl.H);
-      }
       const int x = bxi * a.b.bx - a.rx - kRunPad + lane;
       const int y0 = byi * a.b.by - a.ry, tb = bti * a.b.bt - a.rt;
       const bool xin = x >= -1 && x < sl.W;  // the pair grid has a column for x = -1
@@ -775,13 +810,13 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
       // ---- voxel of each row (row q*16 + l of the chunk; padding reuses row 0)
       for (int r = tid; r < CH; r += NW * 64) {
         const int rr = c0 + (r < nr ? r : 0);
+        if (single) {  // the voxel at the centre of the row's own box
+          rowbase[r] = rr * a.vol1 + (a.rt * a.SY1 + a.ry) * a.SX1 + (a.rx + kRunPad);
+          continue;
+        }
         const int li = a.ulist[(int64_t)bid * BV + rr];
         const int lx = li % a.b.bx, ly = (li / a.b.bx) % a.b.by, lt = li / (a.b.bx * a.b.by);
         rowbase[r] = ((lt + a.rt) * a.SY + (ly + a.ry)) * a.SX + (lx + a.rx + kRunPad);
-        if (a.clear && r < nr) {
-          const int64_t vorg = ((int64_t)(uint32_t)vhi << 32) | (uint32_t)vlo;
-          a.count[vorg + ((int64_t)lt * vH + ly) * vW + lx] = 0;
-        }
       }
       // first slabs of the table
       if constexpr (kEncPairSteps && NBUF == 4 && !enc_pipelined(L)) {
@@ -839,11 +874,11 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
         fz.row_first = row0 + c0;
         fz.nr = nr;
         fz.wm = wm;
-        chunk_ksteps_pn<NA, NT, L, NBUF, MT, FUSE>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2,
+        chunk_ksteps_pn<NA, NT, L, NBUF, MT, FUSE>(mtv, a.nsteps, a.frag, slab, rl, wts_l, vol2,
                                                    rb, accR, accI, cnt, wn, wid, lane, fz);
         if constexpr (FUSE) continue;  // flows written; no rows leave the chip
       } else
-        chunk_ksteps_n<NA, NT, L, NBUF, MT>(mtv, a.nsteps, a.frag, slab, runs_l, wts_l, vol2, rb,
+        chunk_ksteps_n<NA, NT, L, NBUF, MT>(mtv, a.nsteps, a.frag, slab, rl, wts_l, vol2, rb,
                                             accR, accI, cnt, wn, wid, lane);
 
       // ---- normalise by the neighbour count and write the rows: the lane
@@ -923,7 +958,7 @@ __global__ __launch_bounds__(enc_waves(L) * 64) void k_encode(EncArgs a) {
 template <int NA, int NT, int L, int NBUF>
 static size_t encode_lds_bytes(const EncodeTables& et, int vol) {
   using S = EncShape<NA, NT, L>;
-  return (size_t)NBUF * S::SLAB_U4 * 16 + (size_t)et.KP + (size_t)et.KP * 2 +
+  return (size_t)NBUF * S::SLAB_U4 * 16 + (size_t)et.KP * 2 + (size_t)et.KP * 2 +
          (size_t)S::CH * 4 + 16 + (size_t)vol * 4;
 }
 
@@ -937,7 +972,7 @@ static int chunk_rows(int nt, int layout) {
 
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol, int layout) {
   const int na = precision == VECKM_FP32 ? 4 : 2, nt = d / 16;
-  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 3 + (size_t)chunk_rows(nt, layout) * 4 +
+  return (size_t)nbuf * na * nt * 64 * 16 + (size_t)kp * 4 + (size_t)chunk_rows(nt, layout) * 4 +
          16 + (size_t)vol * 4;
 }
 
@@ -1048,7 +1083,7 @@ bool encode_fusable(const EncodeTables& et, int hidden) {
 }
 
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream, int32_t* rowcnt, const MlpWeights* mw) {
+                  int num_cus, void* stream, int32_t* rowcnt, const MlpWeights* mw) {
   EncArgs a;
   a.rowcnt = rowcnt;
   a.w1frag = nullptr;
@@ -1080,10 +1115,15 @@ int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, i
   a.ST = et.brick.bt + 2 * et.rt;
   a.vol = a.SX * a.SY * a.ST;
   a.D = et.d;
-  a.count = w.count;
-  a.clear = clear ? 1 : 0;
   a.ulist = w.ulist;
   a.order = reinterpret_cast<const int4*>(w.order);
+  // single rows: a single voxel's count box, rs of which fit in the brick's
+  a.srow = reinterpret_cast<const int2*>(w.srow);
+  a.runs1 = et.runs1;
+  a.SX1 = box_sx(Brick{1, 1, 1}, et.rx);
+  a.SY1 = 1 + 2 * et.ry;
+  a.ST1 = 1 + 2 * et.rt;
+  a.vol1 = a.SX1 * a.SY1 * a.ST1;
   a.lds_slices = 0;
   a.frag = reinterpret_cast<const uint4*>(et.frag);
   a.runs = et.runs;
@@ -1093,6 +1133,9 @@ int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, i
   a.rows = w.rows;
   a.plan = w.plan;
   if (a.SX > 64) return VECKM_E_INVAL;  // one wavefront copies one box row
+  if (et.sp > 0 && (!et.runs1 || !w.srow || a.SX1 > 64 || et.rs < 1 || et.rs > 16 ||
+                    et.rs * a.vol1 > a.vol))
+    return VECKM_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
   return et.na == 4 ? dispatch_nt<4>(a, et, rows, num_cus, s)
                     : dispatch_nt<2>(a, et, rows, num_cus, s);

@@ -58,13 +58,17 @@ __device__ inline SliceDesc slice_by_event_block(const Batch& bt, int i) {
 
 // One thread per event: validate against its slice, histogram (ADD), remember
 // the slice-local voxel, and mark it as a query voxel when qmark is given
-// (a sliding window's query events).  Voxels over VECKM_MAX_VOXEL_EVENTS are caught
-// where the pair grid is built (k_rank, or k_pairs for a sliding window),
-// which reads every count once.
+// (a sliding window's query events).  With `lines` (bounded-window slice
+// calls) the event also flags its brick x row: lines[gb * by * bt + lt * by +
+// ly] = 1 for brick gb and brick-local row (ly, lt), so that ranking and
+// clearing visit only rows that hold events (plain byte stores: every
+// writer stores the same value).  Voxels over VECKM_MAX_VOXEL_EVENTS are
+// caught where the pair grid is built (k_rank_lines, k_rank, or k_pairs for
+// a sliding window), which reads every count once.
 template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err,
-                          uint8_t* __restrict__ qmark) {
+                          uint8_t* __restrict__ qmark, Brick b, uint8_t* __restrict__ lines) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x * blockDim.x >= bt.n) return;  // (whole block; launches never do this)
   const SliceDesc s = slice_by_event_block(bt, i);
@@ -81,6 +85,11 @@ __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __rest
   const int v = ((int)dt * s.H + e.y) * s.W + e.x;
   if (ADD) atomicAdd(&count[s.grid_off + v], 1);  // result unused: a no-return atomic
   if (qmark) qmark[s.grid_off + v] = 1;
+  if (lines) {
+    const int sx = __builtin_ctz(b.bx), sy = __builtin_ctz(b.by), st = __builtin_ctz(b.bt);
+    const int gb = s.brick_off + (((int)dt >> st) * s.nby + (e.y >> sy)) * s.nbx + (e.x >> sx);
+    lines[(int64_t)gb * (b.by * b.bt) + ((((int)dt & (b.bt - 1)) << sy) | (e.y & (b.by - 1)))] = 1;
+  }
   vox[i] = v;
 }
 
@@ -165,24 +174,20 @@ __global__ void k_mark(const int32_t* __restrict__ queries, Batch bt,
   if (v >= 0) qmark[bt.s0.grid_off + v] = 1;
 }
 
-// One block per brick: number the brick's query voxels in (t, y, x) order.
-// rank[v] gets the brick-local number, ulist[brick][number] the brick-local
-// voxel index, brick_nq[brick] the total.  Wave w of the 4 takes the w-th
-// quarter of the brick in voxel order: a first pass keeps its ballots, one
-// barrier gives every wave its offset, a second pass writes the numbers.
-// Brick sides are powers of two and a brick holds at most 256 kIt voxels.
-// PAIRS: the block also writes the brick's entries of the pair grid (the
-// layout k_pairs writes: entry x of a row holds voxels x - 1 and x; the
-// voxel at x = W - 1 also writes entry W) and checks the voxel limit, so the
-// counts are read once for both.
-template <bool ALL, int kIt, bool PAIRS>
+// One block per brick: number the brick's query voxels in (t, y, x) order
+// (the paper form and sliding windows; bounded-window slice calls use
+// k_rank_lines).  rank[v] gets the brick-local number, ulist[brick][number]
+// the brick-local voxel index, brick_nq[brick] the total.  Wave w of the 4
+// takes the w-th quarter of the brick in voxel order: a first pass keeps its
+// ballots, one barrier gives every wave its offset, a second pass writes the
+// numbers.  Brick sides are powers of two and a brick holds at most 256 kIt
+// voxels.
+template <bool ALL, int kIt>
 __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* __restrict__ count,
                                               uint8_t* __restrict__ qmark,
                                               int32_t* __restrict__ rank,
                                               int32_t* __restrict__ ulist,
-                                              int32_t* __restrict__ brick_nq,
-                                              uint32_t* __restrict__ pairs,
-                                              int32_t* __restrict__ err) {
+                                              int32_t* __restrict__ brick_nq) {
   __shared__ int wave_tot[4];
   const int gb = blockIdx.x;
   const SliceDesc s = slice_by_brick(bt, gb);
@@ -205,42 +210,12 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
   // all loads first (unconditional: a voxel outside the slice reads the
   // slice's first voxel and is masked), then the ballots
   bool flag[kIt];
-  int cv[PAIRS ? kIt : 1], pv[PAIRS ? kIt : 1];  // counts of the voxel and of x - 1
-  const int lx = lane & (b.bx - 1);  // the voxel's x within the brick (b.bx <= 64)
 #pragma unroll
   for (int k = 0; k < kIt; ++k) {
     const int64_t v = k < per ? voxel((wid * per + k) * 64 + lane) : (int64_t)-1;
     const int64_t a = v >= 0 ? v : s.grid_off;
-    if constexpr (PAIRS) {
-      cv[k] = count[a];
-      // the left neighbour of a brick's first column (x0 > 0) lies in the
-      // previous brick: read it; elsewhere it comes from the lane to the left
-      pv[k] = count[lx == 0 && x0 > 0 && v >= 0 ? a - 1 : a];
-    }
-    const bool f = ALL ? (PAIRS ? cv[k] > 0 : count[a] > 0) : (qmark[a] != 0);
+    const bool f = ALL ? count[a] > 0 : (qmark[a] != 0);
     flag[k] = v >= 0 && f;
-  }
-  if constexpr (PAIRS) {
-    bool bad = false;
-#pragma unroll
-    for (int k = 0; k < kIt; ++k) {
-      const int up = __shfl_up(cv[k], 1);  // (all lanes; per is uniform)
-      if (k < per) {
-        const int li = (wid * per + k) * 64 + lane;
-        const int64_t v = voxel(li);
-        if (v >= 0) {
-          const int x = x0 + lx, y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
-          const int lo = lx > 0 ? up : (x > 0 ? pv[k] : 0);
-          const int hi = cv[k];
-          bad |= hi > VECKM_MAX_VOXEL_EVENTS;
-          uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
-          row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
-                   ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
-          if (x == s.W - 1) row[s.W] = (uint32_t)__half_as_ushort(__float2half((float)hi));
-        }
-      }
-    }
-    if (bad) atomicOr(err, kErrOverflow);
   }
   unsigned long long bal[kIt];
   int tot = 0;
@@ -271,6 +246,281 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
   }
 }
 
+// k_rank for bounded-window slice calls, visiting only the brick x rows
+// that k_scatter flagged (`lines`).  Every other voxel of the brick has a
+// zero count and no query, so it is neither loaded nor ranked.  One wave
+// per brick (four bricks per block): it copies the brick's row flags to LDS
+// and clears them there (the last reader; a brick without a flagged row only
+// writes its zero row count), then walks the brick in voxel order, 64 voxels
+// per step, in groups of kG steps: each lane issues the group's loads (its
+// count, and the count beside it that the pair entries need: left of a row's
+// first voxel, right of its last) before using any; lanes of unflagged rows
+// load nothing and a group without a flagged row is skipped.  The wave
+// numbers the query voxels as it goes.  The pair grid is all zero between
+// such calls (k_clear_events returns it there), so only the entries a
+// flagged row touches are written: entry x of each of its voxels, and entry
+// x + 1 of its last voxel in the slice (which the neighbouring brick may also
+// write, with the same value: both read the final counts).  A flagged row
+// lies inside the slice (flags come from valid events only); its voxels
+// beyond the slice's x edge are not flagged.
+template <bool ALL>
+__global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
+                                                    const int32_t* __restrict__ count,
+                                                    uint8_t* __restrict__ lines,
+                                                    uint8_t* __restrict__ qmark,
+                                                    int32_t* __restrict__ rank,
+                                                    int32_t* __restrict__ ulist,
+                                                    int32_t* __restrict__ brick_nq,
+                                                    uint32_t* __restrict__ pairs,
+                                                    int32_t* __restrict__ err) {
+  constexpr int kG = 8;
+  __shared__ uint8_t sfl[4][kMaxBrickVoxels / 4];  // each wave's row flags (bx >= 4)
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gb = blockIdx.x * 4 + wid;
+  const int NL = b.by * b.bt;
+  int any = 0;
+  if (gb < bt.nbricks) {
+    uint8_t* fl = lines + (int64_t)gb * NL;
+    for (int l = lane; l < NL; l += 64) {
+      const uint8_t f = fl[l];
+      sfl[wid][l] = f;
+      any |= f;
+      if (f) fl[l] = 0;  // (the last reader: the flags are clear for the next call)
+    }
+  }
+  __syncthreads();
+  if (gb >= bt.nbricks) return;
+  if (!__ballot(any)) {
+    if (lane == 0) brick_nq[gb] = 0;
+    return;
+  }
+  const SliceDesc s = slice_by_brick(bt, gb);  // (gb is uniform: scalar loads)
+  const int lb = gb - s.brick_off;
+  const int bxi = lb % s.nbx, byi = (lb / s.nbx) % s.nby, bti = lb / (s.nbx * s.nby);
+  const int BV = b.bx * b.by * b.bt;
+  const int sx = __builtin_ctz(b.bx), sy = __builtin_ctz(b.by);
+  const int x0 = bxi * b.bx, y0 = byi * b.by, t0 = bti * b.bt;
+  const int lx = lane & (b.bx - 1);  // the voxel's x within the brick (b.bx <= 64)
+  const int x = x0 + lx;
+  // slice-local voxel of brick-local li (slices hold fewer than 2^31 voxels)
+  auto at = [&](int li) -> int {
+    const int y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+    return (t * s.H + y) * s.W + x;
+  };
+  const int32_t* cnt = count + s.grid_off;
+  const bool has_left = lx == 0 && x > 0, has_right = lx == b.bx - 1 && x + 1 < s.W;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int steps = (BV + 63) >> 6;
+  int base = 0;
+  bool bad = false;
+  for (int k0 = 0; k0 < steps; k0 += kG) {
+    bool lf[kG];
+    bool anyf = false;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int li = (k0 + g) * 64 + lane;
+      lf[g] = li < BV && x < s.W && sfl[wid][li >> sx] != 0;
+      anyf |= lf[g];
+    }
+    if (!__ballot(anyf)) continue;
+    int cv[kG], side[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int o = at((k0 + g) * 64 + lane);
+      cv[g] = lf[g] ? cnt[o] : 0;
+      side[g] = lf[g] && (has_left || has_right) ? cnt[has_left ? o - 1 : o + 1] : 0;
+    }
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int up = __shfl_up(cv[g], 1);  // (all lanes)
+      const int li = (k0 + g) * 64 + lane;
+      bool f = false;
+      if (lf[g]) {
+        const int y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+        const int lo = lx > 0 ? up : side[g];
+        const int hi = cv[g];
+        bad |= hi > VECKM_MAX_VOXEL_EVENTS;
+        uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
+        row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
+                 ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
+        if (lx == b.bx - 1 || x == s.W - 1) {
+          const int right = x + 1 < s.W ? side[g] : 0;
+          row[x + 1] = (uint32_t)__half_as_ushort(__float2half((float)hi)) |
+                       ((uint32_t)__half_as_ushort(__float2half((float)right)) << 16);
+        }
+        f = ALL ? hi > 0 : qmark[s.grid_off + at(li)] != 0;
+      }
+      const unsigned long long bal = __ballot(f);
+      if (f) {
+        const int64_t v = s.grid_off + at(li);
+        const int r = base + __popcll(bal & below);
+        rank[v] = r;
+        if (!ALL) qmark[v] = 0;  // the marks are clear again for the next call
+        ulist[(int64_t)gb * BV + r] = li;
+      }
+      base += __popcll(bal);
+    }
+  }
+  if (bad) atomicOr(err, kErrOverflow);
+  if (lane == 0) brick_nq[gb] = base;
+}
+
+// k_rank_lines for dense calls (most bricks hold many rows): the same work
+// with one block per brick, each of its 4 waves taking a quarter of the
+// brick; the ballots of the query voxels go to LDS, one barrier gives every
+// wave its offset, and a second pass writes the numbers.
+template <bool ALL>
+__global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
+                                                     const int32_t* __restrict__ count,
+                                                     uint8_t* __restrict__ lines,
+                                                     uint8_t* __restrict__ qmark,
+                                                     int32_t* __restrict__ rank,
+                                                     int32_t* __restrict__ ulist,
+                                                     int32_t* __restrict__ brick_nq,
+                                                     uint32_t* __restrict__ pairs,
+                                                     int32_t* __restrict__ err) {
+  constexpr int kG = 8;
+  constexpr int kSteps = kMaxBrickVoxels / 64;
+  __shared__ uint8_t sfl[kMaxBrickVoxels / 4];  // the brick's row flags (bx >= 4)
+  __shared__ unsigned long long sbal[kSteps];   // query-voxel ballot of each step
+  __shared__ int wave_tot[4];
+  const int gb = blockIdx.x;
+  const int NL = b.by * b.bt;
+  int any = 0;
+  {
+    uint8_t* fl = lines + (int64_t)gb * NL;
+    for (int l = threadIdx.x; l < NL; l += 256) {
+      const uint8_t f = fl[l];
+      sfl[l] = f;
+      any |= f;
+      if (f) fl[l] = 0;  // (the last reader: the flags are clear for the next call)
+    }
+  }
+  if (!__syncthreads_or(any)) {
+    if (threadIdx.x == 0) brick_nq[gb] = 0;
+    return;
+  }
+  const SliceDesc s = slice_by_brick(bt, gb);
+  const int lb = gb - s.brick_off;
+  const int bxi = lb % s.nbx, byi = (lb / s.nbx) % s.nby, bti = lb / (s.nbx * s.nby);
+  const int BV = b.bx * b.by * b.bt;
+  const int sx = __builtin_ctz(b.bx), sy = __builtin_ctz(b.by);
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x0 = bxi * b.bx, y0 = byi * b.by, t0 = bti * b.bt;
+  const int lx = lane & (b.bx - 1);  // the voxel's x within the brick (b.bx <= 64)
+  const int x = x0 + lx;
+  auto at = [&](int li) -> int {
+    const int y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+    return (t * s.H + y) * s.W + x;
+  };
+  const int32_t* cnt = count + s.grid_off;
+  const bool has_left = lx == 0 && x > 0, has_right = lx == b.bx - 1 && x + 1 < s.W;
+  const int steps = (BV + 63) >> 6;
+  const int per = (steps + 3) >> 2;  // steps of each wave
+  const int k_lo = wid * per, k_hi = min(k_lo + per, steps);
+  int tot = 0;
+  bool bad = false;
+  for (int k0 = k_lo; k0 < k_hi; k0 += kG) {
+    bool lf[kG];
+    bool anyf = false;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int li = (k0 + g) * 64 + lane;
+      lf[g] = k0 + g < k_hi && li < BV && x < s.W && sfl[li >> sx] != 0;
+      anyf |= lf[g];
+    }
+    if (!__ballot(anyf)) {
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (k0 + g < k_hi && lane == 0) sbal[k0 + g] = 0ull;
+      continue;
+    }
+    int cv[kG], side[kG];
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int o = at((k0 + g) * 64 + lane);
+      cv[g] = lf[g] ? cnt[o] : 0;
+      side[g] = lf[g] && (has_left || has_right) ? cnt[has_left ? o - 1 : o + 1] : 0;
+    }
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+      const int up = __shfl_up(cv[g], 1);  // (all lanes)
+      const int li = (k0 + g) * 64 + lane;
+      bool f = false;
+      if (lf[g]) {
+        const int y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
+        const int lo = lx > 0 ? up : side[g];
+        const int hi = cv[g];
+        bad |= hi > VECKM_MAX_VOXEL_EVENTS;
+        uint32_t* row = pairs + s.pair_off + ((int64_t)t * s.H + y) * (s.W + 1);
+        row[x] = (uint32_t)__half_as_ushort(__float2half((float)lo)) |
+                 ((uint32_t)__half_as_ushort(__float2half((float)hi)) << 16);
+        if (lx == b.bx - 1 || x == s.W - 1) {
+          const int right = x + 1 < s.W ? side[g] : 0;
+          row[x + 1] = (uint32_t)__half_as_ushort(__float2half((float)hi)) |
+                       ((uint32_t)__half_as_ushort(__float2half((float)right)) << 16);
+        }
+        f = ALL ? hi > 0 : qmark[s.grid_off + at(li)] != 0;
+      }
+      const unsigned long long bal = __ballot(f);
+      if (k0 + g < k_hi && lane == 0) sbal[k0 + g] = bal;
+      tot += __popcll(bal);
+    }
+  }
+  if (bad) atomicOr(err, kErrOverflow);
+  if (lane == 0) wave_tot[wid] = tot;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wid; ++w) base += wave_tot[w];
+  if (threadIdx.x == 0) brick_nq[gb] = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int k = k_lo; k < k_hi; ++k) {
+    const unsigned long long bal = sbal[k];
+    if ((bal >> lane) & 1ull) {
+      const int li = k * 64 + lane;
+      const int64_t v = s.grid_off + at(li);
+      const int r = base + __popcll(bal & below);
+      rank[v] = r;
+      if (!ALL) qmark[v] = 0;  // the marks are clear again for the next call
+      ulist[(int64_t)gb * BV + r] = li;
+    }
+    base += __popcll(bal);
+  }
+}
+
+// The count and pair grids of a dense call back to zero: one pass over both
+// (cheaper than the per-event stores when the grids are small beside the
+// events; see dense_batch).
+__global__ void k_fill2_zero(int32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
+                             int64_t nb) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+    if (i < na) a[i] = 0;
+    else b[i - na] = 0u;
+  }
+}
+
+// After a bounded-window slice call: every valid event's voxel count and
+// the two pair entries that hold it (entries x and x + 1 of its row) back to
+// zero; events that share a voxel store the same zeros.  These are all the
+// non-zero entries (an entry holds the counts of voxels x - 1 and x).  The
+// row flags were cleared by the ranking kernel, their last reader.
+__global__ void k_clear_events(Batch bt, const int32_t* __restrict__ vox,
+                               int32_t* __restrict__ count, uint32_t* __restrict__ pairs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x * blockDim.x >= bt.n) return;  // (whole block; launches never do this)
+  const SliceDesc s = slice_by_event_block(bt, i);
+  if (i >= bt.n) return;
+  const int v = vox[i];
+  if (v < 0) return;
+  count[s.grid_off + v] = 0;
+  const int64_t e = s.pair_off + v + v / s.W;  // entry x of row v / W
+  pairs[e] = 0u;
+  pairs[e + 1] = 0u;
+}
+
 // Exclusive scan of the per-brick row counts into off[] (off[nb] = total
 // rows U) and the list of non-empty bricks in order[] (one record per brick:
 // brick, rows, first row, slice), by size class (most encoder chunks
@@ -281,9 +531,23 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
 // a scan of the tile totals, then each tile places its bricks.  Within a
 // tile thread t owns bricks [t kScanPer, (t + 1) kScanPer); nothing is
 // counted with atomics, so order[] is the same on every call.
-constexpr int kScanClasses = 12;  // kScanNV = class counts, then rows
+constexpr int kScanClasses = 12;  // kScanNV = class counts, then rows of the
+constexpr int kRowsD = 12;        // bricks the encoder takes whole,
+constexpr int kRowsS = 13;        // then rows of the bricks it takes as single rows
 constexpr int kScanThreads = 1024, kScanPer = kScanTile / kScanThreads;
-static_assert(kScanNV == kScanClasses + 1 && kScanTile % kScanThreads == 0, "scan tiles");
+static_assert(kScanNV == kScanClasses + 2 && kScanTile % kScanThreads == 0, "scan tiles");
+
+// Bricks with fewer than `sp` rows (0: none) are not the encoder's work
+// items: their rows are numbered after all other rows and listed one by one
+// in srow ({brick, brick-local voxel} per row), and the encoder takes them
+// in items of up to `rs` rows, each row with a count box of its own.
+struct SparseRows {
+  int sp = 0, rs = 1, bv = 0;
+  const int32_t* ulist = nullptr;
+  int2* srow = nullptr;
+};
+
+__device__ inline bool sparse_brick(int q, int sp) { return q > 0 && q < sp; }
 
 __device__ inline int chunk_class(int nq, int ch) {
   const int c = (nq + ch - 1) / ch;
@@ -293,7 +557,7 @@ __device__ inline int chunk_class(int nq, int ch) {
 // The tile's counts (coalesced through LDS), this thread's class counts and
 // rows in v[], their exclusive scan over the tile's threads in ex[], the
 // tile totals in tot[].
-__device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch, int tile,
+__device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch, int sp, int tile,
                                  int (&q)[kScanPer], int (&v)[kScanNV], int (&ex)[kScanNV],
                                  int (&tot)[kScanNV]) {
   constexpr int NWV = kScanThreads / 64;  // waves
@@ -313,8 +577,10 @@ __device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch,
 #pragma unroll
   for (int u = 0; u < kScanPer; ++u) {
     q[u] = tq[tid * kScanPer + u];
-    v[kScanClasses] += q[u];
-    const int c = q[u] > 0 ? chunk_class(q[u], ch) : -1;
+    const bool sb = sparse_brick(q[u], sp);
+    v[kRowsD] += sb ? 0 : q[u];
+    v[kRowsS] += sb ? q[u] : 0;
+    const int c = q[u] > 0 && !sb ? chunk_class(q[u], ch) : -1;
 #pragma unroll
     for (int k = 0; k < kScanClasses; ++k) v[k] += c == k;
   }
@@ -357,10 +623,10 @@ __device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch,
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_totals(const int32_t* __restrict__ nq,
-                                                              int nb, int ch,
+                                                              int nb, int ch, int sp,
                                                               int32_t* __restrict__ part) {
   int q[kScanPer], v[kScanNV], ex[kScanNV], tot[kScanNV];
-  scan_tile(nq, nb, ch, blockIdx.x, q, v, ex, tot);
+  scan_tile(nq, nb, ch, sp, blockIdx.x, q, v, ex, tot);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < kScanNV; ++k) part[blockIdx.x * kScanNV + k] = tot[k];
@@ -369,9 +635,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_totals(const int32_t* __r
 // One block: turns the tile totals into each tile's starting positions
 // (class k of tile b starts at the class's start plus the class counts of
 // tiles before b; rows likewise).
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb,
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb, int rs,
                                                              int32_t* __restrict__ part,
                                                              int32_t* __restrict__ off,
+                                                             int4* __restrict__ order,
                                                              int32_t* __restrict__ plan) {
   __shared__ int sums[kScanNV][kScanThreads];
   const int tid = threadIdx.x;
@@ -401,7 +668,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb,
     start[k] = acc;
     acc += sums[k][kScanThreads - 1];
   }
-  start[kScanClasses] = 0;
+  const int ud = sums[kRowsD][kScanThreads - 1], us = sums[kRowsS][kScanThreads - 1];
+  start[kRowsD] = 0;
+  start[kRowsS] = ud;  // single rows are numbered after the others
   int run[kScanNV];
 #pragma unroll
   for (int k = 0; k < kScanNV; ++k) run[k] = start[k] + sums[k][tid] - v[k];
@@ -412,28 +681,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb,
       part[i * kScanNV + k] = run[k];
       run[k] += t;
     }
+  // the single-row items follow the bricks in the work list
+  const int ns = (us + rs - 1) / rs;
+  for (int j = tid; j < ns; j += kScanThreads)
+    order[acc + j] = make_int4(kSparseTag | j, min(rs, us - j * rs), ud + j * rs, j * rs);
   if (tid == 0) {
-    const int rows = sums[kScanClasses][kScanThreads - 1];
-    off[nb] = rows;
-    plan[0] = rows;
+    off[nb] = ud + us;
+    plan[0] = ud + us;
     plan[1] = 0;
-    plan[2] = acc;
+    plan[2] = acc + ns;
+    plan[3] = ud;
   }
 }
 
 // ONE = true: the bricks fit in one tile, and this single block does the
 // whole scan (part is not used; plan and off[nb] are written here).
-template <bool ONE>
+template <bool ONE, bool SP>
 __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
                                                              const int32_t* __restrict__ nq,
-                                                             int nb, int ch,
+                                                             int nb, int ch, SparseRows sr,
                                                              const int32_t* __restrict__ part,
                                                              int32_t* __restrict__ off,
                                                              int4* __restrict__ order,
                                                              int32_t* __restrict__ plan) {
   int q[kScanPer], v[kScanNV], ex[kScanNV], tot[kScanNV];
-  scan_tile(nq, nb, ch, blockIdx.x, q, v, ex, tot);
+  scan_tile(nq, nb, ch, SP ? sr.sp : 0, blockIdx.x, q, v, ex, tot);
   int pos[kScanNV];
+  int ud;  // rows of the bricks taken whole: single rows start here
   if constexpr (ONE) {
     int start = 0;
 #pragma unroll
@@ -441,24 +715,47 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
       pos[k] = start + ex[k];
       start += tot[k];
     }
-    pos[kScanClasses] = ex[kScanClasses];
+    ud = tot[kRowsD];
+    pos[kRowsD] = ex[kRowsD];
+    pos[kRowsS] = ud + ex[kRowsS];
+    // the single-row items follow the bricks in the work list
+    const int us = SP ? tot[kRowsS] : 0, ns = SP ? (us + sr.rs - 1) / sr.rs : 0;
+    if constexpr (SP)
+      for (int j = threadIdx.x; j < ns; j += kScanThreads)
+        order[start + j] = make_int4(kSparseTag | j, min(sr.rs, us - j * sr.rs), ud + j * sr.rs,
+                                     j * sr.rs);
     if (threadIdx.x == 0) {
-      off[nb] = tot[kScanClasses];
-      plan[0] = tot[kScanClasses];
+      off[nb] = ud + us;
+      plan[0] = ud + us;
       plan[1] = 0;
-      plan[2] = start;
+      plan[2] = start + ns;
+      plan[3] = ud;
     }
   } else {
 #pragma unroll
     for (int k = 0; k < kScanNV; ++k) pos[k] = part[blockIdx.x * kScanNV + k] + ex[k];
+    ud = plan[3];
   }
   const int i0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
 #pragma unroll
   for (int u = 0; u < kScanPer; ++u) {
     const int i = i0 + u;
     if (i >= nb) break;
-    off[i] = pos[kScanClasses];
-    pos[kScanClasses] += q[u];
+    if (SP && sparse_brick(q[u], sr.sp)) {
+      // its rows, one by one, among the single rows (all loads at once)
+      off[i] = pos[kRowsS];
+      int li[kSparseBelow - 1];
+#pragma unroll
+      for (int r = 0; r < kSparseBelow - 1; ++r)
+        li[r] = r < q[u] ? sr.ulist[(int64_t)i * sr.bv + r] : 0;
+#pragma unroll
+      for (int r = 0; r < kSparseBelow - 1; ++r)
+        if (r < q[u]) sr.srow[pos[kRowsS] - ud + r] = make_int2(i, li[r]);
+      pos[kRowsS] += q[u];
+      continue;
+    }
+    off[i] = pos[kRowsD];
+    pos[kRowsD] += q[u];
     if (q[u] > 0) {
       const int c = chunk_class(q[u], ch);
       int p = 0;
@@ -473,27 +770,35 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
           if (bt.table[mid].brick_off <= i) sl = mid; else hi = mid - 1;
         }
       }
-      order[p] = make_int4(i, q[u], pos[kScanClasses] - q[u], sl);
+      order[p] = make_int4(i, q[u], pos[kRowsD] - q[u], sl);
     }
   }
 }
 
 // The three launches of the brick scan (part: kScanNV ints per tile).
 static void launch_brick_scan(const Batch& bt, const Workspace& w, int nb, int ch,
-                              hipStream_t s) {
+                              const SparseRows& sr, hipStream_t s) {
   const int ntiles = nb > 0 ? (int)scan_tiles(nb) : 1;
   int4* order = reinterpret_cast<int4*>(w.order);
   if (ntiles == 1) {
-    hipLaunchKernelGGL(k_scan_place<true>, dim3(1), dim3(kScanThreads), 0, s, bt, w.brick_nq, nb,
-                       ch, w.scan_part, w.brick_off, order, w.plan);
+    if (sr.sp > 0)
+      hipLaunchKernelGGL((k_scan_place<true, true>), dim3(1), dim3(kScanThreads), 0, s, bt,
+                         w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
+    else
+      hipLaunchKernelGGL((k_scan_place<true, false>), dim3(1), dim3(kScanThreads), 0, s, bt,
+                         w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
     return;
   }
   hipLaunchKernelGGL(k_scan_totals, dim3(ntiles), dim3(kScanThreads), 0, s, w.brick_nq, nb, ch,
-                     w.scan_part);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, ntiles, nb, w.scan_part,
-                     w.brick_off, w.plan);
-  hipLaunchKernelGGL(k_scan_place<false>, dim3(ntiles), dim3(kScanThreads), 0, s, bt, w.brick_nq,
-                     nb, ch, w.scan_part, w.brick_off, order, w.plan);
+                     sr.sp, w.scan_part);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, ntiles, nb, sr.rs,
+                     w.scan_part, w.brick_off, order, w.plan);
+  if (sr.sp > 0)
+    hipLaunchKernelGGL((k_scan_place<false, true>), dim3(ntiles), dim3(kScanThreads), 0, s, bt,
+                       w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
+  else
+    hipLaunchKernelGGL((k_scan_place<false, false>), dim3(ntiles), dim3(kScanThreads), 0, s, bt,
+                       w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
 }
 
 // The row of slice-local voxel v (a query voxel of slice s).
@@ -636,45 +941,88 @@ static dim3 pairs_grid(int nslices, int64_t max_rows) {
 
 // k_rank for every voxel with events (all) or only the marked ones; with
 // `pairs` it also builds the pair grid.
-static void launch_rank(const Batch& bt, const Workspace& w, const Brick& b, bool all, bool pairs,
+static void launch_rank(const Batch& bt, const Workspace& w, const Brick& b, bool all,
                         hipStream_t s) {
   static_assert(kMaxBrickVoxels <= 8192, "k_rank holds at most 32 ballots per wave");
   const bool big = b.volume() > 4096;
   auto go = [&](auto fn) {
     hipLaunchKernelGGL(fn, dim3(bt.nbricks), dim3(256), 0, s, bt, b, w.count, w.qmark, w.rank,
-                       w.ulist, w.brick_nq, w.pairs, w.err);
+                       w.ulist, w.brick_nq);
   };
-  if (pairs) {
-    if (all)
-      big ? go(k_rank<true, 32, true>) : go(k_rank<true, 16, true>);
-    else
-      big ? go(k_rank<false, 32, true>) : go(k_rank<false, 16, true>);
-  } else {
-    if (all)
-      big ? go(k_rank<true, 32, false>) : go(k_rank<true, 16, false>);
-    else
-      big ? go(k_rank<false, 32, false>) : go(k_rank<false, 16, false>);
-  }
+  if (all)
+    big ? go(k_rank<true, 32>) : go(k_rank<true, 16>);
+  else
+    big ? go(k_rank<false, 32>) : go(k_rank<false, 16>);
+}
+
+static void launch_rank_lines(const Batch& bt, const Workspace& w, const Brick& b, bool all,
+                              hipStream_t s) {
+  // dense calls: a block per brick; else a wave per brick (latency-bound
+  // sparse bricks)
+  auto go = [&](auto fn, unsigned blocks) {
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, bt, b, w.count, w.lines, w.qmark,
+                       w.rank, w.ulist, w.brick_nq, w.pairs, w.err);
+  };
+  const unsigned nb = (unsigned)bt.nbricks, nb4 = (unsigned)((bt.nbricks + 3) / 4);
+  if (dense_batch(bt))
+    all ? go(k_rank_lines4<true>, nb) : go(k_rank_lines4<false>, nb);
+  else
+    all ? go(k_rank_lines<true>, nb4) : go(k_rank_lines<false>, nb4);
+}
+
+int launch_clear_events(const Batch& bt, const Workspace& w, void* stream) {
+  if (dense_batch(bt))
+    hipLaunchKernelGGL(k_fill2_zero, dim3(fill_grid(bt.nvox + bt.npairs)), dim3(256), 0,
+                       (hipStream_t)stream, w.count, bt.nvox, w.pairs, bt.npairs);
+  else if (bt.n > 0)
+    hipLaunchKernelGGL(k_clear_events, dim3(blocks_for(bt.n, 256)), dim3(256), 0,
+                       (hipStream_t)stream, bt, w.vox, w.count, w.pairs);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int launch_clear_grids(const Batch& bt, const Workspace& w, int64_t nlines, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.npairs)), dim3(256), 0, s,
+                     reinterpret_cast<int32_t*>(w.pairs), bt.npairs, 0);
+  const int64_t words = (nlines + 3) / 4;
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(words)), dim3(256), 0, s,
+                     reinterpret_cast<int32_t*>(w.lines), words, 0);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  // slice calls (not the paper form) find the count grid zero: every such
-  // call returns its counts to zero after use (zeroed once at context
-  // creation; the encoder clears them when every event is queried); the
-  // paper form clears it here
+  // (a brick has at most kMaxBrickVoxels / 4 rows of flags)
+  if (pairs && et.brick.bx < 4) return VECKM_E_INVAL;
+  // slice calls (not the paper form) find the count grid, the pair grid and
+  // the row flags zero: every such call returns them to zero after use (the
+  // ranking kernel clears the flags, launch_clear_events the rest; all three
+  // are zeroed once at context creation); the paper form clears the count
+  // grid here
   if (!pairs)
     hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, s, w.count, bt.nvox, 0);
   if (bt.n > 0)
     hipLaunchKernelGGL(k_scatter<true>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
                        reinterpret_cast<const int4*>(ev), bt, w.count, w.vox, w.err,
-                       (uint8_t*)nullptr);
+                       (uint8_t*)nullptr, et.brick, pairs ? w.lines : (uint8_t*)nullptr);
   if (queries && bt.m > 0)
     hipLaunchKernelGGL(k_mark, dim3(blocks_for(bt.m, 256)), dim3(256), 0, s, queries, bt, w.vox,
                        w.qmark, w.err);
-  launch_rank(bt, w, et.brick, queries == nullptr, pairs, s);
-  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), s);
+  if (pairs)
+    launch_rank_lines(bt, w, et.brick, queries == nullptr, s);
+  else
+    launch_rank(bt, w, et.brick, queries == nullptr, s);
+  SparseRows sr;
+  if (pairs && et.sp > 0 && !dense_batch(bt)) {
+    sr.sp = et.sp;
+    sr.rs = et.rs;
+    sr.bv = et.brick.volume();
+    sr.ulist = w.ulist;
+    sr.srow = reinterpret_cast<int2*>(w.srow);
+  }
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), sr, s);
   // the paper form needs each row's voxel (and its expansion reads the query
   // -> row map); the other forms find rows as they expand
   if (!pairs && bt.m > 0)
@@ -720,16 +1068,11 @@ int launch_window_prepare(const Batch& bt, const Workspace& w, const veckm_event
   if (bt.n > 0) {
     // locate the query events and mark their voxels in one pass
     hipLaunchKernelGGL(k_scatter<false>, dim3(blocks_for(bt.n, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err, w.qmark);
+                       reinterpret_cast<const int4*>(queries), bt, w.count, w.vox, w.err, w.qmark,
+                       et.brick, (uint8_t*)nullptr);
   }
-  launch_rank(bt, w, et.brick, false, false, s);
-  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), s);
-  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
-}
-
-int launch_clear_counts(const Batch& bt, const Workspace& w, void* stream) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(bt.nvox)), dim3(256), 0, (hipStream_t)stream,
-                     w.count, bt.nvox, 0);
+  launch_rank(bt, w, et.brick, false, s);
+  launch_brick_scan(bt, w, bt.nbricks, encode_rows_per_chunk(et.d, et.layout), SparseRows{}, s);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

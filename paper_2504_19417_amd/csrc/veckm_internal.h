@@ -67,6 +67,13 @@ struct Tiling {
                    // 2 = 4 and 3 = 8 pipelined waves over all frequencies of their rows
 };
 constexpr int kMaxBrickVoxels = 8192;  // largest brick (the ranking kernel's limit)
+// Work items of the encoder that hold single rows carry this bit in their
+// brick field (brick numbers stay below it).
+constexpr int kSparseTag = 1 << 30;
+// Bricks with fewer rows than this go to the encoder row by row (each row
+// with its own count box, up to 16 rows per item), when 8 or more such
+// boxes fit in the LDS of the brick's box.
+constexpr int kSparseBelow = 12;
 std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precision, int kp);
 size_t encode_lds_need(int d, int precision, int nbuf, int kp, int vol, int layout = 0);
 int encode_rows_per_chunk(int d, int layout);
@@ -115,16 +122,19 @@ struct Batch {
 // The brick scan works on tiles of kScanTile bricks and keeps kScanNV
 // partial sums per tile.
 constexpr int kScanTile = 8192;
-constexpr int kScanNV = 13;
+constexpr int kScanNV = 14;
 inline int64_t scan_tiles(int64_t nb) { return (nb + kScanTile - 1) / kScanTile; }
 
 struct Workspace {
   int32_t* count = nullptr;     // voxels: int32 event counts, slices back to back; all zero
-                                // between slice calls (the encoder clears the rows' voxels of
-                                // calls that query every event; a query subset fills it after
-                                // use; the paper form fills it before its scatter)
+                                // between slice calls (k_clear_events returns the events'
+                                // voxels to zero after each call; the paper form fills it
+                                // before its scatter)
   uint32_t* pairs = nullptr;    // (W + 1) H T per slice: entry x + 1 of a row holds the fp16
-                                // counts of voxels x and x + 1 of that row, x in [-1, W)
+                                // counts of voxels x and x + 1 of that row, x in [-1, W); all
+                                // zero between bounded-window slice calls, like count
+  uint8_t* lines = nullptr;     // bricks x (by bt): 1 where the brick's x row holds an event;
+                                // all zero between slice calls (the ranking kernel clears them)
   const uint32_t* zeros = nullptr;  // 64 zero dwords (out-of-grid reads)
   int32_t* rank = nullptr;      // voxels: brick-local rank of query voxels
   uint8_t* qmark = nullptr;     // voxels: query-voxel marks (query subsets, windows); all zero
@@ -135,6 +145,8 @@ struct Workspace {
   int32_t* order = nullptr;     // 4 x bricks: the encoder's work list, most chunks first;
                                 // per brick {brick, rows, first row, slice}
   int32_t* scan_part = nullptr; // kScanNV ints per kScanTile bricks (brick-scan partials)
+  int32_t* srow = nullptr;      // 2 U: {brick, brick-local voxel} of each row of the bricks the
+                                // encoder takes row by row (numbered after all other rows)
   int32_t* vox = nullptr;       // n: slice-local voxel of each event, -1 if invalid
   int32_t* qmap = nullptr;      // m: row of each query, -1 if invalid
   int32_t* rowvox = nullptr;    // U: voxel of each row (paper form only)
@@ -164,6 +176,10 @@ struct PaperTables {
 struct EncodeTables {
   const uint16_t* frag = nullptr;  // fragment-native phase table over the slots
   const int32_t* runs = nullptr;   // KP / 4 run byte offsets
+  const int32_t* runs1 = nullptr;  // the same for the count box of a single voxel
+  // bricks with fewer than sp rows (0: none) go to the encoder row by row, in
+  // items of up to rs rows with a count box each
+  int sp = 0, rs = 1;
   const uint16_t* wts = nullptr;   // KP slot weights (fp16)
   int K = 0, KP = 0, na = 4;
   int nbuf = 3;  // k-step slabs of the table buffered in LDS (2 to 4)
@@ -225,11 +241,9 @@ int launch_paper_encode(const Batch& bt, const Workspace& w, const PaperTables& 
 void make_paper_tables(const double* A, int d, int width, int height, int max_bins,
                        std::vector<float>* ttab, std::vector<float>* xtab, std::vector<float>* ytab);
 constexpr int kMaxPaperBins = 1024;  // bins per slice of the paper form
-// clear: also return every row's voxel count to zero (calls that query every
-// event: their rows are exactly the counted voxels).
 // rowcnt: when non-NULL, also the neighbour count of every row (int32 [U]).
 int launch_encode(const Batch& bt, const Workspace& w, const EncodeTables& et, int rows,
-                  bool clear, int num_cus, void* stream, int32_t* rowcnt = nullptr,
+                  int num_cus, void* stream, int32_t* rowcnt = nullptr,
                   const MlpWeights* mw = nullptr);
 // Per-query outputs; use_qmap: rows from the query -> row map (paper form),
 // else found from each query's voxel (`queries` as in the call, or NULL).
@@ -246,8 +260,19 @@ int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queri
 // w.rowflow); -1 for an invalid query.
 int launch_expand_count(const Batch& bt, const Workspace& w, const int32_t* queries,
                         const Brick& b, int32_t* counts, void* stream);
-// The count grid of a batch back to zero (after a run that skipped the expansion).
-int launch_clear_counts(const Batch& bt, const Workspace& w, void* stream);
+// Whether a bounded-window slice call is dense: its count and pair grids
+// hold fewer than 30 entries per event.  Dense calls clear the two grids
+// with one pass over them (about 1.5 GB/ms against about 50 M events/ms for
+// per-event stores), rank a brick per block, and take every non-empty
+// brick whole in the encoder.
+inline bool dense_batch(const Batch& bt) { return bt.nvox + bt.npairs < 30 * (int64_t)bt.n; }
+// After a bounded-window slice call whose launches all went through: the
+// counts and pair entries of its events' voxels back to zero (the ranking
+// kernel has cleared the row flags).
+int launch_clear_events(const Batch& bt, const Workspace& w, void* stream);
+// Dense fill of the count grid, the pair grid and `nlines` row flags (for
+// workspaces whose contents are unknown).
+int launch_clear_grids(const Batch& bt, const Workspace& w, int64_t nlines, void* stream);
 // Copies the device error bits to `host` (pinned) and clears them, in stream order.
 int launch_take_err(const Workspace& w, int32_t* host, void* stream);
 // Sliding window: the bins [clear_b0, clear_b0 + clear_nb) enter the ring of

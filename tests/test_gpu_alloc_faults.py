@@ -43,9 +43,19 @@ def fault_env():
     os.environ.pop("VECKM_FAULT_ALLOC", None)
 
 
-def _free():
+def _free(at_least=None):
+    """Free device memory; with at_least, waits up to a second for it to
+    reach that level (the runtime may hand freed memory back a little
+    later)."""
+    import time
     torch.cuda.synchronize()
-    return torch.cuda.mem_get_info()[0]
+    free = torch.cuda.mem_get_info()[0]
+    for _ in range(20):
+        if at_least is None or free >= at_least:
+            break
+        time.sleep(0.05)
+        free = torch.cuda.mem_get_info()[0]
+    return free
 
 
 def _params(vk, rt=2, precision="fp32"):
@@ -75,9 +85,10 @@ def _sweep(vk, build, max_points=200):
             cleanup()
             break
         assert rc == vk.VECKM_E_NOMEM, (n, rc)
-        free = _free()
+        free = _free(base - SLACK)
         assert free >= base - SLACK, "allocation point %d leaked %d bytes" % (n, base - free)
-    assert _free() >= base - SLACK
+    free = _free(base - SLACK)
+    assert free >= base - SLACK, "the successful build leaked %d bytes" % (base - free)
     return n - 1
 
 
