@@ -203,7 +203,8 @@ int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
    HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
    veckm_flow_noalloc computes what veckm_flow computes with queries = NULL
    (every event queried; bit-identical results), but every per-call
-   workspace (count and pair grids, ranks, brick lists, rows, row flows) lives
+   workspace (count and pair grids, row flags, ranks, brick and row lists,
+   rows, row flows) lives
    in one static device array of VECKM_NOALLOC_SCRATCH_BYTES that the library
    holds on each GPU it runs on until the process ends.  Only the context's
    read-only state is used (phase table, tiling, perceptron weights) and its
@@ -212,11 +213,12 @@ int veckm_flow_batch(veckm_ctx* ctx, const veckm_slice* slices, int32_t count,
    hipFree or allocating library routine (the device address of the array is
    looked up once per device, on the first call there).
      Limits: those of veckm_flow on this context, and the call's workspaces
-     must fit in the array: about 13 W H nbins + (16 + 8 D) n bytes plus the
-     brick lists (a 346 x 260 sensor with 25 bins and 20k events at D = 64
-     needs 50 MB); beyond that it returns VECKM_E_BUDGET and launches nothing.
+     must fit in the array: about 16 W H nbins + (20 + 8 D) n bytes (a
+     346 x 260 sensor with 25 bins and 20k events at D = 64 needs 47 MB);
+     beyond that it returns VECKM_E_BUDGET and launches nothing.
      Sharing: every call on one GPU uses the same array and finds it as the
-     last call left it (the count grid is cleared at the start of each call).
+     last call left it (the count and pair grids and the row flags are
+     cleared at the start of each call).
      Calls that overlap on one GPU, on any streams or contexts or threads,
      race and give undefined results: serialise them (one stream, or
      synchronise between calls).

@@ -1014,8 +1014,10 @@ int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
     launch_rank_lines(bt, w, et.brick, queries == nullptr, s);
   else
     launch_rank(bt, w, et.brick, queries == nullptr, s);
+  // single rows, unless every brick is likely to hold many (a dense call
+  // with 32 or more rows per brick on average)
   SparseRows sr;
-  if (pairs && et.sp > 0 && !dense_batch(bt)) {
+  if (pairs && et.sp > 0 && !(dense_batch(bt) && (int64_t)bt.m >= 32 * (int64_t)bt.nbricks)) {
     sr.sp = et.sp;
     sr.rs = et.rs;
     sr.bv = et.brick.volume();

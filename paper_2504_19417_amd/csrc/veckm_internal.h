@@ -263,8 +263,9 @@ int launch_expand_count(const Batch& bt, const Workspace& w, const int32_t* quer
 // Whether a bounded-window slice call is dense: its count and pair grids
 // hold fewer than 30 entries per event.  Dense calls clear the two grids
 // with one pass over them (about 1.5 GB/ms against about 50 M events/ms for
-// per-event stores), rank a brick per block, and take every non-empty
-// brick whole in the encoder.
+// per-event stores) and rank a brick per block; with 32 or more rows per
+// brick on average they also take every non-empty brick whole in the
+// encoder (no single rows).
 inline bool dense_batch(const Batch& bt) { return bt.nvox + bt.npairs < 30 * (int64_t)bt.n; }
 // After a bounded-window slice call whose launches all went through: the
 // counts and pair entries of its events' voxels back to zero (the ranking

@@ -262,6 +262,14 @@ def test_slice1m_full_run_sampled_parity(vk, slice1m, precision):
     assert st == vk.VECKM_OK
     parity.check(emb[s["q"]], s["emb"], precision, "emb", say=_say)
     parity.check(flow[s["q"]], s["flow"], precision, "flow", say=_say)
+    # the sampled events as a query subset (about 15 per brick: most go to
+    # the encoder as single rows with their own count boxes): bit-identical
+    # to the same rows of the full run
+    _say("case: slice1m %s query subset of %d" % (precision, len(s["q"])))
+    emb_q, st = _run_encode(c, s["ev"], s["t0"], s["T"], queries=s["q"])
+    assert st == vk.VECKM_OK and np.array_equal(emb_q, emb[s["q"]])
+    flow_q, st = _run_flow(c, s["ev"], s["t0"], s["T"], queries=s["q"])
+    assert st == vk.VECKM_OK and np.array_equal(flow_q, flow[s["q"]])
     # P1: the exact windowed count of every event
     evt = torch.from_numpy(s["ev"]).cuda()
     cnt = c.count(evt, s["t0"], s["T"]).cpu().numpy()
