@@ -60,11 +60,11 @@ __device__ inline SliceDesc slice_by_event_block(const Batch& bt, int i) {
 // the slice-local voxel, and mark it as a query voxel when qmark is given
 // (a sliding window's query events).  With `lines` (bounded-window slice
 // calls) the event also flags its brick x row: lines[gb * by * bt + lt * by +
-// ly] = 1 for brick gb and brick-local row (ly, lt), so that ranking and
-// clearing visit only rows that hold events (plain byte stores: every
-// writer stores the same value).  Voxels over VECKM_MAX_VOXEL_EVENTS are
-// caught where the pair grid is built (k_rank_lines, k_rank, or k_pairs for
-// a sliding window), which reads every count once.
+// ly] = 1 for brick gb and brick-local row (ly, lt), so that ranking visits
+// only rows that hold events (plain byte stores: every writer stores the
+// same value).  Voxels over VECKM_MAX_VOXEL_EVENTS are caught where the pair
+// grid is built (k_rank_lines, k_rank, or k_pairs for a sliding window),
+// which reads every count once.
 template <bool ADD>
 __global__ void k_scatter(const int4* __restrict__ ev, Batch bt, int32_t* __restrict__ count,
                           int32_t* __restrict__ vox, int32_t* __restrict__ err,
@@ -535,6 +535,7 @@ constexpr int kScanClasses = 12;  // kScanNV = class counts, then rows of the
 constexpr int kRowsD = 12;        // bricks the encoder takes whole,
 constexpr int kRowsS = 13;        // then rows of the bricks it takes as single rows
 constexpr int kScanThreads = 1024, kScanPer = kScanTile / kScanThreads;
+constexpr int kScanSmall = 256;  // threads of the scan of up to 2048 bricks
 static_assert(kScanNV == kScanClasses + 2 && kScanTile % kScanThreads == 0, "scan tiles");
 
 // Bricks with fewer than `sp` rows (0: none) are not the encoder's work
@@ -557,19 +558,21 @@ __device__ inline int chunk_class(int nq, int ch) {
 // The tile's counts (coalesced through LDS), this thread's class counts and
 // rows in v[], their exclusive scan over the tile's threads in ex[], the
 // tile totals in tot[].
+template <int NT = kScanThreads>
 __device__ inline void scan_tile(const int32_t* __restrict__ nq, int nb, int ch, int sp, int tile,
                                  int (&q)[kScanPer], int (&v)[kScanNV], int (&ex)[kScanNV],
                                  int (&tot)[kScanNV]) {
-  constexpr int NWV = kScanThreads / 64;  // waves
-  __shared__ int tq[kScanTile];
+  constexpr int NWV = NT / 64;  // waves
+  constexpr int TILE = NT * kScanPer;
+  __shared__ int tq[TILE];
   __shared__ int wsum[kScanNV][NWV];
   __shared__ int ttot[kScanNV];
-  const int tid = threadIdx.x, base = tile * kScanTile;
+  const int tid = threadIdx.x, base = tile * TILE;
   const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
   for (int u = 0; u < kScanPer; ++u) {
-    const int i = base + u * kScanThreads + tid;
-    tq[u * kScanThreads + tid] = i < nb ? nq[i] : 0;
+    const int i = base + u * NT + tid;
+    tq[u * NT + tid] = i < nb ? nq[i] : 0;
   }
   __syncthreads();
 #pragma unroll
@@ -696,8 +699,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ntiles, int nb,
 
 // ONE = true: the bricks fit in one tile, and this single block does the
 // whole scan (part is not used; plan and off[nb] are written here).
-template <bool ONE, bool SP>
-__global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
+template <bool ONE, bool SP, int NT = kScanThreads>
+__global__ __launch_bounds__(NT) void k_scan_place(Batch bt,
                                                              const int32_t* __restrict__ nq,
                                                              int nb, int ch, SparseRows sr,
                                                              const int32_t* __restrict__ part,
@@ -705,7 +708,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
                                                              int4* __restrict__ order,
                                                              int32_t* __restrict__ plan) {
   int q[kScanPer], v[kScanNV], ex[kScanNV], tot[kScanNV];
-  scan_tile(nq, nb, ch, SP ? sr.sp : 0, blockIdx.x, q, v, ex, tot);
+  static_assert(ONE || NT == kScanThreads, "tiles of kScanTile bricks");
+  scan_tile<NT>(nq, nb, ch, SP ? sr.sp : 0, blockIdx.x, q, v, ex, tot);
   int pos[kScanNV];
   int ud;  // rows of the bricks taken whole: single rows start here
   if constexpr (ONE) {
@@ -721,7 +725,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
     // the single-row items follow the bricks in the work list
     const int us = SP ? tot[kRowsS] : 0, ns = SP ? (us + sr.rs - 1) / sr.rs : 0;
     if constexpr (SP)
-      for (int j = threadIdx.x; j < ns; j += kScanThreads)
+      for (int j = threadIdx.x; j < ns; j += NT)
         order[start + j] = make_int4(kSparseTag | j, min(sr.rs, us - j * sr.rs), ud + j * sr.rs,
                                      j * sr.rs);
     if (threadIdx.x == 0) {
@@ -736,7 +740,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_place(Batch bt,
     for (int k = 0; k < kScanNV; ++k) pos[k] = part[blockIdx.x * kScanNV + k] + ex[k];
     ud = plan[3];
   }
-  const int i0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  const int i0 = blockIdx.x * (NT * kScanPer) + threadIdx.x * kScanPer;
 #pragma unroll
   for (int u = 0; u < kScanPer; ++u) {
     const int i = i0 + u;
@@ -780,6 +784,15 @@ static void launch_brick_scan(const Batch& bt, const Workspace& w, int nb, int c
                               const SparseRows& sr, hipStream_t s) {
   const int ntiles = nb > 0 ? (int)scan_tiles(nb) : 1;
   int4* order = reinterpret_cast<int4*>(w.order);
+  if (nb <= kScanSmall * kScanPer) {  // one small block: a quarter of the issue work
+    if (sr.sp > 0)
+      hipLaunchKernelGGL((k_scan_place<true, true, kScanSmall>), dim3(1), dim3(kScanSmall), 0, s,
+                         bt, w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
+    else
+      hipLaunchKernelGGL((k_scan_place<true, false, kScanSmall>), dim3(1), dim3(kScanSmall), 0,
+                         s, bt, w.brick_nq, nb, ch, sr, w.scan_part, w.brick_off, order, w.plan);
+    return;
+  }
   if (ntiles == 1) {
     if (sr.sp > 0)
       hipLaunchKernelGGL((k_scan_place<true, true>), dim3(1), dim3(kScanThreads), 0, s, bt,
