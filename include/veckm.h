@@ -385,10 +385,11 @@ int veckm_trainer_get(veckm_trainer* tr, float* W1, float* b1, float* W2, float*
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Stages of one compute call, in launch order. */
-#define VECKM_STAGE_PREPARE 0 /* clear grid, validate + histogram events, rank query voxels */
-#define VECKM_STAGE_ENCODE 1  /* the count x offset-phase contraction (one kernel)          */
-#define VECKM_STAGE_MLP 2     /* the two-layer perceptron (one kernel)                      */
-#define VECKM_STAGE_EXPAND 3  /* per-voxel rows copied out per query (one kernel)           */
+#define VECKM_STAGE_PREPARE 0 /* validate + histogram events, rank query voxels, work list */
+#define VECKM_STAGE_ENCODE 1  /* the count x offset-phase contraction (one kernel; with the
+                                 perceptron inside it in the fused tilings)                 */
+#define VECKM_STAGE_MLP 2     /* the two-layer perceptron as its own kernel (none if fused) */
+#define VECKM_STAGE_EXPAND 3  /* per-voxel rows copied out per query, grids back to zero   */
 #define VECKM_NUM_STAGES 4
 
 /* Turns per-stage timing on (1) or off (0).  While on, every compute call
