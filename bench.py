@@ -395,13 +395,14 @@ PROFILE_WORKLOADS = {
                  "queries",
 }
 PROFILE_NOTES = {
-    "slice1m": "Each form runs 2 warm-up + 5 timed steps (7 calls per form; the 10k-query "
-               "run is skipped).  The encoders run the perceptron themselves (template "
-               "arguments: operand terms, slab tiles, wave layout, ring depth, row format): "
-               "`k_encode<4, 8, 3, 2, 5>` is the FP32 form (fp16 hi/lo operands), "
-               "`k_encode<2, 8, 3, 2, 4>` the FP16/BF16 form (bf16 perceptron); the front-end "
-               "and expansion kernels serve both.  `__amd_rocclr_*` are runtime copies and "
-               "fills outside the steps.",
+    "slice1m": "Each form runs 2 warm-up + 5 timed steps on its default tiling (7 calls per "
+               "form; the 10k-query run and the tuner are skipped).  The encoders run the "
+               "perceptron themselves (template arguments: operand terms, slab tiles, wave "
+               "layout, ring depth, row format): `k_encode<4, 8, 3, 2, 5>` is the FP32 form "
+               "(8 waves, fp16 hi/lo operands; also the tuner's pick), `k_encode<2, 8, 4, 2, 4>` "
+               "the FP16/BF16 form (16 waves, bf16 perceptron; the tuner picks the same layout "
+               "on the 32x16x16 brick); the front-end and expansion kernels serve both.  "
+               "`__amd_rocclr_*` are runtime copies and fills outside the steps.",
     "paper_k8": "Three runs of 2 warm-up + 5 timed steps: FP32 form over all events, FP16/BF16 "
                 "form over all events, FP32 form over the 10k-query subset (7 calls each).  "
                 "`k_paper_rows<false>` and `k_mlp_split` serve the FP32 runs (all events and 10k "
@@ -415,9 +416,12 @@ PROFILE_NOTES["precision5m"] = (
     "and perceptron), 2 warm-up and 5 timed steps.  Template arguments of `k_encode`: operand "
     "terms (2: FP16/BF16 form, 4: FP32 form's hi/lo), slab tiles, wave layout, ring depth, row "
     "format (1: bf16 rows, 3: hi/lo rows, both for `k_mlp_res`; 4 and 5: perceptron inside the "
-    "encoder, bf16 and hi/lo operands).  The fused `<2, 8, 3, 2, 4>` and `<4, 8, 3, 2, 5>` are "
-    "the tuner's picks and run the timed steps; the rest are tuner trials.  The brick scan "
-    "runs as three launches (23,400 bricks: three 8192-brick tiles).")
+    "encoder, bf16 and hi/lo operands).  The fused `<2, 8, 4, 2, 4>` (16 waves, 32x32x8 brick "
+    "in this run) and `<4, 8, 3, 2, 5>` (8 waves, 32x16x8 brick) are the tuner's picks and run "
+    "the timed "
+    "steps (the same template names also cover tuner trials on other bricks); the rest are "
+    "tuner trials.  The brick scan runs as three launches (23,400 bricks: three 8192-brick "
+    "tiles).")
 PROFILE_NOTES["batch64"] = (
     "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end and "
     "encoder), 1 warm-up and 3 timed steps.  FP16 form tilings: `k_encode<2, 8, 4, 1>` is the "
@@ -990,6 +994,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sparse", action="store_true",
                     help="skip the 10k-query run (profiling runs: one call size per kernel)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="slice1m: keep each form's default encoder tiling instead of the "
+                         "tuner's pick (profiling runs: no tuner trials among the kernels)")
     ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="real-time replay of the 32-stream serving workload (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1060,7 +1067,9 @@ def main():
 
     res = {}
     for form in ("fp32", "fp16"):
-        res[form] = run_form(vk, torch, w, ev, t0, T, A, mlp, form, args.steps, args.warmup)
+        # the encoder tiling picked by the library's tuner (set-up, not timed)
+        res[form] = run_form(vk, torch, w, ev, t0, T, A, mlp, form, args.steps, args.warmup,
+                             tune=not args.no_tune)
     # sparse query set (Eqn. 18's C m term shrinks, the c n term stays)
     sparse = None
     if not args.no_sparse:
@@ -1130,7 +1139,7 @@ def main():
         "data": "synthetic (seeded moving edges + 10% uniform noise)",
         "config": {"workload": "slice1m", "sensor": "346x260", "events": n, "bins": T,
                    "d": w.d, "radius_xy": w.rx, "radius_t": w.rt, "hidden": w.hidden,
-                   "queries": "all events"},
+                   "queries": "all events", "tiling_brick_slabs": res["fp32"]["tiling"]},
         "latency_ms": lat(res["fp32"]),
         "err_vs_oracle": err32,
         "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st32.items()},
@@ -1141,6 +1150,7 @@ def main():
             "stages_ms": {k: (round(v, 4) if v is not None else None) for k, v in st16.items()},
             "err_vs_oracle": err16,
             "dtype": "fp16 phase table, bf16 perceptron, fp32 accumulation",
+            "tiling_brick_slabs": res["fp16"]["tiling"],
         },
         "sparse_10k_queries": None if sparse is None else {
             "ms_per_call": round(ms_sparse, 4),

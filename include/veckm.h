@@ -265,11 +265,11 @@ void veckm_graph_destroy(veckm_graph* graph);
    shape x buffered slabs x wave layout): the largest brick that fits beside
    two slabs (as many slabs as fit), larger bricks with fewer slabs, which
    pay off where bricks hold few query voxels (sparse slices), and each of
-   those with other wave layouts.  At D = 64 and 128 index 0 is the default
-   brick in wave layout 3, whose encoder also runs the perceptron (flow
-   calls keep every encoding on the chip); elsewhere index 0 is the default
-   brick in layout 0.  Encodings do not depend on the tiling (bit-identical);
-   flows are bit-identical among layouts 0 and 1 and among layouts 2 and 3,
+   those with other wave layouts.  At D = 64 and 128 index 0 is a layout
+   whose encoder also runs the perceptron (flow calls keep every encoding on
+   the chip): the default brick in wave layout 3 (FP32 form) or 4 (FP16
+   form); elsewhere index 0 is the default brick in layout 0.  Encodings do not depend on the tiling (bit-identical);
+   flows are bit-identical among layouts 0 and 1 and among layouts 2 to 4,
    and agree between the two groups to fp32 rounding (the perceptron's sums
    run in another order).
      veckm_tiling_count     number of tilings (>= 1), or VECKM_E_INVAL
@@ -277,11 +277,12 @@ void veckm_graph_destroy(veckm_graph* graph);
      veckm_tiling_info      info[0..4] = brick x, y, t sides, slabs and wave
                             layout (0: 16 waves of 2 row tiles; 1: 8 waves
                             of 4 row tiles, each table fragment feeding
-                            twice the products; 2: 4 waves of 4 row tiles
-                            and 3: 8 waves of 2 row tiles, each wave over
-                            every frequency of its rows, loads pipelined
-                            within the wave, one slab in flight, the
-                            perceptron inside the encoder at D = 64 and 128)
+                            twice the products; 2: 4 waves of 4 row tiles,
+                            3: 8 waves of 2 row tiles and 4: 16 waves of
+                            one row tile (D <= 128), each wave over every
+                            frequency of its rows, loads pipelined within
+                            the wave, one slab in flight, the perceptron
+                            inside the encoder at D = 64 and 128)
                             of tiling `index` (host int32[5])
      veckm_tiling_select    use tiling `index` from the next call on
      veckm_tune             times every tiling on the given batch (as for

@@ -137,11 +137,13 @@ __host__ __device__ constexpr size_t slice_table_offset(size_t bytes) { return (
 // waves to hide latency); 2 = 4 waves (one per SIMD) of 2 kEncMt row tiles
 // over up to 8 frequency tiles (128 frequencies: every count gather feeds
 // all of a row's frequencies, every table fragment four row tiles; the
-// accumulators take the register file's accumulation half).
+// accumulators take the register file's accumulation half); 3 = 8 waves of
+// kEncMt row tiles and 4 = 16 waves of one row tile, each over every
+// frequency of its rows (more waves to hide latency, 128 registers each).
 constexpr int enc_waves(int L) {
-  return L == 0 ? kEncWaves : L == 1 ? kEncWaves / 2 : L == 2 ? kEncWaves / 4 : kEncWaves / 2;
+  return L == 0 || L == 4 ? kEncWaves : L == 1 ? kEncWaves / 2 : L == 2 ? kEncWaves / 4 : kEncWaves / 2;
 }
-constexpr int enc_mt(int L) { return L == 0 || L == 3 ? kEncMt : 2 * kEncMt; }
+constexpr int enc_mt(int L) { return L == 4 ? kEncMt / 2 : L == 0 || L == 3 ? kEncMt : 2 * kEncMt; }
 constexpr int enc_max_ntw(int L) { return L >= 2 ? 2 * kEncMaxNtw : kEncMaxNtw; }
 // layouts whose k-steps are software-pipelined within each wave
 constexpr bool enc_pipelined(int L) { return L >= 2; }
@@ -1051,6 +1053,8 @@ static int launch_layout(const EncArgs& a, const EncodeTables& et, int rows, int
     if (et.layout == 2) return launch_nb<NA, NT, 2>(a, et, rows, num_cus, s);
     if (et.layout == 3) return launch_nb<NA, NT, 3>(a, et, rows, num_cus, s);
   }
+  if constexpr (NT == 4 || NT == 8)
+    if (et.layout == 4) return launch_nb<NA, NT, 4>(a, et, rows, num_cus, s);
   return launch_nb<NA, NT, 0>(a, et, rows, num_cus, s);
 }
 
@@ -1073,7 +1077,7 @@ int encode_waves(int layout) { return enc_waves(layout); }
 
 bool encode_fusable(const EncodeTables& et, int hidden) {
   const int nt = et.d / 16;
-  if ((et.layout != 2 && et.layout != 3) || (nt != 4 && nt != 8) || hidden < 64 || hidden % 32)
+  if (et.layout < 2 || et.layout > 4 || (nt != 4 && nt != 8) || hidden < 64 || hidden % 32)
     return false;
   const int vol = box_dwords(et.brick, et.rx, et.ry, et.rt);
   const size_t lds = slice_table_offset(encode_lds_need(et.d, et.na == 4 ? VECKM_FP32 : VECKM_FP16,

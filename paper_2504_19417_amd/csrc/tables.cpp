@@ -283,12 +283,13 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
   }
   // each of them also with the other wave layouts (four frequency tiles or
   // more per wave: D >= 64), where they fit: 8 waves of 4 row tiles over half
-  // the frequencies (1); 4 (2) or 8 (3) waves over every frequency of their
-  // rows, whose loads are pipelined within each wave with one slab in flight
-  // (and whose encoder can run the perceptron itself)
+  // the frequencies (1); 4 (2), 8 (3) or, at D <= 128, 16 (4) waves over
+  // every frequency of their rows, whose loads are pipelined within each
+  // wave with one slab in flight (and whose encoder can run the perceptron
+  // itself)
   const size_t n = out.size();
-  for (int layout = 1; layout <= 3; ++layout)
-    for (size_t i = 0; i < n && d >= 64; ++i) {
+  for (int layout = 1; layout <= 4; ++layout)
+    for (size_t i = 0; i < n && d >= 64 && (layout < 4 || d <= 128); ++i) {
       Tiling t = out[i];
       t.layout = layout;
       if (layout >= 2) {
@@ -306,18 +307,27 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
         continue;
       out.push_back(t);
     }
-  // where the encoder can run the perceptron itself (D = 64 or 128), the
-  // 8-wave pipelined layout on the default brick comes first: it measured
-  // fastest for flows on dense slices (fused perceptron, no rows in HBM)
-  if (d == 64 || d == 128)
-    for (size_t k = 1; k < out.size(); ++k)
-      if (out[k].layout == 3 && out[k].brick.bx == def.brick.bx && out[k].brick.by == def.brick.by &&
-          out[k].brick.bt == def.brick.bt) {
-        const Tiling t = out[k];
-        out.erase(out.begin() + (long)k);
-        out.insert(out.begin(), t);
-        break;
-      }
+  // where the encoder can run the perceptron itself (D = 64 or 128), a
+  // pipelined layout on the default brick comes first: it measured fastest
+  // for flows on dense slices (fused perceptron, no rows in HBM).  The FP32
+  // form: 8 waves (16 waves spill its registers).  The FP16 form: 16 waves
+  // (0.32 against 0.36 ms for 8 waves on the 1M-event slice; the tuner
+  // finds the larger bricks' 0.30 ms where slices are long enough for them).
+  if (d == 64 || d == 128) {
+    const int want = precision == VECKM_FP16 ? 4 : 3;
+    long pick = -1;
+    for (size_t k = 1; k < out.size() && pick < 0; ++k) {
+      const Tiling& t = out[k];
+      if (t.layout == want && t.brick.bx == def.brick.bx && t.brick.by == def.brick.by &&
+          t.brick.bt == def.brick.bt)
+        pick = (long)k;
+    }
+    if (pick > 0) {
+      const Tiling t = out[(size_t)pick];
+      out.erase(out.begin() + pick);
+      out.insert(out.begin(), t);
+    }
+  }
   return out;
 }
 
