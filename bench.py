@@ -80,15 +80,19 @@ def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=
     ctx.set_mlp(*mlp)
     evt = torch.from_numpy(ev).cuda()
     tiling = None
-    if tune:  # the library's tuner picks the encoder tiling (set-up, not timed)
-        W, H = w.slices[0].width, w.slices[0].height
-        tiling = list(ctx.tilings()[ctx.tune([(W, H, t0, T, len(ev))], evt, reps=3)])
     qt = None if queries is None else torch.from_numpy(np.asarray(queries, np.int32)).cuda()
     m = len(ev) if queries is None else len(queries)
     out = torch.empty((m, 2), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.flow(evt, t0, T, qt, out=out)
+    if tune:
+        # the library's tuner picks the encoder tiling (set-up, not timed),
+        # once the device has warmed up: the first few tens of calls run slow
+        W, H = w.slices[0].width, w.slices[0].height
+        tiling = list(ctx.tilings()[ctx.tune([(W, H, t0, T, len(ev))], evt, reps=5)])
+        for _ in range(warmup):
+            ctx.flow(evt, t0, T, qt, out=out)
     torch.cuda.synchronize()
     if ctx.status() != vk.VECKM_OK:
         raise RuntimeError("input error reported by the device")
@@ -395,13 +399,16 @@ PROFILE_WORKLOADS = {
                  "queries",
 }
 PROFILE_NOTES = {
-    "slice1m": "Each form runs 2 warm-up + 5 timed steps on its default tiling (7 calls per "
-               "form; the 10k-query run and the tuner are skipped).  The encoders run the "
+    "slice1m": "As the bench runs it (the 10k-query run and serving skipped): each form "
+               "warms up 50 steps, runs the tuner's trials of every tiling, warms up 50 more "
+               "steps on the tuner's pick and times 20; the averages are over each kernel's "
+               "last 20 dispatches (the timed steps; the first few tens of calls after start "
+               "run up to 12 % slower).  The encoders run the "
                "perceptron themselves (template arguments: operand terms, slab tiles, wave "
                "layout, ring depth, row format): `k_encode<4, 8, 3, 2, 5>` is the FP32 form "
-               "(8 waves, fp16 hi/lo operands; also the tuner's pick), `k_encode<2, 8, 4, 2, 4>` "
-               "the FP16/BF16 form (16 waves, bf16 perceptron; the tuner picks the same layout "
-               "on the 32x16x16 brick); the front-end and expansion kernels serve both.  "
+               "(8 waves, fp16 hi/lo operands, 32x16x8 brick), `k_encode<2, 8, 4, 2, 4>` the "
+               "FP16/BF16 form (16 waves, bf16 perceptron, 32x16x16 brick); the other encoder "
+               "instances are tuner trials; the front-end and expansion kernels serve both.  "
                "`__amd_rocclr_*` are runtime copies and fills outside the steps.",
     "paper_k8": "Three runs of 2 warm-up + 5 timed steps: FP32 form over all events, FP16/BF16 "
                 "form over all events, FP32 form over the 10k-query subset (7 calls each).  "
@@ -461,16 +468,33 @@ def profiled_ms(workload, kernel):
         return None
 
 
-def summarize_kernels(stats_dir, command, workload="slice1m"):
-    """Markdown summary of a rocprofv3 --kernel-trace --stats run."""
+def summarize_kernels(stats_dir, command, workload="slice1m", last=0):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run.  With
+    last > 0 the table also gives each kernel's average over its last
+    `last` dispatches (the timed steps, after warm-up and tuner trials),
+    and that average is the one recorded for the bench's cross-check."""
     import csv
     rows = list(csv.DictReader(open(_find_csv(stats_dir, "kernel_stats.csv"))))
+    tail = {}
+    if last > 0:
+        trace = list(csv.DictReader(open(_find_csv(stats_dir, "kernel_trace.csv"))))
+        trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+        per = {}
+        for r in trace:
+            per.setdefault(r["Kernel_Name"], []).append(
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        tail = {k: sum(v[-last:]) / len(v[-last:]) for k, v in per.items()}
+        for r in rows:
+            if r["Name"] in tail:
+                r["AverageNs"] = str(tail[r["Name"]])
+                r["Calls"] = str(min(int(r["Calls"]), last))
     record_kernel_times(rows, workload)
     out = ["# Kernel times: " + PROFILE_WORKLOADS[workload], "",
            "Commands (R = repository root, one MI355X, ROCm 7.2):", ""]
     out += ["    " + c for c in command.split(" ; ")]
+    head = "average (us)" if not last else "average of the last %d (us)" % last
     out += ["", PROFILE_NOTES[workload], "",
-            "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+            "| kernel | calls | %s | min (us) | max (us) | share of GPU time |" % head,
             "|---|---:|---:|---:|---:|---:|"]
     for r in rows:
         out.append("| `%s` | %s | %.1f | %.1f | %.1f | %.2f %% |" % (
@@ -989,7 +1013,7 @@ def main():
                     help="slice1m: the bounded-window 1M-event slice (the headline line); "
                          "paper_k8 / paper_k10: the paper's own form at its recipes")
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sparse", action="store_true",
@@ -1008,6 +1032,9 @@ def main():
     ap.add_argument("--summarize-kernels", metavar="STATS_DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats run into "
                          "profiles/kernels_<workload>.md and exit (no GPU needed)")
+    ap.add_argument("--last", type=int, default=0,
+                    help="with --summarize-kernels: average each kernel over its last N "
+                         "dispatches (the timed steps)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_DIR",
                     help="summarise rocprofv3 --pmc runs (MFMA, LDS and L2 counters) into "
                          "profiles/counters_<workload>.md and exit (no GPU needed)")
@@ -1028,7 +1055,7 @@ def main():
                 f.write(traffic_markdown(rec, wl))
             print(json.dumps(rec["kernels"], indent=1))
         if args.summarize_kernels:
-            text = summarize_kernels(args.summarize_kernels, args.command, wl)
+            text = summarize_kernels(args.summarize_kernels, args.command, wl, args.last)
             with open(os.path.join(ROOT, "profiles", "kernels_%s.md" % wl), "w") as f:
                 f.write(text)
         return
