@@ -405,8 +405,8 @@ PROFILE_NOTES = {
                "last 20 dispatches (the timed steps; the first few tens of calls after start "
                "run up to 12 % slower).  The encoders run the "
                "perceptron themselves (template arguments: operand terms, slab tiles, wave "
-               "layout, ring depth, row format): `k_encode<4, 8, 3, 2, 5>` is the FP32 form "
-               "(8 waves, fp16 hi/lo operands, 32x16x8 brick), `k_encode<2, 8, 4, 2, 4>` the "
+               "layout, ring depth, row format): `k_encode<4, 8, 4, 2, 5>` is the FP32 form "
+               "(16 waves, fp16 hi/lo operands, 32x16x8 brick), `k_encode<2, 8, 4, 2, 4>` the "
                "FP16/BF16 form (16 waves, bf16 perceptron, 32x16x16 brick); the other encoder "
                "instances are tuner trials; the front-end and expansion kernels serve both.  "
                "`__amd_rocclr_*` are runtime copies and fills outside the steps.",

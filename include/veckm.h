@@ -267,8 +267,8 @@ void veckm_graph_destroy(veckm_graph* graph);
    pay off where bricks hold few query voxels (sparse slices), and each of
    those with other wave layouts.  At D = 64 and 128 index 0 is a layout
    whose encoder also runs the perceptron (flow calls keep every encoding on
-   the chip): the default brick in wave layout 3 (FP32 form) or 4 (FP16
-   form); elsewhere index 0 is the default brick in layout 0.  Encodings do not depend on the tiling (bit-identical);
+   the chip): the default brick in wave layout 4; elsewhere index 0 is the
+   default brick in layout 0.  Encodings do not depend on the tiling (bit-identical);
    flows are bit-identical among layouts 0 and 1 and among layouts 2 to 4,
    and agree between the two groups to fp32 rounding (the perceptron's sums
    run in another order).

@@ -307,14 +307,14 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
         continue;
       out.push_back(t);
     }
-  // where the encoder can run the perceptron itself (D = 64 or 128), a
-  // pipelined layout on the default brick comes first: it measured fastest
-  // for flows on dense slices (fused perceptron, no rows in HBM).  The FP32
-  // form: 8 waves (16 waves spill its registers).  The FP16 form: 16 waves
-  // (0.32 against 0.36 ms for 8 waves on the 1M-event slice; the tuner
-  // finds the larger bricks' 0.30 ms where slices are long enough for them).
+  // where the encoder can run the perceptron itself (D = 64 or 128), the
+  // 16-wave pipelined layout on the default brick comes first: it measured
+  // fastest for flows on dense slices (fused perceptron, no rows in HBM;
+  // on the 1M-event slice 0.48 against 0.52 ms for 8 waves in the FP32
+  // form, 0.32 against 0.36 ms in the FP16 form, where the tuner finds the
+  // larger bricks' 0.30 ms when slices are long enough for them).
   if (d == 64 || d == 128) {
-    const int want = precision == VECKM_FP16 ? 4 : 3;
+    const int want = 4;
     long pick = -1;
     for (size_t k = 1; k < out.size() && pick < 0; ++k) {
       const Tiling& t = out[k];
