@@ -439,10 +439,10 @@ __device__ inline void chunk_ksteps_p(int nsteps, const uint4* frag, uint4* slab
   using S = EncShape<NA, NT, L>;
   constexpr int NW = S::NW, NTW = S::NTW, SLAB_U4 = S::SLAB_U4, PFW = S::PFW, WM = S::WM;
   constexpr int AHEAD = NBUF - 1;
-  // (the 16-wave layout's FP32 form reads each tile's fragments just before
-  // its products: four waves per SIMD hide the wait, and the registers of a
-  // second set would not fit in 128)
-  constexpr int TA = L == 4 && NA == 4 ? 0 : kTfAhead < NTW ? kTfAhead : NTW - 1;
+  // (the 16-wave layout reads each tile's fragments just before its
+  // products: four waves per SIMD hide the wait, and with a second set of
+  // fragments its registers spill past 128)
+  constexpr int TA = L == 4 ? 0 : kTfAhead < NTW ? kTfAhead : NTW - 1;
   const int g = lane >> 4;
   const int total = FUSE ? nsteps + fz.msteps : nsteps;  // slabs through the ring
   const int2* runs2 = reinterpret_cast<const int2*>(runs_l);

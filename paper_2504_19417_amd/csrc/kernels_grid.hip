@@ -249,20 +249,24 @@ __global__ __launch_bounds__(256) void k_rank(Batch bt, Brick b, const int32_t* 
 // k_rank for bounded-window slice calls, visiting only the brick x rows
 // that k_scatter flagged (`lines`).  Every other voxel of the brick has a
 // zero count and no query, so it is neither loaded nor ranked.  One wave
-// per brick (four bricks per block): it copies the brick's row flags to LDS
-// and clears them there (the last reader; a brick without a flagged row only
-// writes its zero row count), then walks the brick in voxel order, 64 voxels
-// per step, in groups of kG steps: each lane issues the group's loads (its
-// count, and the count beside it that the pair entries need: left of a row's
-// first voxel, right of its last) before using any; lanes of unflagged rows
-// load nothing and a group without a flagged row is skipped.  The wave
-// numbers the query voxels as it goes.  The pair grid is all zero between
-// such calls (k_clear_events returns it there), so only the entries a
-// flagged row touches are written: entry x of each of its voxels, and entry
-// x + 1 of its last voxel in the slice (which the neighbouring brick may also
-// write, with the same value: both read the final counts).  A flagged row
-// lies inside the slice (flags come from valid events only); its voxels
-// beyond the slice's x edge are not flagged.
+// per brick (four bricks per block): it lists the brick's flagged rows in
+// LDS, in row order, and clears their flags (the last reader; a brick
+// without a flagged row only writes its zero row count).  Then it walks the
+// listed rows, 64 / bx of them per step (a lane per voxel), in groups of
+// kG steps: each lane issues the group's loads (its count, and the count
+// beside it that the pair entries need: left of a row's first voxel, right
+// of its last) before using any.  A brick's rows hold a few tens of events
+// in sparse calls, so most of its rows are not visited at all and the wave
+// waits on few rounds of loads.  Rows are listed in order and a row's
+// voxels are consecutive lanes, so the wave numbers the query voxels in
+// brick-local voxel order (as k_rank_lines4 does).  The pair grid is all
+// zero between such calls (k_clear_events returns it there), so only the
+// entries a flagged row touches are written: entry x of each of its voxels,
+// and entry x + 1 of its last voxel in the slice (which the neighbouring
+// brick may also write, with the same value: both read the final counts).
+// A flagged row lies inside the slice (flags come from valid events only);
+// its voxels beyond the slice's x edge are skipped.  Dynamic LDS: 4 waves x
+// by x bt row numbers (uint16).
 template <bool ALL>
 __global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
                                                     const int32_t* __restrict__ count,
@@ -273,28 +277,44 @@ __global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
                                                     int32_t* __restrict__ brick_nq,
                                                     uint32_t* __restrict__ pairs,
                                                     int32_t* __restrict__ err) {
-  constexpr int kG = 8;
-  __shared__ uint8_t sfl[4][kMaxBrickVoxels / 4];  // each wave's row flags (bx >= 4)
+  constexpr int kG = 8, kU = 8;
+  extern __shared__ uint16_t rl_rows[];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gb = blockIdx.x * 4 + wid;
+  if (gb >= bt.nbricks) return;  // (no barriers below: each wave keeps to its own rows)
   const int NL = b.by * b.bt;
-  int any = 0;
-  if (gb < bt.nbricks) {
+  uint16_t* rows = rl_rows + wid * NL;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int nr = 0;  // flagged rows (wave-uniform)
+  {
     uint8_t* fl = lines + (int64_t)gb * NL;
-    for (int l = lane; l < NL; l += 64) {
-      const uint8_t f = fl[l];
-      sfl[wid][l] = f;
-      any |= f;
-      if (f) fl[l] = 0;  // (the last reader: the flags are clear for the next call)
+    for (int l0 = 0; l0 < NL; l0 += 64 * kU) {
+      uint8_t f[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int l = l0 + u * 64 + lane;
+        f[u] = l < NL ? fl[l] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int l = l0 + u * 64 + lane;
+        const unsigned long long bal = __ballot(f[u] != 0);
+        if (f[u]) {
+          rows[nr + __popcll(bal & below)] = (uint16_t)l;
+          fl[l] = 0;
+        }
+        nr += __popcll(bal);
+      }
     }
   }
-  __syncthreads();
-  if (gb >= bt.nbricks) return;
-  if (!__ballot(any)) {
+  if (nr == 0) {
     if (lane == 0) brick_nq[gb] = 0;
     return;
   }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const SliceDesc s = slice_by_brick(bt, gb);  // (gb is uniform: scalar loads)
   const int lb = gb - s.brick_off;
   const int bxi = lb % s.nbx, byi = (lb / s.nbx) % s.nby, bti = lb / (s.nbx * s.nby);
@@ -302,6 +322,8 @@ __global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
   const int sx = __builtin_ctz(b.bx), sy = __builtin_ctz(b.by);
   const int x0 = bxi * b.bx, y0 = byi * b.by, t0 = bti * b.bt;
   const int lx = lane & (b.bx - 1);  // the voxel's x within the brick (b.bx <= 64)
+  const int slot = lane >> sx;       // which of the step's rows
+  const int rps = 64 >> sx;          // rows per step
   const int x = x0 + lx;
   // slice-local voxel of brick-local li (slices hold fewer than 2^31 voxels)
   auto at = [&](int li) -> int {
@@ -310,31 +332,30 @@ __global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
   };
   const int32_t* cnt = count + s.grid_off;
   const bool has_left = lx == 0 && x > 0, has_right = lx == b.bx - 1 && x + 1 < s.W;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  const int steps = (BV + 63) >> 6;
+  const int steps = (nr + rps - 1) / rps;
   int base = 0;
   bool bad = false;
   for (int k0 = 0; k0 < steps; k0 += kG) {
     bool lf[kG];
-    bool anyf = false;
+    int lis[kG];
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
-      const int li = (k0 + g) * 64 + lane;
-      lf[g] = li < BV && x < s.W && sfl[wid][li >> sx] != 0;
-      anyf |= lf[g];
+      const int j = (k0 + g) * rps + slot;
+      lf[g] = j < nr && x < s.W;
+      lis[g] = j < nr ? ((int)rows[j] << sx) + lx : 0;
     }
-    if (!__ballot(anyf)) continue;
     int cv[kG], side[kG];
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
-      const int o = at((k0 + g) * 64 + lane);
+      const int o = at(lis[g]);
       cv[g] = lf[g] ? cnt[o] : 0;
       side[g] = lf[g] && (has_left || has_right) ? cnt[has_left ? o - 1 : o + 1] : 0;
     }
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
+      if (k0 + g >= steps) break;  // (wave-uniform)
       const int up = __shfl_up(cv[g], 1);  // (all lanes)
-      const int li = (k0 + g) * 64 + lane;
+      const int li = lis[g];
       bool f = false;
       if (lf[g]) {
         const int y = y0 + ((li >> sx) & (b.by - 1)), t = t0 + (li >> (sx + sy));
@@ -972,15 +993,16 @@ static void launch_rank_lines(const Batch& bt, const Workspace& w, const Brick& 
                               hipStream_t s) {
   // dense calls: a block per brick; else a wave per brick (latency-bound
   // sparse bricks)
-  auto go = [&](auto fn, unsigned blocks) {
-    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, bt, b, w.count, w.lines, w.qmark,
+  auto go = [&](auto fn, unsigned blocks, size_t lds) {
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, bt, b, w.count, w.lines, w.qmark,
                        w.rank, w.ulist, w.brick_nq, w.pairs, w.err);
   };
   const unsigned nb = (unsigned)bt.nbricks, nb4 = (unsigned)((bt.nbricks + 3) / 4);
+  const size_t rows_lds = 4 * (size_t)b.by * b.bt * sizeof(uint16_t);  // (at most 16 KiB)
   if (dense_batch(bt))
-    all ? go(k_rank_lines4<true>, nb) : go(k_rank_lines4<false>, nb);
+    all ? go(k_rank_lines4<true>, nb, 0) : go(k_rank_lines4<false>, nb, 0);
   else
-    all ? go(k_rank_lines<true>, nb4) : go(k_rank_lines<false>, nb4);
+    all ? go(k_rank_lines<true>, nb4, rows_lds) : go(k_rank_lines<false>, nb4, rows_lds);
 }
 
 int launch_clear_events(const Batch& bt, const Workspace& w, void* stream) {
@@ -1007,8 +1029,9 @@ int launch_clear_grids(const Batch& bt, const Workspace& w, int64_t nlines, void
 int launch_prepare(const Batch& bt, const Workspace& w, const veckm_event* ev,
                    const int32_t* queries, const EncodeTables& et, bool pairs, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  // (a brick has at most kMaxBrickVoxels / 4 rows of flags)
-  if (pairs && et.brick.bx < 4) return VECKM_E_INVAL;
+  // (a brick has at most kMaxBrickVoxels / 4 rows of flags; a step of the
+  // ranking kernels holds whole rows)
+  if (pairs && (et.brick.bx < 4 || et.brick.bx > 64)) return VECKM_E_INVAL;
   // slice calls (not the paper form) find the count grid, the pair grid and
   // the row flags zero: every such call returns them to zero after use (the
   // ranking kernel clears the flags, launch_clear_events the rest; all three

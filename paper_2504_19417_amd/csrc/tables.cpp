@@ -308,11 +308,11 @@ std::vector<Tiling> tiling_candidates(int rx, int ry, int rt, int d, int precisi
       out.push_back(t);
     }
   // where the encoder can run the perceptron itself (D = 64 or 128), the
-  // 16-wave pipelined layout on the default brick comes first: it measured
-  // fastest for flows on dense slices (fused perceptron, no rows in HBM;
-  // on the 1M-event slice 0.48 against 0.52 ms for 8 waves in the FP32
-  // form, 0.32 against 0.36 ms in the FP16 form, where the tuner finds the
-  // larger bricks' 0.30 ms when slices are long enough for them).
+  // 16-wave pipelined layout on the default brick comes first: the fused
+  // perceptron keeps rows out of HBM, and on the 1M-event slice it runs
+  // the FP32 form as fast as the 8-wave layout (0.46 ms after warm-up) and
+  // the FP16 form's larger bricks about 4 % faster (0.31 against 0.32 ms;
+  // the tuner picks those bricks when slices are long enough for them).
   if (d == 64 || d == 128) {
     const int want = 4;
     long pick = -1;
