@@ -415,10 +415,13 @@ int run(veckm_ctx* c, const Workspace& w, const Batch& bt, const veckm_event* ev
   StageTimer t(c, VECKM_STAGE_EXPAND, stream);
   // (a window's queries are the query events themselves: index i is event i)
   const int32_t* q = c->window ? nullptr : queries;
-  int rc = flow     ? launch_expand_flow(bt, w, q, c->et.brick, c->paper, flow, stream)
+  // (the flows of a dense call and its grid clear share one launch)
+  const bool merged = flow && clear && !c->paper && dense_batch(bt);
+  int rc = merged   ? launch_expand_flow_clear(bt, w, q, c->et.brick, flow, stream)
+           : flow   ? launch_expand_flow(bt, w, q, c->et.brick, c->paper, flow, stream)
            : counts ? launch_expand_count(bt, w, q, c->et.brick, counts, stream)
                     : launch_expand_emb(bt, w, q, c->et.brick, c->paper, c->p.d, emb, stream);
-  if (clear) {
+  if (clear && (rc || !merged)) {
     const int rc2 = rc ? launch_clear_grids(bt, w, nlines, stream) : launch_clear_events(bt, w, stream);
     rc = rc ? rc : rc2;
   }

@@ -514,13 +514,18 @@ __global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
 // The count and pair grids of a dense call back to zero: one pass over both
 // (cheaper than the per-event stores when the grids are small beside the
 // events; see dense_batch).
-__global__ void k_fill2_zero(int32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
-                             int64_t nb) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+__device__ inline void fill2_zero(int blk, int nblk, int32_t* __restrict__ a, int64_t na,
+                                  uint32_t* __restrict__ b, int64_t nb) {
+  const int64_t stride = (int64_t)nblk * blockDim.x;
+  for (int64_t i = (int64_t)blk * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
     if (i < na) a[i] = 0;
     else b[i - na] = 0u;
   }
+}
+
+__global__ void k_fill2_zero(int32_t* __restrict__ a, int64_t na, uint32_t* __restrict__ b,
+                             int64_t nb) {
+  fill2_zero(blockIdx.x, gridDim.x, a, na, b, nb);
 }
 
 // After a bounded-window slice call: every valid event's voxel count and
@@ -914,17 +919,44 @@ __device__ inline int query_row(const int32_t* __restrict__ queries, const Batch
 }
 
 template <bool SUB>
-__global__ void k_expand_flow_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
-                                const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
-                                const int32_t* __restrict__ brick_off,
-                                const float2* __restrict__ rowflow, float2* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x * blockDim.x >= bt.m) return;  // (whole block; launches never do this)
+__device__ inline void expand_flow_q(int blk, const int32_t* __restrict__ queries, const Batch& bt,
+                                     const Brick& b, const int32_t* __restrict__ vox,
+                                     const int32_t* __restrict__ rank,
+                                     const int32_t* __restrict__ brick_off,
+                                     const float2* __restrict__ rowflow, float2* __restrict__ out) {
+  const int i = blk * blockDim.x + threadIdx.x;
+  if (blk * (int)blockDim.x >= bt.m) return;  // (whole block; launches never do this)
   const SliceDesc s = SUB ? bt.s0 : slice_by_event_block(bt, i);
   if (i >= bt.m) return;
   const int r = query_row<SUB>(queries, bt, s, b, vox, rank, brick_off, i);
   const float nan = __builtin_nanf("");
   out[i] = r >= 0 ? rowflow[r] : make_float2(nan, nan);
+}
+
+template <bool SUB>
+__global__ void k_expand_flow_q(const int32_t* __restrict__ queries, Batch bt, Brick b,
+                                const int32_t* __restrict__ vox, const int32_t* __restrict__ rank,
+                                const int32_t* __restrict__ brick_off,
+                                const float2* __restrict__ rowflow, float2* __restrict__ out) {
+  expand_flow_q<SUB>(blockIdx.x, queries, bt, b, vox, rank, brick_off, rowflow, out);
+}
+
+// The flows of a dense call and the clear of its count and pair grids in one
+// launch: blocks [0, eb) expand, the others zero the grids (k_fill2_zero's
+// work).  The expansion reads neither grid, so the two parts need no order,
+// and the call saves a launch.
+template <bool SUB>
+__global__ void k_expand_flow_q_fill(const int32_t* __restrict__ queries, Batch bt, Brick b,
+                                     const int32_t* __restrict__ vox,
+                                     const int32_t* __restrict__ rank,
+                                     const int32_t* __restrict__ brick_off,
+                                     const float2* __restrict__ rowflow, float2* __restrict__ out,
+                                     int eb, int32_t* __restrict__ count,
+                                     uint32_t* __restrict__ pairs) {
+  if ((int)blockIdx.x < eb)
+    expand_flow_q<SUB>(blockIdx.x, queries, bt, b, vox, rank, brick_off, rowflow, out);
+  else
+    fill2_zero(blockIdx.x - eb, gridDim.x - eb, count, bt.nvox, pairs, bt.npairs);
 }
 
 template <bool SUB>
@@ -1154,6 +1186,23 @@ int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queri
   else
     hipLaunchKernelGGL(k_expand_flow_q<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
                        w.rank, w.brick_off, rf, out);
+  return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
+}
+
+int launch_expand_flow_clear(const Batch& bt, const Workspace& w, const int32_t* queries,
+                             const Brick& b, float* flow, void* stream) {
+  if (!dense_batch(bt)) return VECKM_E_INVAL;
+  const int eb = bt.m > 0 ? blocks_for(bt.m, 256) : 0;
+  const dim3 grid(eb + fill_grid(bt.nvox + bt.npairs));
+  const float2* rf = reinterpret_cast<const float2*>(w.rowflow);
+  float2* out = reinterpret_cast<float2*>(flow);
+  hipStream_t s = (hipStream_t)stream;
+  if (queries)
+    hipLaunchKernelGGL(k_expand_flow_q_fill<true>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rf, out, eb, w.count, w.pairs);
+  else
+    hipLaunchKernelGGL(k_expand_flow_q_fill<false>, grid, dim3(256), 0, s, queries, bt, b, w.vox,
+                       w.rank, w.brick_off, rf, out, eb, w.count, w.pairs);
   return hipGetLastError() == hipSuccess ? VECKM_OK : VECKM_E_HIP;
 }
 

@@ -256,6 +256,11 @@ int launch_mlp(const Workspace& w, const MlpWeights& mw, int d, int rows, int nu
 bool mlp_rows_split(int d, int hidden);
 int launch_expand_flow(const Batch& bt, const Workspace& w, const int32_t* queries,
                        const Brick& b, bool use_qmap, float* flow, void* stream);
+// The flows of a dense bounded-window slice call (dense_batch) and the clear
+// of its count and pair grids, in one launch (launch_expand_flow followed by
+// launch_clear_events); VECKM_E_INVAL for a call that is not dense.
+int launch_expand_flow_clear(const Batch& bt, const Workspace& w, const int32_t* queries,
+                             const Brick& b, float* flow, void* stream);
 // Per-query neighbour counts from the rows' counts (int32 [U], held in
 // w.rowflow); -1 for an invalid query.
 int launch_expand_count(const Batch& bt, const Workspace& w, const int32_t* queries,
