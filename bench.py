@@ -430,13 +430,17 @@ PROFILE_NOTES["precision5m"] = (
     "tuner trials.  The brick scan runs as three launches (23,400 bricks: three 8192-brick "
     "tiles).")
 PROFILE_NOTES["batch64"] = (
-    "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end and "
-    "encoder), 1 warm-up and 3 timed steps.  FP16 form tilings: `k_encode<2, 8, 4, 1>` is the "
-    "default 32x16x8 brick (four slabs), `<2, 8, 2, 1>` the 32x32x8 brick (two slabs, the "
-    "tuner's pick: it also runs the timed steps), `<2, 8, 3, 1>` the 32x16x16 brick (three "
-    "slabs); `<4, 8, 2, 3>` is the FP32 form's encoder (one tiling fits).  `k_rank<true, 32>` "
-    "ranks the 8192-voxel bricks, `<true, 16>` the 4096-voxel ones.  The front-end kernels "
-    "serve both forms and the tuner runs.")
+    "Each form runs the tuner (every tiling: 1 untimed + 2 timed runs of the front end, "
+    "encoder and perceptron), 1 warm-up and 3 timed steps.  Template arguments of "
+    "`k_encode`: operand terms (2: FP16/BF16 form, 4: FP32 form's hi/lo), slab tiles, wave "
+    "layout, ring depth, row format (0-3: rows written for `k_mlp_res`; 4, 5: perceptron "
+    "inside the encoder).  The tuner's picks on this batch write rows in wave layout 0: "
+    "`k_encode<2, 8, 0, 2, 1>` (FP16 form, 32x32x8 brick) and `k_encode<4, 8, 0, 2, 3>` "
+    "(FP32 form, 32x16x8), with `k_mlp_res` after them; the other encoder instances are "
+    "tuner trials.  `k_rank_lines` ranks the flagged rows of the batch's bricks (a wave per "
+    "brick: the batch is sparse), `k_clear_events` returns the grids to zero after each "
+    "call, and the brick scan runs as three launches (`k_scan_totals`, `k_scan_tiles`, "
+    "`k_scan_place`).  The front-end kernels serve both forms and the tuner runs.")
 
 
 KERNELS_JSON = os.path.join(ROOT, "profiles", "kernels.json")
