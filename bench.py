@@ -12,7 +12,9 @@ D = 128, window +-5 px, +-3 bins, perceptron 256 -> 256 -> 2.
 Prints one JSON line.  `value` is the FP32 form's flows/s; the FP16/BF16
 form, per-step latency percentiles, per-stage device times, the roofline of
 the dominant kernel and the CPU oracle timed on a bounded sample are extra
-keys.  Only one GPU is used.
+keys.  The timed steps run the plain call; the latency percentiles (an event
+pair around each call) and the stage times (the library's stage timers) come
+from passes of the same number of steps after them.  Only one GPU is used.
 """
 import argparse
 import json
@@ -96,21 +98,31 @@ def run_form(vk, torch, w, ev, t0, T, A, mlp, precision, steps, warmup, queries=
     torch.cuda.synchronize()
     if ctx.status() != vk.VECKM_OK:
         raise RuntimeError("input error reported by the device")
-    ctx.profile(True)
-    ctx.profile_read()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    # the timed steps: the plain call, nothing recorded around it
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    for i in range(steps):
+        ctx.flow(evt, t0, T, qt, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    # after them, not part of the timed value: the latency of each call (an
+    # event pair around it), then the stage split from the library's stage
+    # timers (six event records per call, which add about 20 us to a step)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     for i in range(steps):
         starts[i].record(stream)
         ctx.flow(evt, t0, T, qt, out=out)
         ends[i].record(stream)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    ctx.profile(True)
+    ctx.profile_read()
+    for i in range(steps):
+        ctx.flow(evt, t0, T, qt, out=out)
+    torch.cuda.synchronize()
     stages = ctx.profile_read()
     ctx.profile(False)
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     rows = ctx.last_rows()
     flows = out.cpu().numpy()
     st = ctx.status()
@@ -813,13 +825,18 @@ def batch_main(args):
         for _ in range(args.warmup):
             c.flow_batch(specs, evt, out=out)
         torch.cuda.synchronize()
-        c.profile(True)
-        c.profile_read()
         t = time.perf_counter()
         for _ in range(args.steps):
             c.flow_batch(specs, evt, out=out)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
+        # the stage split, from the library's stage timers (after the timed
+        # steps: their event records add to each call)
+        c.profile(True)
+        c.profile_read()
+        for _ in range(args.steps):
+            c.flow_batch(specs, evt, out=out)
+        torch.cuda.synchronize()
         st = {k: (round(v[0] / v[1], 4) if v[1] else None) for k, v in c.profile_read().items()}
         c.profile(False)
         status = c.status()
