@@ -413,9 +413,10 @@ PROFILE_WORKLOADS = {
 PROFILE_NOTES = {
     "slice1m": "As the bench runs it (the 10k-query run and serving skipped): each form "
                "warms up 50 steps, runs the tuner's trials of every tiling, warms up 50 more "
-               "steps on the tuner's pick and times 20; the averages are over each kernel's "
-               "last 20 dispatches (the timed steps; the first few tens of calls after start "
-               "run up to 12 % slower).  The encoders run the "
+               "steps on the tuner's pick, times 20, then runs 20 with an event pair around "
+               "each call and 20 with the library's stage timers; the averages are over each "
+               "kernel's last 60 dispatches (those three passes; the first few tens of calls "
+               "after start run up to 12 % slower).  The encoders run the "
                "perceptron themselves (template arguments: operand terms, slab tiles, wave "
                "layout, ring depth, row format): `k_encode<4, 8, 4, 2, 5>` is the FP32 form "
                "(16 waves, fp16 hi/lo operands, 32x16x8 brick), `k_encode<2, 8, 4, 2, 4>` the "
