@@ -388,11 +388,12 @@ __global__ __launch_bounds__(256) void k_rank_lines(Batch bt, Brick b,
 }
 
 // k_rank_lines for dense calls (most bricks hold many rows): the same work
-// with one block per brick, each of its 4 waves taking a quarter of the
-// brick; the ballots of the query voxels go to LDS, one barrier gives every
-// wave its offset, and a second pass writes the numbers.
-template <bool ALL>
-__global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
+// with one block per brick, each of its NW waves taking an equal run of the
+// brick's voxel steps, in order; the ballots of the query voxels go to LDS,
+// one barrier gives every wave its offset, and a second pass writes the
+// numbers.
+template <bool ALL, int NW>
+__global__ __launch_bounds__(NW * 64) void k_rank_lines4(Batch bt, Brick b,
                                                      const int32_t* __restrict__ count,
                                                      uint8_t* __restrict__ lines,
                                                      uint8_t* __restrict__ qmark,
@@ -405,13 +406,13 @@ __global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
   constexpr int kSteps = kMaxBrickVoxels / 64;
   __shared__ uint8_t sfl[kMaxBrickVoxels / 4];  // the brick's row flags (bx >= 4)
   __shared__ unsigned long long sbal[kSteps];   // query-voxel ballot of each step
-  __shared__ int wave_tot[4];
+  __shared__ int wave_tot[NW];
   const int gb = blockIdx.x;
   const int NL = b.by * b.bt;
   int any = 0;
   {
     uint8_t* fl = lines + (int64_t)gb * NL;
-    for (int l = threadIdx.x; l < NL; l += 256) {
+    for (int l = threadIdx.x; l < NL; l += NW * 64) {
       const uint8_t f = fl[l];
       sfl[l] = f;
       any |= f;
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
   const int32_t* cnt = count + s.grid_off;
   const bool has_left = lx == 0 && x > 0, has_right = lx == b.bx - 1 && x + 1 < s.W;
   const int steps = (BV + 63) >> 6;
-  const int per = (steps + 3) >> 2;  // steps of each wave
+  const int per = (steps + NW - 1) / NW;  // steps of each wave
   const int k_lo = wid * per, k_hi = min(k_lo + per, steps);
   int tot = 0;
   bool bad = false;
@@ -495,7 +496,11 @@ __global__ __launch_bounds__(256) void k_rank_lines4(Batch bt, Brick b,
   __syncthreads();
   int base = 0;
   for (int w = 0; w < wid; ++w) base += wave_tot[w];
-  if (threadIdx.x == 0) brick_nq[gb] = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+  if (threadIdx.x == 0) {
+    int nq = 0;
+    for (int w = 0; w < NW; ++w) nq += wave_tot[w];
+    brick_nq[gb] = nq;
+  }
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int k = k_lo; k < k_hi; ++k) {
     const unsigned long long bal = sbal[k];
@@ -1029,12 +1034,22 @@ static void launch_rank_lines(const Batch& bt, const Workspace& w, const Brick& 
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, bt, b, w.count, w.lines, w.qmark,
                        w.rank, w.ulist, w.brick_nq, w.pairs, w.err);
   };
+  auto go8 = [&](auto fn, unsigned blocks) {
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(512), 0, s, bt, b, w.count, w.lines, w.qmark,
+                       w.rank, w.ulist, w.brick_nq, w.pairs, w.err);
+  };
   const unsigned nb = (unsigned)bt.nbricks, nb4 = (unsigned)((bt.nbricks + 3) / 4);
   const size_t rows_lds = 4 * (size_t)b.by * b.bt * sizeof(uint16_t);  // (at most 16 KiB)
-  if (dense_batch(bt))
-    all ? go(k_rank_lines4<true>, nb, 0) : go(k_rank_lines4<false>, nb, 0);
-  else
+  if (dense_batch(bt)) {
+    // (8 waves for the largest bricks: with a quarter of the blocks, 4 waves
+    // each left the kernel latency-bound)
+    if (b.volume() > 4096)
+      all ? go8(k_rank_lines4<true, 8>, nb) : go8(k_rank_lines4<false, 8>, nb);
+    else
+      all ? go(k_rank_lines4<true, 4>, nb, 0) : go(k_rank_lines4<false, 4>, nb, 0);
+  } else {
     all ? go(k_rank_lines<true>, nb4, rows_lds) : go(k_rank_lines<false>, nb4, rows_lds);
+  }
 }
 
 int launch_clear_events(const Batch& bt, const Workspace& w, void* stream) {
